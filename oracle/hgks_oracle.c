@@ -1,0 +1,1023 @@
+/*
+ * hgks_oracle.c -- plain FP64 CPU reference of one explicit
+ * HGKS step (third-order unstructured WENO, Gauss-point gas-kinetic flux,
+ * two-stage fourth-order update) on tetrahedral meshes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  It is linked by the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark, never by the product path, and it
+ * shares no code with the GPU library.  It is written for obviousness, not speed:
+ * every step follows the paper (arXiv 2407.00656, Sec. 2) in the paper's order:
+ *
+ *   geometry ............ Sec. 3.1 (areas, volumes, local frames)
+ *   stencils ............ Sec. 3.1 item 4 / Algorithm 1, Sec. 2.3 (tet sub-stencils)
+ *   WENO ................ Sec. 2.3, Eqs. (polys) and (weno), WENO-Z weights,
+ *                         smoothness indicators beta_m
+ *   gas-kinetic flux .... Sec. 2.1, Eqs. (flux-G), (flux), compatibility
+ *                         condition for Q0, slope relations <a>, <a.u + A> = 0
+ *   time fit ............ Sec. 2.2, Eq. (expansion-1) and its 2x2 system
+ *   S2O4 update ......... Sec. 2.2
+ *
+ * Readings where the paper is silent (all are parameters or documented choices):
+ *   - 3-point degree-2 Gauss rule on each triangular face (weights 1/3);
+ *   - WENO-Z with exponent 1 and the epsilon given in the parameters;
+ *   - unweighted least squares in cell-scaled centroid coordinates, solved by
+ *     normal equations + Cholesky;
+ *   - the slopes of the equilibrium state use dQ0 = (dQ_l + dQ_r)/2;
+ *   - tau = 0 (smooth flow, Sec. 5.1) or tau = eps*dt + C*|pl-pr|/(pl+pr)*dt;
+ *   - dt = CFL * min_i h_i / (|U_i| + c_i), h_i = 6|Omega_i| / sum_p S_ip.
+ *
+ * Conventions: cells are 0-based; face p of a tetrahedron is the one opposite
+ * its node p (Sec. 3.1 item 1); the neighbour across face p is "i_{p+1}" of
+ * Sec. 2.3.  Meshes may be periodic: period[a] > 0 identifies x_a with
+ * x_a + period[a]; each cell is unwrapped around its first node.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG 1
+#define ORC_E_MESH 2
+#define ORC_E_NONPHYS 6
+
+#define MAXSTEN 32
+#define MAXSUB 8
+
+typedef struct {
+    double gamma;
+    double cfl;
+    int tau_mode;          /* 0: tau = 0;  1: tau = tau_eps*dt + tau_C*|pl-pr|/(pl+pr)*dt */
+    double tau_eps;
+    double tau_C;
+    double weno_eps;
+    double gamma_lin;      /* linear weight of each sub-stencil; gamma_0 = 1 - 4*gamma_lin */
+} orc_params;
+
+typedef struct {
+    int64_t nc, nn, nf;
+    double period[3];
+    double (*vert)[4][3];          /* unwrapped vertices of each cell */
+    double *vol;
+    double (*cen)[3];
+    double *h;                      /* |Omega|^(1/3): length scale of the local coordinates */
+    double *hdt;                    /* 6|Omega| / sum of face areas */
+    /* faces */
+    int64_t (*fcell)[2];            /* left, right */
+    double (*fshift)[3];            /* right cell's image in the left cell's frame = right + fshift */
+    double (*fnrm)[3];
+    double *farea;
+    double (*fgp)[3][3];            /* Gauss points, left cell's frame */
+    int64_t (*cface)[4];            /* face opposite local node p */
+    /* neighbours i_1..i_4 */
+    int64_t (*nb)[4];
+    double (*nbshift)[4][3];
+    /* big stencil and the four sub-stencils (members other than the cell itself) */
+    int *nsten;
+    int64_t (*sten)[MAXSTEN];
+    double (*stsh)[MAXSTEN][3];
+    int (*nsub)[4];
+    int64_t (*sub)[4][MAXSUB];
+    double (*subsh)[4][MAXSUB][3];
+} orc_mesh;
+
+/* ------------------------------------------------------------------------- */
+/* small helpers                                                             */
+/* ------------------------------------------------------------------------- */
+
+static void sub3(const double *a, const double *b, double *c) { c[0] = a[0] - b[0]; c[1] = a[1] - b[1]; c[2] = a[2] - b[2]; }
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void set_err(char *err, int errlen, const char *msg) {
+    if (err && errlen > 0) { strncpy(err, msg, (size_t)errlen - 1); err[errlen - 1] = 0; }
+}
+
+/* Degree-2 exact 4-point rule on a tetrahedron (points a*V_q + b*sum of others). */
+static void tet_points(const double v[4][3], double pts[4][3]) {
+    const double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0;
+    const double b = (5.0 - sqrt(5.0)) / 20.0;
+    for (int q = 0; q < 4; ++q)
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+            for (int r = 0; r < 4; ++r) s += (r == q ? a : b) * v[r][d];
+            pts[q][d] = s;
+        }
+}
+
+/* Basis exponents for p_d, |d| = 1..2 (Eq. polys): x, y, z, xx, yy, zz, xy, xz, yz. */
+static const int DEXP[9][3] = {{1,0,0},{0,1,0},{0,0,1},{2,0,0},{0,2,0},{0,0,2},{1,1,0},{1,0,1},{0,1,1}};
+
+static double ipow(double x, int e) { double r = 1.0; for (int k = 0; k < e; ++k) r *= x; return r; }
+static double mono(const int e[3], const double *xi) { return ipow(xi[0], e[0]) * ipow(xi[1], e[1]) * ipow(xi[2], e[2]); }
+/* d/dxi_j of xi^e */
+static double dmono(const int e[3], int j, const double *xi) {
+    if (e[j] == 0) return 0.0;
+    int f[3] = {e[0], e[1], e[2]};
+    f[j] -= 1;
+    return (double)e[j] * mono(f, xi);
+}
+/* d^2/(dxi_j dxi_k) of xi^e */
+static double d2mono(const int e[3], int j, int k, const double *xi) {
+    int f[3] = {e[0], e[1], e[2]};
+    double c = (double)f[j];
+    if (f[j] == 0) return 0.0;
+    f[j] -= 1;
+    c *= (double)f[k];
+    if (f[k] == 0) return 0.0;
+    f[k] -= 1;
+    return c * mono(f, xi);
+}
+
+/* Mean over tetrahedron `v` (any frame) of the 9 monomials in the scaled coordinates
+ * of a cell with centroid c and length h: xi = (x - c)/h. */
+static void tet_monomial_means(const double v[4][3], const double *c, double h, double out[9]) {
+    double pts[4][3];
+    tet_points(v, pts);
+    for (int d = 0; d < 9; ++d) out[d] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        double xi[3] = {(pts[q][0] - c[0]) / h, (pts[q][1] - c[1]) / h, (pts[q][2] - c[2]) / h};
+        for (int d = 0; d < 9; ++d) out[d] += 0.25 * mono(DEXP[d], xi);
+    }
+}
+
+/* Least squares min ||A x - B|| via the normal equations and Cholesky.
+ * A: m x n row-major, B: m x r, X: n x r.  Returns 0 or -1 (not positive definite). */
+static int lsq_normal(int m, int n, const double *A, int r, const double *B, double *X) {
+    double N[9 * 9], R[9 * 5], Lc[9 * 9];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < m; ++k) s += A[k * n + a] * A[k * n + b];
+            N[a * n + b] = s;
+        }
+    for (int a = 0; a < n; ++a)
+        for (int c = 0; c < r; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < m; ++k) s += A[k * n + a] * B[k * r + c];
+            R[a * r + c] = s;
+        }
+    memset(Lc, 0, sizeof(Lc));
+    for (int j = 0; j < n; ++j) {
+        double s = N[j * n + j];
+        for (int k = 0; k < j; ++k) s -= Lc[j * n + k] * Lc[j * n + k];
+        if (!(s > 1e-14 * N[j * n + j]) || !(s > 0.0)) return -1;
+        Lc[j * n + j] = sqrt(s);
+        for (int i = j + 1; i < n; ++i) {
+            double t = N[i * n + j];
+            for (int k = 0; k < j; ++k) t -= Lc[i * n + k] * Lc[j * n + k];
+            Lc[i * n + j] = t / Lc[j * n + j];
+        }
+    }
+    for (int c = 0; c < r; ++c) {
+        double y[9];
+        for (int i = 0; i < n; ++i) {
+            double t = R[i * r + c];
+            for (int k = 0; k < i; ++k) t -= Lc[i * n + k] * y[k];
+            y[i] = t / Lc[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int k = i + 1; k < n; ++k) t -= Lc[k * n + i] * X[k * r + c];
+            X[i * r + c] = t / Lc[i * n + i];
+        }
+    }
+    return 0;
+}
+
+/* Dense n x n solve with partial pivoting (n <= 5). */
+static int gauss_solve(int n, const double *Ain, const double *bin, double *x) {
+    double A[25], b[5];
+    memcpy(A, Ain, sizeof(double) * n * n);
+    memcpy(b, bin, sizeof(double) * n);
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r) if (fabs(A[r * n + c]) > fabs(A[p * n + c])) p = r;
+        if (A[p * n + c] == 0.0) return -1;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) { double t = A[c * n + k]; A[c * n + k] = A[p * n + k]; A[p * n + k] = t; }
+            double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * x[k];
+        x[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* mesh: connectivity (Sec. 3.1) and geometry                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { int64_t key[3]; int64_t cell; int p; } face_rec;
+
+static int cmp_face(const void *a, const void *b) {
+    const face_rec *x = (const face_rec *)a, *y = (const face_rec *)b;
+    for (int k = 0; k < 3; ++k) {
+        if (x->key[k] < y->key[k]) return -1;
+        if (x->key[k] > y->key[k]) return 1;
+    }
+    if (x->cell != y->cell) return x->cell < y->cell ? -1 : 1;
+    return x->p - y->p;
+}
+
+static void sort3(int64_t *k) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (k[b] < k[a]) { int64_t t = k[a]; k[a] = k[b]; k[b] = t; }
+}
+
+void orc_mesh_free(orc_mesh *m);
+
+static int same_member(int64_t c1, const double *s1, int64_t c2, const double *s2) {
+    return c1 == c2 && fabs(s1[0] - s2[0]) < 1e-9 && fabs(s1[1] - s2[1]) < 1e-9 && fabs(s1[2] - s2[2]) < 1e-9;
+}
+
+orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t *cell_nodes,
+                       const double *period, char *err, int errlen) {
+    if (nn <= 0 || nc <= 0 || !xyz || !cell_nodes) { set_err(err, errlen, "empty mesh"); return NULL; }
+    orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+    m->nc = nc; m->nn = nn;
+    for (int a = 0; a < 3; ++a) m->period[a] = period ? period[a] : 0.0;
+    m->vert = malloc(sizeof(*m->vert) * nc);
+    m->vol = malloc(sizeof(double) * nc);
+    m->cen = malloc(sizeof(*m->cen) * nc);
+    m->h = malloc(sizeof(double) * nc);
+    m->hdt = malloc(sizeof(double) * nc);
+    m->cface = malloc(sizeof(*m->cface) * nc);
+    m->nb = malloc(sizeof(*m->nb) * nc);
+    m->nbshift = malloc(sizeof(*m->nbshift) * nc);
+
+    /* unwrap every cell around its first node; volume, centroid */
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int q = 0; q < 4; ++q) {
+            int64_t nid = cell_nodes[c * 4 + q];
+            if (nid < 0 || nid >= nn) { set_err(err, errlen, "node id out of range"); orc_mesh_free(m); return NULL; }
+        }
+        const double *x0 = xyz + 3 * cell_nodes[c * 4];
+        for (int q = 0; q < 4; ++q) {
+            const double *xq = xyz + 3 * cell_nodes[c * 4 + q];
+            for (int a = 0; a < 3; ++a) {
+                double d = xq[a] - x0[a];
+                if (m->period[a] > 0.0) d -= m->period[a] * nearbyint(d / m->period[a]);
+                m->vert[c][q][a] = x0[a] + d;
+            }
+        }
+        double e1[3], e2[3], e3[3], cr[3];
+        sub3(m->vert[c][1], m->vert[c][0], e1);
+        sub3(m->vert[c][2], m->vert[c][0], e2);
+        sub3(m->vert[c][3], m->vert[c][0], e3);
+        cross3(e2, e3, cr);
+        double v = fabs(dot3(e1, cr)) / 6.0;
+        double ext = 0.0;
+        for (int a = 0; a < 3; ++a) ext = fmax(ext, fabs(e1[a]) + fabs(e2[a]) + fabs(e3[a]));
+        if (!(v > 1e-12 * ext * ext * ext)) { set_err(err, errlen, "degenerate tetrahedron"); orc_mesh_free(m); return NULL; }
+        m->vol[c] = v;
+        m->h[c] = cbrt(v);
+        for (int a = 0; a < 3; ++a)
+            m->cen[c][a] = 0.25 * (m->vert[c][0][a] + m->vert[c][1][a] + m->vert[c][2][a] + m->vert[c][3][a]);
+    }
+
+    /* faces: match the node triples of all cell faces (CellFace / FaceCell) */
+    face_rec *fr = malloc(sizeof(face_rec) * nc * 4);
+    for (int64_t c = 0; c < nc; ++c)
+        for (int p = 0; p < 4; ++p) {
+            face_rec *r = &fr[c * 4 + p];
+            int k = 0;
+            for (int q = 0; q < 4; ++q) if (q != p) r->key[k++] = cell_nodes[c * 4 + q];
+            sort3(r->key);
+            r->cell = c; r->p = p;
+        }
+    qsort(fr, (size_t)(nc * 4), sizeof(face_rec), cmp_face);
+    int64_t nf = 0;
+    for (int64_t k = 0; k < nc * 4;) {
+        int64_t j = k + 1;
+        while (j < nc * 4 && memcmp(fr[j].key, fr[k].key, sizeof(fr[k].key)) == 0) ++j;
+        if (j - k != 2) {
+            set_err(err, errlen, j - k == 1 ? "boundary face (only periodic meshes are supported)" : "non-conforming face");
+            free(fr); orc_mesh_free(m); return NULL;
+        }
+        ++nf; k = j;
+    }
+    m->nf = nf;
+    m->fcell = malloc(sizeof(*m->fcell) * nf);
+    m->fshift = malloc(sizeof(*m->fshift) * nf);
+    m->fnrm = malloc(sizeof(*m->fnrm) * nf);
+    m->farea = malloc(sizeof(double) * nf);
+    m->fgp = malloc(sizeof(*m->fgp) * nf);
+    double *asum = calloc((size_t)nc, sizeof(double));
+    int64_t f = 0;
+    for (int64_t k = 0; k < nc * 4; k += 2, ++f) {
+        const face_rec *A = &fr[k], *B = &fr[k + 1];          /* A->cell <= B->cell */
+        int64_t l = A->cell, r = B->cell;
+        int pl = A->p, pr = B->p;
+        m->fcell[f][0] = l; m->fcell[f][1] = r;
+        m->cface[l][pl] = f; m->cface[r][pr] = f;
+        /* face vertices in the left frame, and the right cell's image shift */
+        double tri[3][3];
+        int t = 0;
+        for (int q = 0; q < 4; ++q) if (q != pl) { memcpy(tri[t], m->vert[l][q], sizeof(tri[t])); ++t; }
+        int64_t n0 = cell_nodes[l * 4 + (pl == 0 ? 1 : 0)];
+        int ql = -1, qr = -1;
+        for (int q = 0; q < 4; ++q) { if (cell_nodes[l * 4 + q] == n0) ql = q; if (cell_nodes[r * 4 + q] == n0) qr = q; }
+        sub3(m->vert[l][ql], m->vert[r][qr], m->fshift[f]);
+        double e1[3], e2[3], nrm[3];
+        sub3(tri[1], tri[0], e1);
+        sub3(tri[2], tri[0], e2);
+        cross3(e1, e2, nrm);
+        double len = sqrt(dot3(nrm, nrm));
+        m->farea[f] = 0.5 * len;
+        for (int a = 0; a < 3; ++a) nrm[a] /= len;
+        double fc[3], d[3];
+        for (int a = 0; a < 3; ++a) fc[a] = (tri[0][a] + tri[1][a] + tri[2][a]) / 3.0;
+        sub3(fc, m->cen[l], d);
+        if (dot3(nrm, d) < 0.0) for (int a = 0; a < 3; ++a) nrm[a] = -nrm[a];
+        memcpy(m->fnrm[f], nrm, sizeof(nrm));
+        /* 3-point degree-2 rule: barycentric permutations of (2/3, 1/6, 1/6) */
+        for (int g = 0; g < 3; ++g)
+            for (int a = 0; a < 3; ++a) {
+                double s = 0.0;
+                for (int v = 0; v < 3; ++v) s += (v == g ? 2.0 / 3.0 : 1.0 / 6.0) * tri[v][a];
+                m->fgp[f][g][a] = s;
+            }
+        asum[l] += m->farea[f];
+        asum[r] += m->farea[f];
+        m->nb[l][pl] = r;
+        m->nb[r][pr] = l;
+        for (int a = 0; a < 3; ++a) { m->nbshift[l][pl][a] = m->fshift[f][a]; m->nbshift[r][pr][a] = -m->fshift[f][a]; }
+    }
+    free(fr);
+    for (int64_t c = 0; c < nc; ++c) m->hdt[c] = 6.0 * m->vol[c] / asum[c];
+    free(asum);
+
+    /* two-layer stencil (Algorithm 1, self excluded) and the tet sub-stencils (Sec. 2.3) */
+    m->nsten = malloc(sizeof(int) * nc);
+    m->sten = malloc(sizeof(*m->sten) * nc);
+    m->stsh = malloc(sizeof(*m->stsh) * nc);
+    m->nsub = malloc(sizeof(*m->nsub) * nc);
+    m->sub = malloc(sizeof(*m->sub) * nc);
+    m->subsh = malloc(sizeof(*m->subsh) * nc);
+    static const double zero[3] = {0, 0, 0};
+    /* S_1 = {i1,i2,i3} + N(i1), S_2 = {i1,i2,i4} + N(i2), S_3 = {i2,i3,i4} + N(i3), S_4 = {i3,i1,i4} + N(i4) */
+    static const int SUBFIRST[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
+    for (int64_t i = 0; i < nc; ++i) {
+        int n = 0;
+        for (int p = 0; p < 4; ++p) {
+            int dup = same_member(m->nb[i][p], m->nbshift[i][p], i, zero);
+            for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], m->stsh[i][k], m->nb[i][p], m->nbshift[i][p]);
+            if (!dup) { m->sten[i][n] = m->nb[i][p]; memcpy(m->stsh[i][n], m->nbshift[i][p], sizeof(double) * 3); ++n; }
+        }
+        for (int p = 0; p < 4; ++p) {
+            int64_t j = m->nb[i][p];
+            for (int q = 0; q < 4; ++q) {
+                int64_t c = m->nb[j][q];
+                double s[3];
+                for (int a = 0; a < 3; ++a) s[a] = m->nbshift[i][p][a] + m->nbshift[j][q][a];
+                int dup = same_member(c, s, i, zero);
+                for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], m->stsh[i][k], c, s);
+                if (!dup) {
+                    if (n >= MAXSTEN) { set_err(err, errlen, "stencil too large"); orc_mesh_free(m); return NULL; }
+                    m->sten[i][n] = c; memcpy(m->stsh[i][n], s, sizeof(s)); ++n;
+                }
+            }
+        }
+        m->nsten[i] = n;
+        for (int s_ = 0; s_ < 4; ++s_) {
+            int k = 0;
+            for (int t = 0; t < 3; ++t) {
+                int p = SUBFIRST[s_][t];
+                int dup = 0;
+                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], m->subsh[i][s_][u], m->nb[i][p], m->nbshift[i][p]);
+                if (!dup) { m->sub[i][s_][k] = m->nb[i][p]; memcpy(m->subsh[i][s_][k], m->nbshift[i][p], sizeof(double) * 3); ++k; }
+            }
+            int64_t j = m->nb[i][s_];
+            for (int q = 0; q < 4; ++q) {
+                int64_t c = m->nb[j][q];
+                double s[3];
+                for (int a = 0; a < 3; ++a) s[a] = m->nbshift[i][s_][a] + m->nbshift[j][q][a];
+                int dup = same_member(c, s, i, zero);
+                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], m->subsh[i][s_][u], c, s);
+                if (!dup) { m->sub[i][s_][k] = c; memcpy(m->subsh[i][s_][k], s, sizeof(s)); ++k; }
+            }
+            m->nsub[i][s_] = k;
+        }
+    }
+    return m;
+}
+
+void orc_mesh_free(orc_mesh *m) {
+    if (!m) return;
+    free(m->vert); free(m->vol); free(m->cen); free(m->h); free(m->hdt);
+    free(m->fcell); free(m->fshift); free(m->fnrm); free(m->farea); free(m->fgp);
+    free(m->cface); free(m->nb); free(m->nbshift);
+    free(m->nsten); free(m->sten); free(m->stsh); free(m->nsub); free(m->sub); free(m->subsh);
+    free(m);
+}
+
+/* accessors for tests */
+int64_t orc_mesh_nfaces(const orc_mesh *m) { return m->nf; }
+void orc_mesh_cells(const orc_mesh *m, double *vol, double *cen, double *hdt) {
+    for (int64_t c = 0; c < m->nc; ++c) {
+        if (vol) vol[c] = m->vol[c];
+        if (cen) memcpy(cen + 3 * c, m->cen[c], sizeof(double) * 3);
+        if (hdt) hdt[c] = m->hdt[c];
+    }
+}
+void orc_mesh_faces(const orc_mesh *m, int64_t *lr, double *nrm, double *area, double *shift, double *gp) {
+    for (int64_t f = 0; f < m->nf; ++f) {
+        if (lr) { lr[2 * f] = m->fcell[f][0]; lr[2 * f + 1] = m->fcell[f][1]; }
+        if (nrm) memcpy(nrm + 3 * f, m->fnrm[f], sizeof(double) * 3);
+        if (area) area[f] = m->farea[f];
+        if (shift) memcpy(shift + 3 * f, m->fshift[f], sizeof(double) * 3);
+        if (gp) memcpy(gp + 9 * f, m->fgp[f], sizeof(double) * 9);
+    }
+}
+/* stencil of cell i: returns K; members[K], shifts[K][3]; sub-stencil sizes[4], members[4][MAXSUB] */
+int orc_mesh_stencil(const orc_mesh *m, int64_t i, int64_t *members, double *shifts, int *nsub, int64_t *sub) {
+    int n = m->nsten[i];
+    for (int k = 0; k < n; ++k) {
+        if (members) members[k] = m->sten[i][k];
+        if (shifts) memcpy(shifts + 3 * k, m->stsh[i][k], sizeof(double) * 3);
+    }
+    for (int s = 0; s < 4; ++s) {
+        if (nsub) nsub[s] = m->nsub[i][s];
+        if (sub) for (int k = 0; k < MAXSUB; ++k) sub[s * MAXSUB + k] = k < m->nsub[i][s] ? m->sub[i][s][k] : -1;
+    }
+    return n;
+}
+void orc_mesh_neighbors(const orc_mesh *m, int64_t *nb) {
+    for (int64_t c = 0; c < m->nc; ++c) for (int p = 0; p < 4; ++p) nb[4 * c + p] = m->nb[c][p];
+}
+
+/* ------------------------------------------------------------------------- */
+/* WENO reconstruction (Sec. 2.3)                                            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double a[5][9];        /* P0 coefficients, per variable */
+    double b[4][5][3];     /* P_m coefficients (linear), per sub-stencil and variable */
+    double beta[5][5];     /* [variable][m], m = 0..4 */
+    double wbar[5][5];     /* normalised non-linear weights [variable][m] */
+    double mean_i[9];      /* mean over the cell of xi^d */
+} orc_weno;
+
+/* Shifted copy of a member's vertices in the target cell's frame. */
+static void member_vertices(const orc_mesh *m, int64_t k, const double *shift, double v[4][3]) {
+    for (int q = 0; q < 4; ++q) for (int a = 0; a < 3; ++a) v[q][a] = m->vert[k][q][a] + shift[a];
+}
+
+static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i, orc_weno *w) {
+    const double *ci = m->cen[i];
+    const double hi = m->h[i];
+    tet_monomial_means(m->vert[i], ci, hi, w->mean_i);
+    /* quadratic P0 on the big stencil: constraints (1/|Omega_k|) int_{Omega_k} P0 = Q_k */
+    int K = m->nsten[i];
+    double A[MAXSTEN * 9], B[MAXSTEN * 5];
+    for (int k = 0; k < K; ++k) {
+        double v[4][3], mk[9];
+        member_vertices(m, m->sten[i][k], m->stsh[i][k], v);
+        tet_monomial_means(v, ci, hi, mk);
+        for (int d = 0; d < 9; ++d) A[k * 9 + d] = mk[d] - w->mean_i[d];
+        for (int q = 0; q < 5; ++q) B[k * 5 + q] = Q[5 * m->sten[i][k] + q] - Q[5 * i + q];
+    }
+    double X[9 * 5];
+    if (lsq_normal(K, 9, A, 5, B, X)) return ORC_E_MESH;
+    for (int d = 0; d < 9; ++d) for (int q = 0; q < 5; ++q) w->a[q][d] = X[d * 5 + q];
+    /* linear P_m on the sub-stencils */
+    for (int s = 0; s < 4; ++s) {
+        int n = m->nsub[i][s];
+        double As[MAXSUB * 3], Bs[MAXSUB * 5], Xs[3 * 5];
+        for (int k = 0; k < n; ++k) {
+            double v[4][3], mk[9];
+            member_vertices(m, m->sub[i][s][k], m->subsh[i][s][k], v);
+            tet_monomial_means(v, ci, hi, mk);
+            for (int d = 0; d < 3; ++d) As[k * 3 + d] = mk[d] - w->mean_i[d];
+            for (int q = 0; q < 5; ++q) Bs[k * 5 + q] = Q[5 * m->sub[i][s][k] + q] - Q[5 * i + q];
+        }
+        if (lsq_normal(n, 3, As, 5, Bs, Xs)) return ORC_E_MESH;
+        for (int d = 0; d < 3; ++d) for (int q = 0; q < 5; ++q) w->b[s][q][d] = Xs[d * 5 + q];
+    }
+    /* smoothness indicators: beta_m = sum_{1<=|l|<=r_m} |Omega|^(2|l|/3-1) int (d^l P_m)^2 dV,
+     * evaluated in physical coordinates with the degree-2 rule (exact for these integrands) */
+    double pts[4][3];
+    tet_points(m->vert[i], pts);
+    const double V = m->vol[i];
+    const double w1 = pow(V, 2.0 / 3.0 - 1.0), w2 = pow(V, 4.0 / 3.0 - 1.0);
+    static const int L2IDX[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    for (int q = 0; q < 5; ++q) {
+        for (int s = 0; s < 5; ++s) {
+            int nd = s == 0 ? 9 : 3;
+            const double *c = s == 0 ? w->a[q] : w->b[s - 1][q];
+            double beta = 0.0;
+            for (int j = 0; j < 3; ++j) {               /* |l| = 1 */
+                double integral = 0.0;
+                for (int g = 0; g < 4; ++g) {
+                    double xi[3] = {(pts[g][0] - ci[0]) / hi, (pts[g][1] - ci[1]) / hi, (pts[g][2] - ci[2]) / hi};
+                    double dp = 0.0;
+                    for (int d = 0; d < nd; ++d) dp += c[d] * dmono(DEXP[d], j, xi) / hi;
+                    integral += 0.25 * V * dp * dp;
+                }
+                beta += w1 * integral;
+            }
+            if (s == 0) {                                 /* |l| = 2, each multi-index once */
+                for (int t = 0; t < 6; ++t) {
+                    double xi0[3] = {0, 0, 0};
+                    double d2 = 0.0;
+                    for (int d = 0; d < 9; ++d) d2 += c[d] * d2mono(DEXP[d], L2IDX[t][0], L2IDX[t][1], xi0) / (hi * hi);
+                    beta += w2 * V * d2 * d2;
+                }
+            }
+            w->beta[q][s] = beta;
+        }
+        /* WENO-Z non-linear weights */
+        double g[5];
+        g[0] = 1.0 - 4.0 * p->gamma_lin;
+        for (int s = 1; s < 5; ++s) g[s] = p->gamma_lin;
+        double tauZ = 0.0;
+        for (int s = 1; s < 5; ++s) tauZ += fabs(w->beta[q][0] - w->beta[q][s]) / 4.0;
+        double om[5], sum = 0.0;
+        for (int s = 0; s < 5; ++s) { om[s] = g[s] * (1.0 + tauZ / (w->beta[q][s] + p->weno_eps)); sum += om[s]; }
+        for (int s = 0; s < 5; ++s) w->wbar[q][s] = om[s] / sum;
+    }
+    return ORC_OK;
+}
+
+/* Point value and gradient of the WENO combination (Eq. weno) at x (cell i's frame). */
+static void weno_eval(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i, const orc_weno *w,
+                      const double *x, double *val, double grad[5][3]) {
+    const double hi = m->h[i];
+    double xi[3] = {(x[0] - m->cen[i][0]) / hi, (x[1] - m->cen[i][1]) / hi, (x[2] - m->cen[i][2]) / hi};
+    const double g0 = 1.0 - 4.0 * p->gamma_lin, gm = p->gamma_lin;
+    for (int q = 0; q < 5; ++q) {
+        double P[5], dP[5][3];
+        for (int s = 0; s < 5; ++s) {
+            int nd = s == 0 ? 9 : 3;
+            const double *c = s == 0 ? w->a[q] : w->b[s - 1][q];
+            double v = Q[5 * i + q];
+            for (int d = 0; d < nd; ++d) v += c[d] * (mono(DEXP[d], xi) - w->mean_i[d]);
+            P[s] = v;
+            for (int j = 0; j < 3; ++j) {
+                double t = 0.0;
+                for (int d = 0; d < nd; ++d) t += c[d] * dmono(DEXP[d], j, xi) / hi;
+                dP[s][j] = t;
+            }
+        }
+        double v = w->wbar[q][0] * P[0] / g0;
+        for (int s = 1; s < 5; ++s) v += -w->wbar[q][0] * gm / g0 * P[s] + w->wbar[q][s] * P[s];
+        val[q] = v;
+        for (int j = 0; j < 3; ++j) {
+            double t = w->wbar[q][0] * dP[0][j] / g0;
+            for (int s = 1; s < 5; ++s) t += -w->wbar[q][0] * gm / g0 * dP[s][j] + w->wbar[q][s] * dP[s][j];
+            grad[q][j] = t;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Maxwellian moments (Sec. 2.1)                                             */
+/* ------------------------------------------------------------------------- */
+
+/* A polynomial in (u, v, w, xi^2): sum of c * u^a v^b w^c (xi^2)^d. */
+typedef struct { double c; int e[4]; } term;
+typedef struct { int n; term t[16]; } poly;
+
+static poly PSI[5];            /* collision invariants psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2) */
+static poly P_PP[5][5];        /* psi_a psi_b */
+static poly P_UPP[3][5][5];    /* u_j psi_a psi_b */
+static poly P_UUPP[3][5][5];   /* u u_j psi_a psi_b */
+static poly P_UP[5];           /* u psi_a */
+static int tables_ready = 0;
+
+static poly pmul(const poly *x, const poly *y) {
+    poly r; r.n = 0;
+    for (int i = 0; i < x->n; ++i)
+        for (int j = 0; j < y->n; ++j) {
+            term t;
+            t.c = x->t[i].c * y->t[j].c;
+            for (int k = 0; k < 4; ++k) t.e[k] = x->t[i].e[k] + y->t[j].e[k];
+            r.t[r.n++] = t;
+        }
+    return r;
+}
+
+static poly pvar(int k) { poly r; r.n = 1; r.t[0].c = 1.0; memset(r.t[0].e, 0, sizeof(r.t[0].e)); if (k >= 0) r.t[0].e[k] = 1; return r; }
+
+static void build_tables(void) {
+    if (tables_ready) return;
+    PSI[0] = pvar(-1);
+    PSI[1] = pvar(0);
+    PSI[2] = pvar(1);
+    PSI[3] = pvar(2);
+    PSI[4].n = 4;
+    for (int k = 0; k < 4; ++k) {
+        PSI[4].t[k].c = 0.5;
+        memset(PSI[4].t[k].e, 0, sizeof(PSI[4].t[k].e));
+        if (k < 3) PSI[4].t[k].e[k] = 2; else PSI[4].t[k].e[3] = 1;
+    }
+    poly U = pvar(0);
+    for (int a = 0; a < 5; ++a) {
+        P_UP[a] = pmul(&U, &PSI[a]);
+        for (int b = 0; b < 5; ++b) {
+            P_PP[a][b] = pmul(&PSI[a], &PSI[b]);
+            for (int j = 0; j < 3; ++j) {
+                poly uj = pvar(j);
+                P_UPP[j][a][b] = pmul(&uj, &P_PP[a][b]);
+                poly uuj = pmul(&U, &uj);
+                P_UUPP[j][a][b] = pmul(&uuj, &P_PP[a][b]);
+            }
+        }
+    }
+    tables_ready = 1;
+}
+
+/* Normalised moments <u^n>, <v^n>, <w^n>, <xi^(2n)> of one Maxwellian;
+ * half = +1 / -1 selects the half space u > 0 / u < 0 for the u-moments. */
+typedef struct { double mu[7], mv[7], mw[7], mxi[3]; } moments;
+
+static void full_moments_1d(double U, double lam, double *m) {
+    m[0] = 1.0;
+    m[1] = U;
+    for (int n = 2; n < 7; ++n) m[n] = U * m[n - 1] + (double)(n - 1) / (2.0 * lam) * m[n - 2];
+}
+
+static void half_moments_1d(double U, double lam, int half, double *m) {
+    double s = sqrt(lam) * U;
+    double g = exp(-lam * U * U) / (2.0 * sqrt(M_PI * lam));
+    if (half > 0) { m[0] = 0.5 * erfc(-s); m[1] = U * m[0] + g; }
+    else          { m[0] = 0.5 * erfc(s);  m[1] = U * m[0] - g; }
+    for (int n = 2; n < 7; ++n) m[n] = U * m[n - 1] + (double)(n - 1) / (2.0 * lam) * m[n - 2];
+}
+
+static void make_moments(double U, double V, double W, double lam, double K, int half, moments *M) {
+    if (half == 0) full_moments_1d(U, lam, M->mu); else half_moments_1d(U, lam, half, M->mu);
+    full_moments_1d(V, lam, M->mv);
+    full_moments_1d(W, lam, M->mw);
+    M->mxi[0] = 1.0;
+    M->mxi[1] = K / (2.0 * lam);
+    M->mxi[2] = K * (K + 2.0) / (4.0 * lam * lam);
+}
+
+static double expect(const moments *M, const poly *P) {
+    double s = 0.0;
+    for (int i = 0; i < P->n; ++i) {
+        const term *t = &P->t[i];
+        s += t->c * M->mu[t->e[0]] * M->mv[t->e[1]] * M->mw[t->e[2]] * M->mxi[t->e[3]];
+    }
+    return s;
+}
+
+/* The 5x5 moment matrix <psi psi^T> of one state. */
+static void moment_matrix(const moments *M, double *A) {
+    for (int r = 0; r < 5; ++r) for (int c = 0; c < 5; ++c) A[r * 5 + c] = expect(M, &P_PP[r][c]);
+}
+
+/* Solve <(a.psi) psi> = b for the micro-slope a (5x5 moment system, dense elimination). */
+static int slope_solve(const moments *M, const double *b, double *a) {
+    double A[25];
+    moment_matrix(M, A);
+    return gauss_solve(5, A, b, a);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gas-kinetic flux at one Gauss point (Sec. 2.1, Eq. flux; Sec. 2.2)        */
+/* ------------------------------------------------------------------------- */
+
+static void local_frame(const double *n, double *t1, double *t2) {
+    int k = 0;
+    for (int a = 1; a < 3; ++a) if (fabs(n[a]) < fabs(n[k])) k = a;
+    double e[3] = {0, 0, 0};
+    e[k] = 1.0;
+    cross3(n, e, t1);
+    double l = sqrt(dot3(t1, t1));
+    for (int a = 0; a < 3; ++a) t1[a] /= l;
+    cross3(n, t1, t2);
+}
+
+/* rotate the momentum components of a 5-vector into (n, t1, t2) */
+static void to_local(const double *q, const double *n, const double *t1, const double *t2, double *out) {
+    out[0] = q[0];
+    out[1] = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    out[2] = q[1] * t1[0] + q[2] * t1[1] + q[3] * t1[2];
+    out[3] = q[1] * t2[0] + q[2] * t2[1] + q[3] * t2[2];
+    out[4] = q[4];
+}
+
+typedef struct { double rho, U, V, W, lam, p; } prim;
+
+static prim primitives(const double *q, double gamma) {
+    prim s;
+    s.rho = q[0];
+    s.U = q[1] / q[0]; s.V = q[2] / q[0]; s.W = q[3] / q[0];
+    s.p = (gamma - 1.0) * (q[4] - 0.5 * s.rho * (s.U * s.U + s.V * s.V + s.W * s.W));
+    s.lam = s.rho / (2.0 * s.p);
+    return s;
+}
+
+/*
+ * F(t) fitted linearly over [0, dt] (Eq. expansion-1).  Inputs are the
+ * reconstructed left/right states at the Gauss point and their gradients in
+ * the global frame; outputs are F^n and dF^n/dt per unit area, global frame.
+ */
+int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3]*/,
+                 const double *qr, const double *gr, const double *n, double dt,
+                 double *F, double *dF) {
+    build_tables();
+    const double K = (5.0 - 3.0 * p->gamma) / (p->gamma - 1.0);
+    double t1[3], t2[3];
+    local_frame(n, t1, t2);
+    const double *e[3] = {n, t1, t2};
+    double Ql[5], Qr[5], dQl[3][5], dQr[3][5];
+    to_local(ql, n, t1, t2, Ql);
+    to_local(qr, n, t1, t2, Qr);
+    for (int j = 0; j < 3; ++j) {               /* derivative along local axis j, then rotate */
+        double dl[5], dr[5];
+        for (int q = 0; q < 5; ++q) {
+            dl[q] = gl[q * 3 + 0] * e[j][0] + gl[q * 3 + 1] * e[j][1] + gl[q * 3 + 2] * e[j][2];
+            dr[q] = gr[q * 3 + 0] * e[j][0] + gr[q * 3 + 1] * e[j][1] + gr[q * 3 + 2] * e[j][2];
+        }
+        to_local(dl, n, t1, t2, dQl[j]);
+        to_local(dr, n, t1, t2, dQr[j]);
+    }
+    prim sl = primitives(Ql, p->gamma), sr = primitives(Qr, p->gamma);
+    if (!(sl.rho > 0 && sr.rho > 0 && sl.p > 0 && sr.p > 0)) return ORC_E_NONPHYS;
+    moments Ml, Mr, Mlp, Mrn;
+    make_moments(sl.U, sl.V, sl.W, sl.lam, K, 0, &Ml);
+    make_moments(sr.U, sr.V, sr.W, sr.lam, K, 0, &Mr);
+    make_moments(sl.U, sl.V, sl.W, sl.lam, K, +1, &Mlp);
+    make_moments(sr.U, sr.V, sr.W, sr.lam, K, -1, &Mrn);
+    /* compatibility: Q0 = int_{u>0} psi g_l + int_{u<0} psi g_r */
+    double Q0[5];
+    for (int a = 0; a < 5; ++a) Q0[a] = sl.rho * expect(&Mlp, &PSI[a]) + sr.rho * expect(&Mrn, &PSI[a]);
+    prim s0;
+    s0.rho = Q0[0]; s0.U = Q0[1] / Q0[0]; s0.V = Q0[2] / Q0[0]; s0.W = Q0[3] / Q0[0];
+    s0.lam = (K + 3.0) * s0.rho / (4.0 * (Q0[4] - 0.5 * s0.rho * (s0.U * s0.U + s0.V * s0.V + s0.W * s0.W)));
+    if (!(s0.rho > 0 && s0.lam > 0)) return ORC_E_NONPHYS;
+    moments M0;
+    make_moments(s0.U, s0.V, s0.W, s0.lam, K, 0, &M0);
+    /* spatial micro-slopes: <a^k_j> = dQ_k/dn_j ; <abar_j> = dQ0/dn_j with dQ0 = (dQ_l + dQ_r)/2 */
+    double Gl[25], Gr[25], G0[25];
+    moment_matrix(&Ml, Gl);
+    moment_matrix(&Mr, Gr);
+    moment_matrix(&M0, G0);
+    double al[3][5], ar[3][5], a0[3][5];
+    for (int j = 0; j < 3; ++j) {
+        double bl[5], br[5], b0[5];
+        for (int q = 0; q < 5; ++q) {
+            bl[q] = dQl[j][q] / sl.rho;
+            br[q] = dQr[j][q] / sr.rho;
+            b0[q] = 0.5 * (dQl[j][q] + dQr[j][q]) / s0.rho;
+        }
+        if (gauss_solve(5, Gl, bl, al[j]) || gauss_solve(5, Gr, br, ar[j]) || gauss_solve(5, G0, b0, a0[j])) return ORC_E_NONPHYS;
+    }
+    /* temporal slopes: <a_1 u + a_2 v + a_3 w + A> = 0 (full-space moments of each state) */
+    double Al[5], Ar[5], A0[5];
+    {
+        double bl[5], br[5], b0[5];
+        for (int a = 0; a < 5; ++a) {
+            double sl_ = 0, sr_ = 0, s0_ = 0;
+            for (int j = 0; j < 3; ++j)
+                for (int b = 0; b < 5; ++b) {
+                    sl_ += al[j][b] * expect(&Ml, &P_UPP[j][b][a]);
+                    sr_ += ar[j][b] * expect(&Mr, &P_UPP[j][b][a]);
+                    s0_ += a0[j][b] * expect(&M0, &P_UPP[j][b][a]);
+                }
+            bl[a] = -sl_; br[a] = -sr_; b0[a] = -s0_;
+        }
+        if (gauss_solve(5, Gl, bl, Al) || gauss_solve(5, Gr, br, Ar) || gauss_solve(5, G0, b0, A0)) return ORC_E_NONPHYS;
+    }
+    /* collision time */
+    double tau = 0.0;
+    if (p->tau_mode == 1) tau = p->tau_eps * dt + p->tau_C * fabs(sl.p - sr.p) / (sl.p + sr.p) * dt;
+    /* moments of the three pieces of f (Eq. flux) that the time integrals weight:
+     * the equilibrium part, and the left/right initial parts on their half spaces */
+    double e0[3][5], el[3][5], er[3][5];       /* [0]: <u psi>, [1]: sum_j <u u_j (a_j.psi) psi>, [2]: <u (A.psi) psi> */
+    for (int a = 0; a < 5; ++a) {
+        e0[0][a] = expect(&M0, &P_UP[a]); el[0][a] = expect(&Mlp, &P_UP[a]); er[0][a] = expect(&Mrn, &P_UP[a]);
+        e0[1][a] = el[1][a] = er[1][a] = 0.0;
+        e0[2][a] = el[2][a] = er[2][a] = 0.0;
+        for (int b = 0; b < 5; ++b) {
+            for (int j = 0; j < 3; ++j) {
+                e0[1][a] += a0[j][b] * expect(&M0, &P_UUPP[j][b][a]);
+                el[1][a] += al[j][b] * expect(&Mlp, &P_UUPP[j][b][a]);
+                er[1][a] += ar[j][b] * expect(&Mrn, &P_UUPP[j][b][a]);
+            }
+            e0[2][a] += A0[b] * expect(&M0, &P_UPP[0][b][a]);
+            el[2][a] += Al[b] * expect(&Mlp, &P_UPP[0][b][a]);
+            er[2][a] += Ar[b] * expect(&Mrn, &P_UPP[0][b][a]);
+        }
+    }
+    /* time-integrated flux I(delta) = int_0^delta F(t) dt, for delta = dt and dt/2 */
+    double I[2][5];
+    for (int h = 0; h < 2; ++h) {
+        double d = h == 0 ? dt : 0.5 * dt;
+        double q0, q1, q2, q3, q4, q5;
+        if (tau == 0.0) { q0 = d; q1 = 0.0; q2 = 0.5 * d * d; q3 = q4 = q5 = 0.0; }
+        else {
+            double E = exp(-d / tau);
+            q0 = d - tau * (1.0 - E);
+            q1 = 2.0 * tau * tau - tau * d - tau * (d + 2.0 * tau) * E;
+            q2 = 0.5 * d * d - tau * d + tau * tau * (1.0 - E);
+            q3 = tau * (1.0 - E);
+            q4 = -2.0 * tau * tau + tau * (d + 2.0 * tau) * E;
+            q5 = -tau * tau * (1.0 - E);
+        }
+        for (int a = 0; a < 5; ++a)
+            I[h][a] = s0.rho * (q0 * e0[0][a] + q1 * e0[1][a] + q2 * e0[2][a])
+                    + sl.rho * (q3 * el[0][a] + q4 * el[1][a] + q5 * el[2][a])
+                    + sr.rho * (q3 * er[0][a] + q4 * er[1][a] + q5 * er[2][a]);
+    }
+    /* solve  F dt + dF dt^2/2 = I(dt),  F dt/2 + dF dt^2/8 = I(dt/2)  (Cramer) */
+    const double m11 = dt, m12 = 0.5 * dt * dt, m21 = 0.5 * dt, m22 = dt * dt / 8.0;
+    const double det = m11 * m22 - m12 * m21;
+    double Fl[5], dFl[5];
+    for (int a = 0; a < 5; ++a) {
+        Fl[a] = (I[0][a] * m22 - m12 * I[1][a]) / det;
+        dFl[a] = (m11 * I[1][a] - I[0][a] * m21) / det;
+    }
+    /* rotate back to the global frame */
+    F[0] = Fl[0]; dF[0] = dFl[0];
+    for (int a = 0; a < 3; ++a) {
+        F[1 + a] = Fl[1] * n[a] + Fl[2] * t1[a] + Fl[3] * t2[a];
+        dF[1 + a] = dFl[1] * n[a] + dFl[2] * t1[a] + dFl[3] * t2[a];
+    }
+    F[4] = Fl[4]; dF[4] = dFl[4];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* L(Q), dL/dt (Eq. finite) and the S2O4 step (Sec. 2.2)                     */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * L_i = -(1/|Omega_i|) sum_faces F S (outward), and the same for dL/dt.
+ * Independent loops (cells, then faces, then cells) may run on several OpenMP
+ * threads: each iteration writes only its own slot, and the per-cell sum over a
+ * cell's four faces runs in local face order, so the result does not depend on
+ * the thread count.
+ */
+int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, double *L, double *dL) {
+    orc_weno *W = malloc(sizeof(orc_weno) * m->nc);
+    double (*FF)[10] = malloc(sizeof(double[10]) * m->nf);   /* S * sum_G w_G (F, dF) per face */
+    int rc = ORC_OK;
+#pragma omp parallel for schedule(static) reduction(max: rc)
+    for (int64_t i = 0; i < m->nc; ++i) {
+        int r_ = weno_cell(m, p, Q, i, &W[i]);
+        if (r_ > rc) rc = r_;
+    }
+    if (rc == ORC_OK) {
+#pragma omp parallel for schedule(static) reduction(max: rc)
+        for (int64_t f = 0; f < m->nf; ++f) {
+            int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+            double Ff[5] = {0}, dFf[5] = {0};
+            for (int g = 0; g < 3; ++g) {
+                double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5];
+                for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
+                weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
+                weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+                int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
+                if (r_ > rc) rc = r_;
+                for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
+            }
+            for (int q = 0; q < 5; ++q) { FF[f][q] = Ff[q] * m->farea[f]; FF[f][5 + q] = dFf[q] * m->farea[f]; }
+        }
+    }
+    if (rc == ORC_OK) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < m->nc; ++i) {
+            double s[10] = {0};
+            for (int p_ = 0; p_ < 4; ++p_) {
+                int64_t f = m->cface[i][p_];
+                double sign = m->fcell[f][0] == i ? -1.0 : 1.0;    /* the normal points out of the left cell */
+                for (int q = 0; q < 10; ++q) s[q] += sign * FF[f][q];
+            }
+            for (int q = 0; q < 5; ++q) { L[5 * i + q] = s[q] / m->vol[i]; dL[5 * i + q] = s[5 + q] / m->vol[i]; }
+        }
+    }
+    free(W);
+    free(FF);
+    return rc;
+}
+
+double orc_cfl_dt(const orc_mesh *m, const orc_params *p, const double *Q) {
+    double best = INFINITY;
+    for (int64_t i = 0; i < m->nc; ++i) {
+        prim s = primitives(Q + 5 * i, p->gamma);
+        double c = sqrt(p->gamma * s.p / s.rho);
+        double v = sqrt(s.U * s.U + s.V * s.V + s.W * s.W);
+        double d = m->hdt[i] / (v + c);
+        if (d < best) best = d;
+    }
+    return p->cfl * best;
+}
+
+void orc_s2o4_stage1(int64_t n, const double *q, const double *L, const double *dL, double dt, double *qs) {
+    for (int64_t k = 0; k < n; ++k) qs[k] = q[k] + 0.5 * dt * L[k] + dt * dt / 8.0 * dL[k];
+}
+
+void orc_s2o4_stage2(int64_t n, const double *q, const double *L, const double *dL, const double *dLs,
+                     double dt, double *qn) {
+    for (int64_t k = 0; k < n; ++k) qn[k] = q[k] + dt * L[k] + dt * dt / 6.0 * (dL[k] + 2.0 * dLs[k]);
+}
+
+static int physical(const double *Q, int64_t nc, double gamma) {
+    for (int64_t i = 0; i < nc; ++i) {
+        for (int q = 0; q < 5; ++q) if (!isfinite(Q[5 * i + q])) return 0;
+        prim s = primitives(Q + 5 * i, gamma);
+        if (!(s.rho > 0.0 && s.p > 0.0)) return 0;
+    }
+    return 1;
+}
+
+/* nsteps S2O4 steps in place; dt from the CFL rule unless dt_fixed > 0. */
+int orc_step(const orc_mesh *m, const orc_params *p, double *Q, int nsteps, double dt_fixed, double *dt_last) {
+    const int64_t n = 5 * m->nc;
+    double *L = malloc(sizeof(double) * n), *dL = malloc(sizeof(double) * n);
+    double *Ls = malloc(sizeof(double) * n), *dLs = malloc(sizeof(double) * n);
+    double *Qs = malloc(sizeof(double) * n), *Qn = malloc(sizeof(double) * n);
+    int rc = ORC_OK;
+    for (int s = 0; s < nsteps && rc == ORC_OK; ++s) {
+        double dt = dt_fixed > 0.0 ? dt_fixed : orc_cfl_dt(m, p, Q);
+        if (dt_last) *dt_last = dt;
+        rc = orc_rhs(m, p, Q, dt, L, dL);
+        if (rc) break;
+        orc_s2o4_stage1(n, Q, L, dL, dt, Qs);
+        if (!physical(Qs, m->nc, p->gamma)) { rc = ORC_E_NONPHYS; break; }
+        rc = orc_rhs(m, p, Qs, dt, Ls, dLs);
+        if (rc) break;
+        orc_s2o4_stage2(n, Q, L, dL, dLs, dt, Qn);
+        if (!physical(Qn, m->nc, p->gamma)) { rc = ORC_E_NONPHYS; break; }
+        memcpy(Q, Qn, sizeof(double) * n);
+    }
+    free(L); free(dL); free(Ls); free(dLs); free(Qs); free(Qn);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* test hooks: pieces of the method exposed for pinning                      */
+/* ------------------------------------------------------------------------- */
+
+void orc_moments_1d(double U, double lam, double *full, double *pos, double *neg) {
+    if (full) full_moments_1d(U, lam, full);
+    if (pos) half_moments_1d(U, lam, +1, pos);
+    if (neg) half_moments_1d(U, lam, -1, neg);
+}
+
+int orc_slope(double U, double V, double W, double lam, double K, const double *b, double *a) {
+    build_tables();
+    moments M;
+    make_moments(U, V, W, lam, K, 0, &M);
+    return slope_solve(&M, b, a);
+}
+
+/* Q0 of the collision of two states (conservative, already in the local frame). */
+void orc_collision(const orc_params *p, const double *ql, const double *qr, double *q0) {
+    build_tables();
+    const double K = (5.0 - 3.0 * p->gamma) / (p->gamma - 1.0);
+    prim sl = primitives(ql, p->gamma), sr = primitives(qr, p->gamma);
+    moments Mlp, Mrn;
+    make_moments(sl.U, sl.V, sl.W, sl.lam, K, +1, &Mlp);
+    make_moments(sr.U, sr.V, sr.W, sr.lam, K, -1, &Mrn);
+    for (int a = 0; a < 5; ++a) q0[a] = sl.rho * expect(&Mlp, &PSI[a]) + sr.rho * expect(&Mrn, &PSI[a]);
+}
+
+/* WENO of one cell: P0 coefficients a[5][9], P_m coefficients b[4][5][3], beta[5][5], wbar[5][5]. */
+int orc_weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i,
+                  double *a, double *b, double *beta, double *wbar) {
+    orc_weno w;
+    int rc = weno_cell(m, p, Q, i, &w);
+    if (rc) return rc;
+    if (a) memcpy(a, w.a, sizeof(w.a));
+    if (b) memcpy(b, w.b, sizeof(w.b));
+    if (beta) memcpy(beta, w.beta, sizeof(w.beta));
+    if (wbar) memcpy(wbar, w.wbar, sizeof(w.wbar));
+    return ORC_OK;
+}
+
+/* Reconstructed value and gradient of cell i at point x (cell i's frame). */
+int orc_reconstruct(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i, const double *x,
+                    double *val, double *grad) {
+    orc_weno w;
+    int rc = weno_cell(m, p, Q, i, &w);
+    if (rc) return rc;
+    double g[5][3];
+    weno_eval(m, p, Q, i, &w, x, val, g);
+    memcpy(grad, g, sizeof(g));
+    return ORC_OK;
+}
+
+/* mean over cell i of the scaled monomials, as used by the least-squares rows */
+void orc_cell_monomial_means(const orc_mesh *m, int64_t i, const double *target_c, double target_h, double *out) {
+    tet_monomial_means(m->vert[i], target_c, target_h, out);
+}

@@ -1,0 +1,285 @@
+"""Seeded synthetic inputs for the HGKS step: meshes, initial states, request streams.
+
+This module only *generates inputs*; it holds none of the scheme's arithmetic.
+Both the GPU path (tests, bench, serving) and the CPU oracle's tests draw their
+inputs from here.
+
+* Mesh: the periodic accuracy-test box of Sec. 5.1, "every cube divided into six
+  tetrahedra".  The split is the Kuhn split along the main diagonal: for cube
+  (i, j, k) and each permutation sigma of the axes (lexicographic order), the
+  tetrahedron is the lattice path v0 -> v0+e_s1 -> v0+e_s1+e_s2 -> v0+(1,1,1).
+  Cell id = 6*((i*N + j)*N + k) + sigma.  Interior vertices are jittered by
+  i.i.d. U(-j*h, j*h) per component; vertices on the box boundary (index 0 mod N
+  on any axis) are not moved.
+* Random numbers: SplitMix64 in counter form (Steele, Lea & Flood, 2014): the
+  k-th draw of a stream with seed s is mix(s + (k+1) * 0x9E3779B97F4A7C15), and a
+  uniform double in [0,1) is (x >> 11) * 2^-53.
+* Cell averages: collapsed-coordinate (Duffy) Gauss-Jacobi product rule on each
+  tetrahedron, exact for polynomials of total degree 2n-1.
+* Initial data: the advection test of Sec. 5.1, rho = 1 + A sin(pi k.(x - U t) + phi),
+  uniform velocity U and pressure p, given as exact cell averages of the
+  conservative variables (point values at centroids would add an O(h^2) error).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.special as _sp
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+# Lexicographic permutations of the three axes; tet sigma walks e_s[0], e_s[1], e_s[2].
+KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+SEED_ADVECTION = 0x2407006561
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Draws start..start+count-1 of the counter-form SplitMix64 stream `seed`."""
+    with np.errstate(over="ignore"):
+        k = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + k * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed: int, count: int, start: int = 0) -> np.ndarray:
+    return (splitmix64(seed, count, start) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+@dataclass
+class TetMesh:
+    """A tetrahedral mesh in the form the library and the oracle both take.
+
+    nodes       [n_nodes, 3] float64 coordinates
+    cell_nodes  [n_cells, 4] int64 node ids (0-based)
+    period      [3] float64; period[a] > 0 identifies x_a and x_a + period[a]
+    cell_vertices [n_cells, 4, 3] unwrapped vertex coordinates (generator-side
+                only, used to integrate initial data)
+    """
+    nodes: np.ndarray
+    cell_nodes: np.ndarray
+    period: np.ndarray
+    cell_vertices: np.ndarray
+    n: int = 0
+    box: float = 2.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_nodes.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.nodes.shape[0])
+
+
+def kuhn_box(n: int, box: float = 2.0, jitter: float = 0.1, seed: int = SEED_ADVECTION,
+             periodic=(True, True, True)) -> TetMesh:
+    """6*n^3 Kuhn tetrahedra in [0, box]^3, jittered from `seed`."""
+    if n < 4:
+        raise ValueError("kuhn_box needs n >= 4 (two-layer stencils must not wrap onto themselves)")
+    periodic = tuple(bool(p) for p in periodic)
+    h = box / n
+    dims = np.array([n if p else n + 1 for p in periodic], dtype=np.int64)
+    ix, iy, iz = np.meshgrid(np.arange(dims[0]), np.arange(dims[1]), np.arange(dims[2]), indexing="ij")
+    idx = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)          # node id order
+    nodes = idx.astype(np.float64) * h
+    interior = np.all((idx % n) != 0, axis=1)
+    if jitter > 0.0:
+        u = uniform01(seed, 3 * idx.shape[0]).reshape(-1, 3)
+        nodes = nodes + np.where(interior[:, None], (2.0 * u - 1.0) * jitter * h, 0.0)
+
+    def node_id(a, b, c):
+        return (a * dims[1] + b) * dims[2] + c
+
+    ci, cj, ck = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)          # cube order (i, j, k)
+    n_cubes = base.shape[0]
+    cell_nodes = np.empty((n_cubes, 6, 4), dtype=np.int64)
+    cell_vertices = np.empty((n_cubes, 6, 4, 3), dtype=np.float64)
+    period = np.array([box if p else 0.0 for p in periodic])
+    for s, perm in enumerate(KUHN_PERMS):
+        off = np.zeros(3, dtype=np.int64)
+        for v in range(4):
+            if v > 0:
+                off = off.copy()
+                off[perm[v - 1]] += 1
+            lat = base + off                                               # unwrapped lattice index
+            wrap = np.zeros_like(lat)
+            for a in range(3):
+                if periodic[a]:
+                    wrap[:, a] = lat[:, a] // n
+            li = lat - wrap * n
+            nid = node_id(li[:, 0], li[:, 1], li[:, 2])
+            cell_nodes[:, s, v] = nid
+            cell_vertices[:, s, v, :] = nodes[nid] + wrap * period
+    return TetMesh(nodes=nodes, cell_nodes=cell_nodes.reshape(-1, 4),
+                   period=period, cell_vertices=cell_vertices.reshape(-1, 4, 3),
+                   n=n, box=box, meta={"seed": seed, "jitter": jitter, "periodic": periodic})
+
+
+def tet_rule(npts: int):
+    """Collapsed Gauss-Jacobi product rule on the reference tetrahedron.
+
+    Returns (xyz [P,3] reference coordinates, w [P]) with sum(w) = 1/6; exact for
+    polynomials of total degree <= 2*npts - 1.
+    """
+    ta, wa = _sp.roots_jacobi(npts, 2.0, 0.0)
+    tb, wb = _sp.roots_jacobi(npts, 1.0, 0.0)
+    tc, wc = _sp.roots_jacobi(npts, 0.0, 0.0)
+    a, b, c = (ta + 1) / 2, (tb + 1) / 2, (tc + 1) / 2
+    wa, wb, wc = wa / 8, wb / 4, wc / 2
+    A, B, C = np.meshgrid(a, b, c, indexing="ij")
+    W = wa[:, None, None] * wb[None, :, None] * wc[None, None, :]
+    x = A
+    y = (1 - A) * B
+    z = (1 - A) * (1 - B) * C
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1), W.ravel()
+
+
+def default_npts(cell_vertices: np.ndarray, ksum: float) -> int:
+    """Points per direction so that the rule error for sin(k.x) stays near 1e-15.
+
+    ksum = sum_a |k_a| bounds the phase change per unit of per-axis extent; the
+    Gauss error for an entire function of half-range r behaves like
+    (r/2)^(2n) / (2n)!.
+    """
+    ext = float(np.max(np.ptp(cell_vertices[: min(len(cell_vertices), 4096)], axis=1)))
+    r = 0.5 * ksum * ext
+    for npts in range(2, 12):
+        d = 2 * npts
+        if (0.5 * r) ** d / math.factorial(d) < 1e-15:
+            return npts
+    return 12
+
+
+def cell_average(cell_vertices: np.ndarray, fun, npts: int, chunk: int = 65536) -> np.ndarray:
+    """Exact-to-rule cell averages of fun(x, y, z) -> [..] over every tetrahedron."""
+    ref, w = tet_rule(npts)
+    w6 = 6.0 * w
+    nc = cell_vertices.shape[0]
+    out = np.empty(nc, dtype=np.float64)
+    refT = np.ascontiguousarray(ref.T)                                        # [3, P]
+    for s in range(0, nc, chunk):
+        v = cell_vertices[s:s + chunk]
+        v0 = v[:, 0, :]
+        e = v[:, 1:, :] - v0[:, None, :]                                      # [c, 3 edges, 3]
+        x, y, z = (v0[:, d:d + 1] + e[:, :, d] @ refT for d in range(3))
+        out[s:s + chunk] = fun(x, y, z) @ w6
+    return out
+
+
+@dataclass
+class AdvectionCase:
+    """rho = 1 + amp*sin(pi*(k.(x - U t)) + phase), velocity U, pressure p."""
+    amp: float = 0.2
+    k: tuple = (1.0, 1.0, 1.0)
+    phase: float = 0.0
+    vel: tuple = (1.0, 1.0, 1.0)
+    p: float = 1.0
+    gamma: float = 1.4
+
+    def density_fn(self, t: float):
+        kx, ky, kz = self.k
+        ux, uy, uz = self.vel
+
+        def f(x, y, z):
+            return 1.0 + self.amp * np.sin(math.pi * (kx * (x - ux * t) + ky * (y - uy * t)
+                                                      + kz * (z - uz * t)) + self.phase)
+        return f
+
+    def density_average(self, mesh: TetMesh, t: float = 0.0, npts: int | None = None) -> np.ndarray:
+        if npts is None:
+            npts = default_npts(mesh.cell_vertices, math.pi * sum(abs(v) for v in self.k))
+        return cell_average(mesh.cell_vertices, self.density_fn(t), npts)
+
+    def conservative(self, mesh: TetMesh, t: float = 0.0, npts: int | None = None) -> np.ndarray:
+        """[n_cells, 5] cell averages of (rho, rho U, rho V, rho W, rho E)."""
+        rho = self.density_average(mesh, t, npts)
+        u = np.asarray(self.vel, dtype=np.float64)
+        q = np.empty((rho.shape[0], 5))
+        q[:, 0] = rho
+        q[:, 1:4] = rho[:, None] * u[None, :]
+        q[:, 4] = self.p / (self.gamma - 1.0) + 0.5 * rho * float(u @ u)
+        return q
+
+
+def uniform_state(n_cells: int, rho=1.0, vel=(0.3, -0.2, 0.5), p=1.0, gamma=1.4) -> np.ndarray:
+    u = np.asarray(vel, dtype=np.float64)
+    q = np.empty((n_cells, 5))
+    q[:, 0] = rho
+    q[:, 1:4] = rho * u
+    q[:, 4] = p / (gamma - 1.0) + 0.5 * rho * float(u @ u)
+    return q
+
+
+def error_norms(mesh_volumes: np.ndarray, num: np.ndarray, exact: np.ndarray) -> dict:
+    """Volume-weighted L1 / L2 / Linf of cell-average errors (not divided by |D|)."""
+    e = num - exact
+    return {"L1": float(np.sum(np.abs(e) * mesh_volumes)),
+            "L2": float(np.sqrt(np.sum(e * e * mesh_volumes))),
+            "Linf": float(np.max(np.abs(e)))}
+
+
+def tet_volumes(cell_vertices: np.ndarray) -> np.ndarray:
+    e = cell_vertices[:, 1:, :] - cell_vertices[:, :1, :]
+    return np.abs(np.linalg.det(e)) / 6.0
+
+
+def advection_config(n: int, seed_offset: int | None = None, jitter: float = 0.1):
+    """The periodic accuracy-test box at resolution n (seed SEED+n unless given)."""
+    seed = SEED_ADVECTION + (n if seed_offset is None else seed_offset)
+    if n == 8 and seed_offset is None:
+        seed = SEED_ADVECTION
+    mesh = kuhn_box(n, 2.0, jitter, seed)
+    case = AdvectionCase()
+    return mesh, case
+
+
+@dataclass
+class Request:
+    rid: int
+    n: int
+    seed: int
+    case: AdvectionCase
+    precision: int          # 0 = FP64, 1 = FP32-mixed
+    steps: int
+    arrival: float = 0.0
+
+
+def serve_requests(count: int = 256, seed: int = 2407, n_range=(8, 48), steps: int = 200,
+                   rate: float = 1.0) -> list:
+    """Seeded request stream: Kuhn boxes of 6 N^3 cells with random smooth data.
+
+    N ~ U{n_range}, amplitude ~ U[0.05, 0.2], k in {1,2}^3, phase ~ U[0, 2pi),
+    Mach ~ U[0.1, 2.0] along a direction uniform on the sphere, p = 1,
+    precision ~ Bernoulli(1/2), Poisson arrivals at `rate` per second.
+    """
+    u = uniform01(seed, 16 * count).reshape(count, 16)
+    reqs = []
+    t = 0.0
+    for r in range(count):
+        row = u[r]
+        n = n_range[0] + int(row[0] * (n_range[1] - n_range[0] + 1))
+        amp = 0.05 + 0.15 * row[1]
+        k = tuple(1.0 + float(row[2 + a] >= 0.5) for a in range(3))
+        phase = 2 * math.pi * row[5]
+        mach = 0.1 + 1.9 * row[6]
+        cz = 2 * row[7] - 1
+        ph = 2 * math.pi * row[8]
+        sz = math.sqrt(max(0.0, 1 - cz * cz))
+        d = (sz * math.cos(ph), sz * math.sin(ph), cz)
+        c = math.sqrt(1.4)            # sound speed at rho = 1, p = 1
+        vel = tuple(mach * c * x for x in d)
+        prec = int(row[9] >= 0.5)
+        t += -math.log(max(1e-300, 1.0 - row[10])) / rate
+        reqs.append(Request(rid=r, n=n, seed=seed * 1000003 + r, precision=prec, steps=steps,
+                            case=AdvectionCase(amp=amp, k=k, phase=phase, vel=vel), arrival=t))
+    return reqs
