@@ -1,0 +1,193 @@
+"""Throughput of the HGKS S2O4 step on one MI355X.
+
+Workload: the smooth-advection accuracy test of Sec. 5.1 at 6*64^3 = 1,572,864
+jittered Kuhn tetrahedra (periodic [0,2]^3, rho = 1 + 0.2 sin(pi(x+y+z)),
+U = V = W = 1, p = 1, CFL 0.3, tau = 0), inputs already resident in HBM.
+A step is one full two-stage S2O4 step (CFL dt, two WENO reconstructions,
+two face-flux passes, two stage updates).  Reports cell-updates/s for the FP64
+path (the headline value) and for the FP32-mixed form, the roofline position
+of the dominant kernel (per-kernel HIP events inside the timed region), and the
+CPU oracle timed on this host.
+
+    python bench.py [--steps K] [--warmup W] [--n N] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
+
+# Algorithmic bytes each kernel must move, per unit (cell or face), FP64 form:
+#   weno   per cell: 16 stencil ids (64) + own state (40) + big-stencil pseudo-inverse
+#          9x16 (1152) + sub-stencil pseudo-inverses 4x3x6 (576) + 1/h and second
+#          moments (56) + reconstruction written (400)                       = 2288
+#   flux   per face: cells (8) + normal, area, Gauss offsets (176) + flux written (80)
+#          = 264, plus per cell the reconstruction read once (400)
+#   update per cell: face ids (16) + its faces' fluxes (2 faces' worth, 160) + 1/|V|
+#          and h (16) + state traffic (stage 1: 3 x 40, stage 2: 2 x 40)       ~ 292
+def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool) -> float:
+    if kernel == "weno":
+        return nc * (64 + 40 + 1152 + 576 + 56 + (200 if mixed else 400))
+    if kernel == "flux":
+        return nf * 264 + nc * ((200 + 40) if mixed else 400)
+    if kernel == "update":
+        return nc * (16 + 160 + 16 + 100)
+    return 0.0
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2407_00656_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_hip_sha") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    v = t.get("bytes_per_launch", {}).get(kernel)
+    return float(v) if v is not None else None
+
+
+def run_gpu(mesh, q0, precision, steps, warmup):
+    from paper_2407_00656_amd import hgks
+    s = hgks.Solver(hgks.params(precision=precision))
+    t0 = time.perf_counter()
+    s.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period)
+    t_setup = time.perf_counter() - t0
+    s.init_state(q0)
+    s.step(warmup)
+    s.sync()
+    s.profile_enable(True)
+    s.profile_reset()
+    s.sync()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    el = time.perf_counter() - t0
+    prof = {k: s.profile_read(k) for k in ("dt", "weno", "flux", "update")}
+    s.profile_enable(False)
+    info = s.info()
+    foot = s.footprint()
+    q, t = s.get_state()
+    s.close()
+    return {"seconds": el, "setup_s": t_setup, "prof": prof, "info": info, "footprint": foot, "t": t, "q": q}
+
+
+def cpu_baseline(n_sample: int = 32):
+    """One oracle S2O4 step on 6*n^3 tets of the same advection data (all host threads)."""
+    from oracle import oracle as O
+    from paper_2407_00656_amd import workloads as W
+    mesh = W.kuhn_box(n_sample, seed=W.SEED_ADVECTION + n_sample)
+    q0 = W.AdvectionCase().conservative(mesh)
+    om = O.Mesh.from_workload(mesh)
+    t0 = time.perf_counter()
+    om.step(q0, 1)
+    el = time.perf_counter() - t0
+    return {"value": mesh.n_cells / el, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"one S2O4 step of the FP64 oracle on 6*{n_sample}^3 = {mesh.n_cells} tets "
+                      f"(same advection data), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU halo "
+              "exchange is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2407_00656_amd import hgks
+    from paper_2407_00656_amd import workloads as W
+
+    n = args.n
+    print(f"bench: building inputs 6*{n}^3", file=sys.stderr, flush=True)
+    mesh = W.kuhn_box(n, seed=W.SEED_ADVECTION + (0 if n == 8 else n))
+    q0 = W.AdvectionCase().conservative(mesh)
+    nc = mesh.n_cells
+    workload = f"advection 6*{n}^3 tets"
+
+    print("bench: FP64", file=sys.stderr, flush=True)
+    r64 = run_gpu(mesh, q0, hgks.FP64, args.steps, args.warmup)
+    nf = r64["info"]["n_faces"]
+    value = nc * args.steps / r64["seconds"]
+    r32 = None
+    if not args.no_fp32:
+        print("bench: FP32-mixed", file=sys.stderr, flush=True)
+        r32 = run_gpu(mesh, q0, hgks.FP32_MIXED, args.steps, args.warmup)
+
+    # dominant kernel of the FP64 step and its roofline position
+    prof = r64["prof"]
+    dom = max(("weno", "flux", "update"), key=lambda k: prof[k][0])
+    ms_total, launches = prof[dom]
+    avg_s = ms_total / 1e3 / max(1, launches)
+    per_launch = algorithmic_bytes(dom, nc, nf, False)
+    achieved = per_launch / avg_s / 1e9
+    kernels = {}
+    for k in ("dt", "weno", "flux", "update"):
+        ms, cnt = prof[k]
+        b = algorithmic_bytes(k, nc, nf, False)
+        kernels[k] = {"avg_us": 1e3 * ms / max(1, cnt), "launches": cnt,
+                      "share": ms / max(1e-12, sum(v[0] for v in prof.values())),
+                      "alg_GBps": (b / (ms / 1e3 / max(1, cnt)) / 1e9) if b and cnt else None}
+    traffic = measured_traffic(dom, workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(32 if n >= 32 else n)
+
+    out = {
+        "metric": "cell-updates/s per S2O4 step on 1 MI355X (FP64 vs FP32-mixed); serve p50/p99",
+        "value": round(value, 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r64["seconds"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{workload}, periodic [0,2]^3, jitter 0.1h, rho=1+0.2sin(pi(x+y+z)), "
+                               f"U=(1,1,1), p=1, CFL 0.3, tau=0", "cells": nc, "faces": nf},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp32_mixed": None if r32 is None else {
+            "value": round(nc * args.steps / r32["seconds"], 1),
+            "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
+            "speedup_vs_fp64": round(r64["seconds"] / r32["seconds"], 3)},
+        "kernels": kernels,
+        "setup_s": round(r64["setup_s"], 2),
+        "footprint_GB": round(r64["footprint"] / 1e9, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

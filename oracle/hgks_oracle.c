@@ -36,6 +36,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_E_ARG 1
@@ -1020,4 +1023,115 @@ int orc_reconstruct(const orc_mesh *m, const orc_params *p, const double *Q, int
 /* mean over cell i of the scaled monomials, as used by the least-squares rows */
 void orc_cell_monomial_means(const orc_mesh *m, int64_t i, const double *target_c, double target_h, double *out) {
     tet_monomial_means(m->vert[i], target_c, target_h, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* One S2O4 step for a sample of cells only                                   */
+/* ------------------------------------------------------------------------- */
+
+/* mark every cell of the two-layer stencil of each marked cell, and the cell */
+static void mark_stencils(const orc_mesh *m, const unsigned char *in, unsigned char *out) {
+    for (int64_t i = 0; i < m->nc; ++i) {
+        if (!in[i]) continue;
+        out[i] = 1;
+        for (int k = 0; k < m->nsten[i]; ++k) out[m->sten[i][k]] = 1;
+    }
+}
+
+/* faces touching a marked cell, and the cells on their other side */
+static void mark_faces(const orc_mesh *m, const unsigned char *cells, unsigned char *faces, unsigned char *both) {
+    for (int64_t f = 0; f < m->nf; ++f) {
+        int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+        if (cells[l] || cells[r]) { faces[f] = 1; both[l] = both[r] = 1; }
+    }
+}
+
+/* L and dL/dt of the cells in `need`, evaluating WENO and fluxes only where needed. */
+static int rhs_subset(const orc_mesh *m, const orc_params *p, const double *Q, double dt,
+                      const unsigned char *need, double *L, double *dL) {
+    unsigned char *faces = calloc((size_t)m->nf, 1), *wcells = calloc((size_t)m->nc, 1);
+    mark_faces(m, need, faces, wcells);
+    orc_weno *W = malloc(sizeof(orc_weno) * m->nc);
+    int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 64) reduction(max: rc)
+    for (int64_t i = 0; i < m->nc; ++i) {
+        if (!wcells[i]) continue;
+        int r_ = weno_cell(m, p, Q, i, &W[i]);
+        if (r_ > rc) rc = r_;
+    }
+    double (*FF)[10] = calloc((size_t)m->nf, sizeof(double[10]));
+    if (rc == ORC_OK) {
+#pragma omp parallel for schedule(dynamic, 64) reduction(max: rc)
+        for (int64_t f = 0; f < m->nf; ++f) {
+            if (!faces[f]) continue;
+            int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+            double Ff[5] = {0}, dFf[5] = {0};
+            for (int g = 0; g < 3; ++g) {
+                double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5];
+                for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
+                weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
+                weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+                int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
+                if (r_ > rc) rc = r_;
+                for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
+            }
+            for (int q = 0; q < 5; ++q) { FF[f][q] = Ff[q] * m->farea[f]; FF[f][5 + q] = dFf[q] * m->farea[f]; }
+        }
+    }
+    if (rc == ORC_OK)
+        for (int64_t i = 0; i < m->nc; ++i) {
+            if (!need[i]) continue;
+            double s[10] = {0};
+            for (int p_ = 0; p_ < 4; ++p_) {
+                int64_t f = m->cface[i][p_];
+                double sign = m->fcell[f][0] == i ? -1.0 : 1.0;
+                for (int q = 0; q < 10; ++q) s[q] += sign * FF[f][q];
+            }
+            for (int q = 0; q < 5; ++q) { L[5 * i + q] = s[q] / m->vol[i]; dL[5 * i + q] = s[5 + q] / m->vol[i]; }
+        }
+    free(faces); free(wcells); free(W); free(FF);
+    return rc;
+}
+
+/*
+ * Q^{n+1} of the listed cells after one S2O4 step of size dt from Q (the whole
+ * state): the same arithmetic as orc_step, evaluated only on the dependency
+ * region of the sample (the cells whose stage values the sample's fluxes read).
+ */
+int orc_step_sample(const orc_mesh *m, const orc_params *p, const double *Q, double dt,
+                    int64_t ns, const int64_t *cells, double *out /*[ns][5]*/) {
+    const int64_t nc = m->nc;
+    unsigned char *s2 = calloc((size_t)nc, 1), *w2 = calloc((size_t)nc, 1), *qs_need = calloc((size_t)nc, 1);
+    unsigned char *f2 = calloc((size_t)m->nf, 1);
+    for (int64_t k = 0; k < ns; ++k) s2[cells[k]] = 1;
+    mark_faces(m, s2, f2, w2);                 /* cells whose WENO at Q* the sample needs */
+    mark_stencils(m, w2, qs_need);             /* cells whose Q* those reconstructions read */
+    double *L = calloc((size_t)(5 * nc), sizeof(double)), *dL = calloc((size_t)(5 * nc), sizeof(double));
+    double *Qs = malloc(sizeof(double) * 5 * nc);
+    memcpy(Qs, Q, sizeof(double) * 5 * nc);
+    int rc = rhs_subset(m, p, Q, dt, qs_need, L, dL);
+    if (rc == ORC_OK) {
+        for (int64_t i = 0; i < nc; ++i)
+            if (qs_need[i])
+                for (int q = 0; q < 5; ++q) Qs[5 * i + q] = Q[5 * i + q] + 0.5 * dt * L[5 * i + q] + dt * dt / 8.0 * dL[5 * i + q];
+        double *Ls = calloc((size_t)(5 * nc), sizeof(double)), *dLs = calloc((size_t)(5 * nc), sizeof(double));
+        rc = rhs_subset(m, p, Qs, dt, s2, Ls, dLs);
+        for (int64_t k = 0; k < ns && rc == ORC_OK; ++k) {
+            int64_t i = cells[k];
+            for (int q = 0; q < 5; ++q)
+                out[5 * k + q] = Q[5 * i + q] + dt * L[5 * i + q] + dt * dt / 6.0 * (dL[5 * i + q] + 2.0 * dLs[5 * i + q]);
+        }
+        free(Ls); free(dLs);
+    }
+    free(s2); free(w2); free(qs_need); free(f2); free(L); free(dL); free(Qs);
+    return rc;
+}
+
+/* number of threads the parallel loops use */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

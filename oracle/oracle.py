@@ -85,6 +85,9 @@ def lib():
         L.orc_reconstruct.restype = C.c_int
         L.orc_reconstruct.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int64, _dp, _dp, _dp]
         L.orc_cell_monomial_means.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_double, _dp]
+        L.orc_threads.restype = C.c_int
+        L.orc_step_sample.restype = C.c_int
+        L.orc_step_sample.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_double, C.c_int64, _i64p, _dp]
         _lib = L
     return _lib
 
@@ -187,6 +190,18 @@ class Mesh:
             raise OracleError(f"orc_step failed ({rc})")
         return q, dt.value
 
+    def step_sample(self, q, dt, cells, params=None):
+        """Q^{n+1} of the listed cells after one step of size dt (same arithmetic as step)."""
+        p = params or default_params()
+        q = _f64(q, (self.nc, 5))
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty((cells.shape[0], 5))
+        rc = lib().orc_step_sample(self._h, C.byref(p), _d(q), float(dt), cells.shape[0],
+                                   cells.ctypes.data_as(_i64p), _d(out))
+        if rc:
+            raise OracleError(f"orc_step_sample failed ({rc})")
+        return out
+
     def weno_cell(self, q, i, params=None):
         p = params or default_params()
         q = _f64(q, (self.nc, 5))
@@ -206,6 +221,10 @@ class Mesh:
         if rc:
             raise OracleError(f"orc_reconstruct failed ({rc})")
         return val, grad
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def gks_flux(ql, gl, qr, gr, n, dt, params=None):

@@ -1,0 +1,711 @@
+// C ABI of the HGKS library: contexts (one problem each), the step driver and
+// the pool that batches many contexts into shared launches.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hgks.h"
+#include "hgks_internal.h"
+#include "kernels.h"
+
+using namespace hgks;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Workgroups are handed to the eight XCDs round-robin by workgroup id.  Give
+// each XCD a contiguous run of tiles so that the stencil / neighbour data a
+// tile shares with the next one sits in the same XCD's L2.
+template <class T>
+void xcd_order(std::vector<T> &tiles, size_t b, size_t e) {
+    const size_t n = e - b;
+    if (n < 16) return;
+    std::vector<T> src(tiles.begin() + b, tiles.begin() + e);
+    size_t start[8];
+    size_t s = 0;
+    for (int x = 0; x < 8; ++x) {
+        start[x] = s;
+        s += (n > (size_t)x) ? (n - x + 7) / 8 : 0;
+    }
+    for (size_t k = 0; k < n; ++k) tiles[b + k] = src[start[k % 8] + k / 8];
+}
+
+struct Layout {
+    size_t sten, pinv0, pinvs, cgeo, cface, fcell, fgeo, Q, Qs, R, C, C32, FF, acc, dtpart, scal, desc, tiles, total;
+};
+
+Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, bool mixed, bool coloured) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t p = o; o += up(bytes); return p; };
+    L.sten = take((size_t)SLOTS * nc * 4);
+    L.pinv0 = take((size_t)144 * nc * 8);
+    L.pinvs = take((size_t)72 * nc * 8);
+    L.cgeo = take((size_t)CGEO * nc * 8);
+    L.cface = take((size_t)4 * nc * 4);
+    L.fcell = take((size_t)2 * nf * 4);
+    L.fgeo = take((size_t)FGEO * nf * 8);
+    L.Q = take((size_t)5 * nc * 8);
+    L.Qs = take((size_t)5 * nc * 8);
+    L.R = take((size_t)5 * nc * 8);
+    L.C = take(mixed ? 0 : (size_t)5 * NCOEF * nc * 8);
+    L.C32 = take(mixed ? (size_t)5 * NCOEF * nc * 4 : 0);
+    L.FF = take(coloured ? 0 : (size_t)10 * nf * 8);
+    L.acc = take(coloured ? (size_t)10 * nc * 8 : 0);
+    L.dtpart = take((size_t)n_ctiles * 8);
+    L.scal = take(64);
+    L.desc = take(sizeof(ProbDesc));
+    L.tiles = take((size_t)(n_ctiles + n_ftiles) * sizeof(Tile));
+    L.total = o;
+    return L;
+}
+
+int n_cell_tiles(int64_t nc) { return (int)((nc + UPD_TILE - 1) / UPD_TILE); }
+
+}  // namespace
+
+struct hgks_ctx {
+    hgks_params prm{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hgks_allocator alloc{};
+    bool user_alloc = false;
+    std::string err;
+    bool has_mesh = false, has_state = false;
+    int64_t nc = 0, nf = 0;
+    std::vector<int64_t> perm;
+    std::vector<int32_t> colour_offsets;   // face offsets of each colour class
+    std::vector<int32_t> colour_tiles;     // tile offsets of each colour class
+    char *base = nullptr;                  // the one device allocation
+    size_t bytes = 0;
+    ProbDesc desc{};
+    ProbDesc *d_desc = nullptr;
+    Tile *d_ctiles = nullptr, *d_ftiles = nullptr;
+    int n_ctiles = 0, n_ftiles = 0;
+    std::vector<Tile> h_ctiles, h_ftiles;  // host copies (pool builds its tables from them)
+    // profiling
+    bool prof = false;
+    struct Rec { int id; hipEvent_t a, b; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> spare;
+    double prof_ms[4] = {0, 0, 0, 0};
+    int64_t prof_n[4] = {0, 0, 0, 0};
+    int pool_refs = 0;
+    hipStream_t pool_stream = nullptr;    // stream of the pool holding this context
+};
+
+namespace {
+
+hgks_status fail(hgks_ctx *c, hgks_status s, const std::string &m) {
+    if (c) c->err = m;
+    return s;
+}
+
+hgks_status hip_fail(hgks_ctx *c, hipError_t e, const char *what) {
+    return fail(c, HGKS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, x)                                    \
+    do {                                                \
+        hipError_t e_ = (x);                            \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #x); \
+    } while (0)
+
+void release(hgks_ctx *c) {
+    if (c->base) {
+        if (c->user_alloc)
+            c->alloc.free(c->base, c->stream, c->alloc.user);
+        else
+            (void)hipFree(c->base);
+    }
+    c->base = nullptr;
+    c->bytes = 0;
+    c->has_mesh = c->has_state = false;
+}
+
+hipEvent_t take_event(hgks_ctx *c) {
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `launch` on the context's stream, bracketed by events when profiling.
+template <class F>
+void timed(hgks_ctx *c, int id, F &&launch) {
+    if (!c->prof) {
+        launch();
+        return;
+    }
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) {
+        launch();
+        return;
+    }
+    (void)hipEventRecord(a, c->stream);
+    launch();
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({id, a, b});
+}
+
+void collect_profile(hgks_ctx *c) {
+    for (auto &r : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            c->prof_ms[r.id] += ms;
+            c->prof_n[r.id] += 1;
+        }
+        c->spare.push_back(r.a);
+        c->spare.push_back(r.b);
+    }
+    c->pending.clear();
+}
+
+bool tau0_of(const hgks_params &p) { return p.tau_mode == 0; }
+
+hgks_status check_params(const hgks_params *p) {
+    if (!p) return HGKS_E_INVALID_ARG;
+    if (!(p->gamma > 1.0 && p->gamma < 5.0 / 3.0 + 1e-12)) return HGKS_E_INVALID_ARG;
+    if (!(p->cfl > 0.0) || !(p->weno_eps > 0.0) || !(p->gamma_lin > 0.0 && p->gamma_lin < 0.25)) return HGKS_E_INVALID_ARG;
+    if (p->tau_mode < 0 || p->tau_mode > 1) return HGKS_E_INVALID_ARG;
+    if (p->precision != HGKS_FP64 && p->precision != HGKS_FP32_MIXED) return HGKS_E_INVALID_ARG;
+    if (p->accumulation != HGKS_ACC_GATHER && p->accumulation != HGKS_ACC_COLOURED) return HGKS_E_INVALID_ARG;
+    return HGKS_OK;
+}
+
+// Queue one S2O4 step of a single context.
+void enqueue_step(hgks_ctx *c, double dt_fixed) {
+    const bool mixed = c->prm.precision == HGKS_FP32_MIXED;
+    const bool tau0 = tau0_of(c->prm);
+    const bool col = c->prm.accumulation == HGKS_ACC_COLOURED;
+    hipStream_t s = c->stream;
+    timed(c, 0, [&] { launch_dt_final(c->d_desc, 1, dt_fixed, s); });
+    for (int stage = 1; stage <= 2; ++stage) {
+        timed(c, 1, [&] { launch_weno(c->d_desc, c->d_ctiles, c->n_ctiles, stage, mixed, s); });
+        if (col) {
+            for (size_t k = 0; k + 1 < c->colour_tiles.size(); ++k) {
+                int t0 = c->colour_tiles[k], t1 = c->colour_tiles[k + 1];
+                timed(c, 2, [&] { launch_flux(c->d_desc, c->d_ftiles + t0, t1 - t0, stage, mixed, tau0, true, s); });
+            }
+        } else {
+            timed(c, 2, [&] { launch_flux(c->d_desc, c->d_ftiles, c->n_ftiles, stage, mixed, tau0, false, s); });
+        }
+        timed(c, 3, [&] { launch_update(c->d_desc, c->d_ctiles, c->n_ctiles, stage, col, s); });
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void hgks_default_params(hgks_params *p) {
+    if (!p) return;
+    p->gamma = 1.4;
+    p->cfl = 0.3;
+    p->tau_mode = 0;
+    p->tau_eps = 0.05;
+    p->tau_C = 1.0;
+    p->weno_eps = 1e-8;
+    p->gamma_lin = 0.025;
+    p->precision = HGKS_FP64;
+    p->accumulation = HGKS_ACC_GATHER;
+    p->reorder = 1;
+}
+
+hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream, const hgks_allocator *alloc,
+                        hgks_ctx **out) {
+    if (!out) return HGKS_E_INVALID_ARG;
+    *out = nullptr;
+    if (check_params(params) != HGKS_OK) return HGKS_E_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HGKS_E_INVALID_ARG;
+    if (alloc && (!alloc->alloc || !alloc->free)) return HGKS_E_INVALID_ARG;
+    hgks_ctx *c = new (std::nothrow) hgks_ctx;
+    if (!c) return HGKS_E_OOM;
+    c->prm = *params;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (alloc) {
+        c->alloc = *alloc;
+        c->user_alloc = true;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return HGKS_E_DEVICE;
+    }
+    *out = c;
+    return HGKS_OK;
+}
+
+hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells, int npc,
+                             const int64_t *cell_nodes, const double *period, int64_t n_bfaces,
+                             const int64_t *bface_nodes, const int32_t *bface_kind) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    if (c->pool_refs) return fail(c, HGKS_E_STATE, "context is in a pool");
+    if (n_bfaces != 0 || bface_nodes || bface_kind)
+        return fail(c, HGKS_E_INVALID_ARG, "boundary faces are not supported: every face must join two cells");
+    HostMesh hm;
+    std::string err;
+    hgks_status st = build_mesh(c->prm, n_nodes, xyz, n_cells, npc, cell_nodes, period, hm, err);
+    if (st != HGKS_OK) return fail(c, st, err);
+    HIPCHK(c, hipSetDevice(c->device));
+    release(c);
+    const bool mixed = c->prm.precision == HGKS_FP32_MIXED;
+    const bool col = c->prm.accumulation == HGKS_ACC_COLOURED;
+    // tile tables
+    std::vector<Tile> ct, ft;
+    const int nct = n_cell_tiles(hm.nc);
+    for (int t = 0; t < nct; ++t) {
+        int b = t * UPD_TILE;
+        ct.push_back({0, b, t, (int32_t)std::min<int64_t>(hm.nc, b + UPD_TILE)});
+    }
+    xcd_order(ct, 0, ct.size());
+    c->colour_tiles.clear();
+    if (col) {
+        for (size_t k = 0; k + 1 < hm.colour_offsets.size(); ++k) {
+            c->colour_tiles.push_back((int)ft.size());
+            size_t b0 = ft.size();
+            for (int32_t b = hm.colour_offsets[k]; b < hm.colour_offsets[k + 1]; b += FACE_TILE)
+                ft.push_back({0, b, (int)ft.size(), std::min<int32_t>(hm.colour_offsets[k + 1], b + FACE_TILE)});
+            xcd_order(ft, b0, ft.size());
+        }
+        c->colour_tiles.push_back((int)ft.size());
+    } else {
+        for (int64_t b = 0; b < hm.nf; b += FACE_TILE)
+            ft.push_back({0, (int32_t)b, (int)ft.size(), (int32_t)std::min<int64_t>(hm.nf, b + FACE_TILE)});
+        xcd_order(ft, 0, ft.size());
+    }
+    Layout L = layout_for(hm.nc, hm.nf, (int)ct.size(), (int)ft.size(), mixed, col);
+    void *mem = nullptr;
+    if (c->user_alloc) {
+        mem = c->alloc.alloc(L.total, c->stream, c->alloc.user);
+        if (!mem) return fail(c, HGKS_E_OOM, "allocator returned NULL");
+    } else {
+        hipError_t e = hipMalloc(&mem, L.total);
+        if (e != hipSuccess) return fail(c, HGKS_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->base = (char *)mem;
+    c->bytes = L.total;
+    char *B = c->base;
+    ProbDesc &D = c->desc;
+    D = ProbDesc{};
+    D.nc = (int32_t)hm.nc;
+    D.nf = (int32_t)hm.nf;
+    D.n_cell_tiles = (int32_t)ct.size();
+    D.sten = (const int32_t *)(B + L.sten);
+    D.pinv0 = (const double *)(B + L.pinv0);
+    D.pinvs = (const double *)(B + L.pinvs);
+    D.cgeo = (const double *)(B + L.cgeo);
+    D.cface = (const int32_t *)(B + L.cface);
+    D.fcell = (const int32_t *)(B + L.fcell);
+    D.fgeo = (const double *)(B + L.fgeo);
+    D.Q = (double *)(B + L.Q);
+    D.Qs = (double *)(B + L.Qs);
+    D.R = (double *)(B + L.R);
+    D.C = mixed ? nullptr : (double *)(B + L.C);
+    D.C32 = mixed ? (float *)(B + L.C32) : nullptr;
+    D.FF = col ? nullptr : (double *)(B + L.FF);
+    D.acc = col ? (double *)(B + L.acc) : nullptr;
+    D.dtpart = (double *)(B + L.dtpart);
+    D.dt = (double *)(B + L.scal);
+    D.time = (double *)(B + L.scal + 8);
+    D.flag = (int32_t *)(B + L.scal + 16);
+    D.gamma = c->prm.gamma;
+    D.K = (5.0 - 3.0 * c->prm.gamma) / (c->prm.gamma - 1.0);
+    D.weno_eps = c->prm.weno_eps;
+    D.gamma_lin = c->prm.gamma_lin;
+    D.cfl = c->prm.cfl;
+    D.tau_eps = c->prm.tau_eps;
+    D.tau_C = c->prm.tau_C;
+    D.tau_mode = c->prm.tau_mode;
+    D.mixed = mixed ? 1 : 0;
+    c->d_desc = (ProbDesc *)(B + L.desc);
+    c->d_ctiles = (Tile *)(B + L.tiles);
+    c->d_ftiles = c->d_ctiles + ct.size();
+    c->n_ctiles = (int)ct.size();
+    c->n_ftiles = (int)ft.size();
+    c->h_ctiles = ct;
+    c->h_ftiles = ft;
+    hipStream_t s = c->stream;
+    auto h2d = [&](const void *dst, const void *src, size_t n) {
+        return hipMemcpyAsync((void *)dst, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIPCHK(c, h2d(D.sten, hm.sten.data(), hm.sten.size() * 4));
+    HIPCHK(c, h2d(D.pinv0, hm.pinv0.data(), hm.pinv0.size() * 8));
+    HIPCHK(c, h2d(D.pinvs, hm.pinvs.data(), hm.pinvs.size() * 8));
+    HIPCHK(c, h2d(D.cgeo, hm.cgeo.data(), hm.cgeo.size() * 8));
+    HIPCHK(c, h2d(D.cface, hm.cface.data(), hm.cface.size() * 4));
+    HIPCHK(c, h2d(D.fcell, hm.fcell.data(), hm.fcell.size() * 4));
+    HIPCHK(c, h2d(D.fgeo, hm.fgeo.data(), hm.fgeo.size() * 8));
+    HIPCHK(c, h2d(c->d_desc, &D, sizeof(ProbDesc)));
+    HIPCHK(c, h2d(c->d_ctiles, ct.data(), ct.size() * sizeof(Tile)));
+    HIPCHK(c, h2d(c->d_ftiles, ft.data(), ft.size() * sizeof(Tile)));
+    if (col) launch_fill(D.acc, 0.0, (int64_t)10 * hm.nc, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->nc = hm.nc;
+    c->nf = hm.nf;
+    c->perm = std::move(hm.perm);
+    c->colour_offsets = hm.colour_offsets;
+    c->has_mesh = true;
+    c->has_state = false;
+    return HGKS_OK;
+}
+
+hgks_status hgks_init_state(hgks_ctx *c, const double *q, double t0) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    if (!c->has_mesh) return fail(c, HGKS_E_STATE, "init_state before mesh_upload");
+    if (c->pool_refs) return fail(c, HGKS_E_STATE, "context is in a pool");
+    if (!q || !std::isfinite(t0)) return fail(c, HGKS_E_INVALID_ARG, "null state");
+    const int64_t nc = c->nc;
+    std::vector<double> soa((size_t)5 * nc);
+    for (int64_t i = 0; i < nc; ++i) {
+        const double *x = q + 5 * c->perm[i];
+        double rho = x[0], ke = 0.5 * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]) / rho;
+        double p = (c->prm.gamma - 1.0) * (x[4] - ke);
+        bool ok = std::isfinite(x[0]) && std::isfinite(x[1]) && std::isfinite(x[2]) && std::isfinite(x[3]) &&
+                  std::isfinite(x[4]) && rho > 0.0 && p > 0.0;
+        if (!ok) return fail(c, HGKS_E_NONPHYSICAL, "initial state has rho <= 0, p <= 0 or a non-finite value");
+        for (int v = 0; v < 5; ++v) soa[(size_t)v * nc + i] = x[v];
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    double scal[3] = {0.0, t0, 0.0};
+    int32_t zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->desc.Q, soa.data(), soa.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->desc.dt, scal, 16, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->desc.flag, &zero, 4, hipMemcpyHostToDevice, c->stream));
+    launch_dt_local(c->d_desc, c->d_ctiles, c->n_ctiles, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->has_state = true;
+    return HGKS_OK;
+}
+
+hgks_status hgks_sync(hgks_ctx *c) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->pool_refs) HIPCHK(c, hipStreamSynchronize(c->pool_stream));
+    if (!c->has_state) return HGKS_OK;
+    int32_t flag = 0;
+    HIPCHK(c, hipMemcpy(&flag, c->desc.flag, 4, hipMemcpyDeviceToHost));
+    if (flag) return fail(c, HGKS_E_NONPHYSICAL, "a step produced rho <= 0, p <= 0 or a non-finite value");
+    return HGKS_OK;
+}
+
+hgks_status hgks_step_s2o4(hgks_ctx *c, int32_t nsteps, double dt_fixed, double *dt_last) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    if (!c->has_state) return fail(c, HGKS_E_STATE, "step before init_state");
+    if (c->pool_refs) return fail(c, HGKS_E_STATE, "context is in a pool: step it with hgks_pool_step");
+    if (nsteps < 0 || !std::isfinite(dt_fixed)) return fail(c, HGKS_E_INVALID_ARG, "bad step arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    for (int32_t k = 0; k < nsteps; ++k) enqueue_step(c, dt_fixed);
+    HIPCHK(c, hipGetLastError());
+    if (dt_last) {
+        hgks_status st = hgks_sync(c);
+        HIPCHK(c, hipMemcpy(dt_last, c->desc.dt, 8, hipMemcpyDeviceToHost));
+        if (st != HGKS_OK) return st;
+    }
+    return HGKS_OK;
+}
+
+hgks_status hgks_get_state(hgks_ctx *c, double *q_out, double *t_out) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    if (!c->has_state) return fail(c, HGKS_E_STATE, "get_state before init_state");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->pool_refs) HIPCHK(c, hipStreamSynchronize(c->pool_stream));
+    const int64_t nc = c->nc;
+    std::vector<double> soa((size_t)5 * nc);
+    HIPCHK(c, hipMemcpy(soa.data(), c->desc.Q, soa.size() * 8, hipMemcpyDeviceToHost));
+    double tt = 0.0;
+    int32_t flag = 0;
+    HIPCHK(c, hipMemcpy(&tt, c->desc.time, 8, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&flag, c->desc.flag, 4, hipMemcpyDeviceToHost));
+    if (q_out)
+        for (int64_t i = 0; i < nc; ++i)
+            for (int v = 0; v < 5; ++v) q_out[5 * c->perm[i] + v] = soa[(size_t)v * nc + i];
+    if (t_out) *t_out = tt;
+    if (flag) return fail(c, HGKS_E_NONPHYSICAL, "a step produced rho <= 0, p <= 0 or a non-finite value");
+    return HGKS_OK;
+}
+
+hgks_status hgks_mesh_info(const hgks_ctx *c, int64_t *n_cells, int64_t *n_faces, int32_t *slots, int32_t *ncol) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    if (!c->has_mesh) return HGKS_E_STATE;
+    if (n_cells) *n_cells = c->nc;
+    if (n_faces) *n_faces = c->nf;
+    if (slots) *slots = SLOTS;
+    if (ncol) *ncol = (int32_t)c->colour_offsets.size() - 1;
+    return HGKS_OK;
+}
+
+hgks_status hgks_footprint(const hgks_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return HGKS_E_INVALID_ARG;
+    *bytes = c->bytes;
+    return HGKS_OK;
+}
+
+hgks_status hgks_profile_enable(hgks_ctx *c, int on) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    c->prof = on != 0;
+    return HGKS_OK;
+}
+
+hgks_status hgks_profile_read(hgks_ctx *c, int id, double *ms, int64_t *n) {
+    if (!c || id < 0 || id > 3) return HGKS_E_INVALID_ARG;
+    collect_profile(c);
+    if (ms) *ms = c->prof_ms[id];
+    if (n) *n = c->prof_n[id];
+    return HGKS_OK;
+}
+
+hgks_status hgks_profile_reset(hgks_ctx *c) {
+    if (!c) return HGKS_E_INVALID_ARG;
+    collect_profile(c);
+    for (int k = 0; k < 4; ++k) {
+        c->prof_ms[k] = 0;
+        c->prof_n[k] = 0;
+    }
+    return HGKS_OK;
+}
+
+const char *hgks_last_error(const hgks_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void hgks_destroy(hgks_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    collect_profile(c);
+    for (auto e : c->spare) (void)hipEventDestroy(e);
+    release(c);
+    delete c;
+}
+
+hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const double *xyz, int64_t n_cells, int npc,
+                              const int64_t *cell_nodes, const double *period, double *stats, int64_t *perm,
+                              int32_t *sten) {
+    hgks_params p;
+    if (params) p = *params; else hgks_default_params(&p);
+    if (check_params(&p) != HGKS_OK) return HGKS_E_INVALID_ARG;
+    HostMesh hm;
+    std::string err;
+    hgks_status st = build_mesh(p, n_nodes, xyz, n_cells, npc, cell_nodes, period, hm, err);
+    if (st != HGKS_OK) return st;
+    if (stats) {
+        stats[0] = (double)hm.nf;
+        stats[1] = SLOTS;
+        stats[2] = hm.max_members;
+        stats[3] = hm.min_members;
+        stats[4] = (double)hm.colour_offsets.size() - 1;
+        stats[5] = hm.pinv_residual;
+        stats[6] = hm.closure;
+        stats[7] = hm.dup_slots;
+    }
+    if (perm) std::memcpy(perm, hm.perm.data(), hm.perm.size() * 8);
+    if (sten) std::memcpy(sten, hm.sten.data(), hm.sten.size() * 4);
+    return HGKS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// pool
+// ----------------------------------------------------------------------------
+}  // extern "C"
+
+struct hgks_pool {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0, used = 0;
+    std::vector<hgks_ctx *> slot;
+    // device tables for the current batch
+    char *tab = nullptr;
+    size_t tab_bytes = 0;
+    std::vector<int> last_key;
+    // launch plan of the current batch
+    ProbDesc *d_probs = nullptr;
+    int nprobs = 0;
+    Tile *d_ct = nullptr, *d_ft = nullptr;
+    struct Group { bool mixed, tau0; int c0, c1, f0, f1; };
+    std::vector<Group> groups;
+    int n_ct = 0;
+};
+
+namespace {
+
+size_t footprint_of(const hgks_params &p, int64_t nc) {
+    const int64_t nf = 2 * nc;
+    const int nct = n_cell_tiles(nc);
+    // coloured accumulation rounds every colour class up to whole tiles (at most 8 classes)
+    const bool col = p.accumulation == HGKS_ACC_COLOURED;
+    const int nft = (int)((nf + FACE_TILE - 1) / FACE_TILE) + (col ? 8 : 0);
+    Layout L = layout_for(nc, nf, nct, nft, p.precision == HGKS_FP32_MIXED, p.accumulation == HGKS_ACC_COLOURED);
+    return L.total;
+}
+
+hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
+    std::vector<int> key(slots, slots + n);
+    if (key == P->last_key && P->tab) return HGKS_OK;
+    // group contexts by kernel variant; FP64 first, then FP32-mixed
+    std::vector<int> order(key);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        auto ka = std::make_pair(P->slot[a]->prm.precision, P->slot[a]->prm.tau_mode);
+        auto kb = std::make_pair(P->slot[b]->prm.precision, P->slot[b]->prm.tau_mode);
+        return ka < kb;
+    });
+    std::vector<ProbDesc> probs;
+    std::vector<Tile> ct, ft;
+    P->groups.clear();
+    for (size_t k = 0; k < order.size(); ++k) {
+        hgks_ctx *c = P->slot[order[k]];
+        bool mixed = c->prm.precision == HGKS_FP32_MIXED, tau0 = c->prm.tau_mode == 0;
+        if (P->groups.empty() || P->groups.back().mixed != mixed || P->groups.back().tau0 != tau0)
+            P->groups.push_back({mixed, tau0, (int)ct.size(), (int)ct.size(), (int)ft.size(), (int)ft.size()});
+        const int pid = (int)probs.size();
+        probs.push_back(c->desc);
+        for (Tile t : c->h_ctiles) { t.prob = pid; ct.push_back(t); }
+        for (Tile t : c->h_ftiles) { t.prob = pid; ft.push_back(t); }
+        P->groups.back().c1 = (int)ct.size();
+        P->groups.back().f1 = (int)ft.size();
+    }
+    for (auto &g : P->groups) {
+        xcd_order(ct, g.c0, g.c1);
+        xcd_order(ft, g.f0, g.f1);
+    }
+    size_t need = up(probs.size() * sizeof(ProbDesc)) + up(ct.size() * sizeof(Tile)) + up(ft.size() * sizeof(Tile));
+    if (need > P->tab_bytes) {
+        if (P->tab) {
+            (void)hipStreamSynchronize(P->stream);
+            (void)hipFree(P->tab);
+        }
+        P->tab = nullptr;
+        if (hipMalloc((void **)&P->tab, need * 2) != hipSuccess) return HGKS_E_OOM;
+        P->tab_bytes = need * 2;
+    }
+    (void)hipStreamSynchronize(P->stream);
+    P->d_probs = (ProbDesc *)P->tab;
+    P->d_ct = (Tile *)(P->tab + up(probs.size() * sizeof(ProbDesc)));
+    P->d_ft = (Tile *)((char *)P->d_ct + up(ct.size() * sizeof(Tile)));
+    if (hipMemcpy(P->d_probs, probs.data(), probs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->d_ct, ct.data(), ct.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->d_ft, ft.data(), ft.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
+        return HGKS_E_DEVICE;
+    P->nprobs = (int)probs.size();
+    P->n_ct = (int)ct.size();
+    P->last_key = key;
+    return HGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hgks_pool **out) {
+    if (!out) return HGKS_E_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HGKS_E_INVALID_ARG;
+    hgks_pool *p = new (std::nothrow) hgks_pool;
+    if (!p) return HGKS_E_OOM;
+    p->device = device;
+    p->stream = (hipStream_t)hip_stream;
+    p->budget = hbm_budget;
+    *out = p;
+    return HGKS_OK;
+}
+
+hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int npc, size_t *bytes) {
+    if (!params || !bytes || n_cells <= 0 || npc != 4) return HGKS_E_INVALID_ARG;
+    *bytes = footprint_of(*params, n_cells);
+    return HGKS_OK;
+}
+
+hgks_status hgks_pool_add(hgks_pool *p, hgks_ctx *c, int *slot) {
+    if (!p || !c || !slot) return HGKS_E_INVALID_ARG;
+    if (!c->has_state) return HGKS_E_STATE;
+    if (c->device != p->device || c->prm.accumulation != HGKS_ACC_GATHER) return HGKS_E_INVALID_ARG;
+    if (p->budget && p->used + c->bytes > p->budget) return HGKS_E_OOM;
+    for (auto *x : p->slot)
+        if (x == c) return HGKS_E_INVALID_ARG;
+    // the pool runs on its own stream: finish the context's queued work first
+    (void)hipSetDevice(p->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return HGKS_E_DEVICE;
+    int s = -1;
+    for (size_t k = 0; k < p->slot.size(); ++k)
+        if (!p->slot[k]) { s = (int)k; break; }
+    if (s < 0) { s = (int)p->slot.size(); p->slot.push_back(nullptr); }
+    p->slot[s] = c;
+    p->used += c->bytes;
+    c->pool_refs++;
+    c->pool_stream = p->stream;
+    p->last_key.clear();
+    *slot = s;
+    return HGKS_OK;
+}
+
+hgks_status hgks_pool_step(hgks_pool *p, const int *slots, int n, int32_t nsteps) {
+    if (!p || (n > 0 && !slots) || n < 0 || nsteps < 0) return HGKS_E_INVALID_ARG;
+    if (n == 0 || nsteps == 0) return HGKS_OK;
+    for (int k = 0; k < n; ++k) {
+        if (slots[k] < 0 || slots[k] >= (int)p->slot.size() || !p->slot[slots[k]]) return HGKS_E_INVALID_ARG;
+        for (int j = 0; j < k; ++j)
+            if (slots[j] == slots[k]) return HGKS_E_INVALID_ARG;
+    }
+    if (hipSetDevice(p->device) != hipSuccess) return HGKS_E_DEVICE;
+    hgks_status st = pool_plan(p, slots, n);
+    if (st != HGKS_OK) return st;
+    hipStream_t s = p->stream;
+    for (int32_t it = 0; it < nsteps; ++it) {
+        launch_dt_final(p->d_probs, p->nprobs, 0.0, s);
+        for (int stage = 1; stage <= 2; ++stage) {
+            for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.mixed, s);
+            for (auto &g : p->groups) launch_flux(p->d_probs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.mixed, g.tau0, false, s);
+            launch_update(p->d_probs, p->d_ct, p->n_ct, stage, false, s);
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+    return HGKS_OK;
+}
+
+hgks_status hgks_pool_remove(hgks_pool *p, int slot) {
+    if (!p || slot < 0 || slot >= (int)p->slot.size() || !p->slot[slot]) return HGKS_E_INVALID_ARG;
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    hgks_ctx *c = p->slot[slot];
+    p->used -= c->bytes;
+    c->pool_refs--;
+    p->slot[slot] = nullptr;
+    p->last_key.clear();
+    return HGKS_OK;
+}
+
+hgks_status hgks_pool_used(const hgks_pool *p, size_t *bytes, int *n_slots) {
+    if (!p) return HGKS_E_INVALID_ARG;
+    if (bytes) *bytes = p->used;
+    if (n_slots) {
+        int k = 0;
+        for (auto *x : p->slot) k += x != nullptr;
+        *n_slots = k;
+    }
+    return HGKS_OK;
+}
+
+void hgks_pool_destroy(hgks_pool *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    for (auto *c : p->slot)
+        if (c) c->pool_refs--;
+    if (p->tab) (void)hipFree(p->tab);
+    delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal layouts shared by the host precompute, the HIP kernels and the C ABI.
+//
+// Device layout (everything structure-of-arrays over the internal cell / face
+// numbering, so that consecutive lanes touch consecutive addresses):
+//
+//   sten   int32  [16][nc]       two-layer stencil slots: 0..3 the face neighbours
+//                                i_1..i_4 (face p opposite node p), 4+3m..6+3m the
+//                                three other neighbours of i_{m+1} (Sec. 2.3); a cell
+//                                reached twice keeps both slots (the later one gets
+//                                zero weight), so sub-stencil membership is static
+//   pinv0  double [72][nc][2]    big-stencil pseudo-inverse, 9 rows x 16 slots;
+//                                element (r, s) in pair r*8 + s/2, lane s%2
+//   pinvs  double [36][nc][2]    sub-stencil pseudo-inverses, 4 x 3 rows x 6 members;
+//                                element ((m*3+k)*6+t) in pair e/2, lane e%2
+//   cgeo   double [9][nc]        1/h, scaled second moments (xx,yy,zz,xy,xz,yz),
+//                                1/|Omega|, h_dt = 6|Omega|/sum S
+//   cface  int32  [4][nc]        (face << 1) | (cell is the face's right cell)
+//   fcell  int32  [2][nf]        left, right cell of each face (normal points left->right)
+//   fgeo   double [22][nf]       n(3), S, Gauss-point offsets from the left centroid
+//                                [3][3], offsets from the right centroid [3][3]
+//   C      double [50][nc]       reconstruction: per variable (c0, g(3), H(6)) of
+//                                P(y) = c0 + g.y + H_xx y_x^2 + ... + H_yz y_y y_z,
+//                                y = x - centroid (FP32 in the mixed form, where c0
+//                                holds the deviation from the cell mean)
+//   FF     double [10][nf]       per face S * sum_G w_G (F, dF/dt)
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hgks.h"
+
+namespace hgks {
+
+constexpr int SLOTS = 16;
+constexpr int NCOEF = 10;          // per variable: c0, g(3), H(6)
+constexpr int CGEO = 9;
+constexpr int FGEO = 22;
+constexpr int CELL_TILE = 256;     // cells per workgroup (weno, update, dt)
+constexpr int FACE_TILE = 64;      // faces per workgroup (flux: 3 waves, one per Gauss point)
+
+// Sub-stencil m takes first-layer slots SUBFIRST[m][0..2] and slots 4+3m..6+3m.
+// S_1 = {i1,i2,i3} + N(i1), S_2 = {i1,i2,i4} + N(i2), S_3 = {i2,i3,i4} + N(i3),
+// S_4 = {i3,i1,i4} + N(i4)   (Sec. 2.3, tetrahedral sub-stencils)
+constexpr int SUBFIRST[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
+
+struct HostMesh {
+    int64_t nc = 0, nf = 0;
+    std::vector<int64_t> perm;      // internal cell c holds caller cell perm[c]
+    std::vector<int32_t> sten;      // [16][nc]
+    std::vector<double> pinv0;      // [72][nc][2]
+    std::vector<double> pinvs;      // [36][nc][2]
+    std::vector<double> cgeo;       // [9][nc]
+    std::vector<int32_t> cface;     // [4][nc]
+    std::vector<int32_t> fcell;     // [2][nf]
+    std::vector<double> fgeo;       // [22][nf]
+    // faces grouped by colour (coloured accumulation); colour_offsets[c]..[c+1]
+    std::vector<int32_t> colour_offsets;
+    // diagnostics
+    int max_members = 0, min_members = 0, dup_slots = 0;
+    double pinv_residual = 0.0, closure = 0.0;
+};
+
+// Builds the device-ready arrays on the host.  Returns HGKS_OK or an error with `err` set.
+hgks_status build_mesh(const hgks_params &prm, int64_t n_nodes, const double *xyz, int64_t n_cells,
+                       int nodes_per_cell, const int64_t *cell_nodes, const double *period,
+                       HostMesh &out, std::string &err);
+
+int host_threads();
+
+}  // namespace hgks

@@ -1,0 +1,55 @@
+// Kernel-side descriptors and launch wrappers (host interface of kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace hgks {
+
+// One problem's device arrays and constants; kernels read it from a table so
+// that one launch can cover the tiles of many problems (continuous batching).
+struct ProbDesc {
+    int32_t nc, nf;
+    int32_t n_cell_tiles, pad0;
+    const int32_t *sten;
+    const double *pinv0;
+    const double *pinvs;
+    const double *cgeo;
+    const int32_t *cface;
+    const int32_t *fcell;
+    const double *fgeo;
+    double *Q;          // state Q^n [5][nc]
+    double *Qs;         // stage state Q* [5][nc]
+    double *R;          // Q^n + dt L^n + dt^2/6 dL^n [5][nc]
+    double *C;          // FP64 reconstruction [50][nc]
+    float *C32;         // FP32 reconstruction deviation [50][nc]
+    double *FF;         // face fluxes [10][nf]
+    double *acc;        // coloured accumulation [10][nc]
+    double *dtpart;     // per cell tile minimum of h/(|U|+c)
+    double *dt;         // [0] dt of the current step
+    double *time;       // [0] simulated time
+    int32_t *flag;      // [0] non-physical state seen
+    double gamma, K, weno_eps, gamma_lin, cfl, tau_eps, tau_C;
+    int32_t tau_mode, mixed;
+};
+
+struct Tile {
+    int32_t prob;   // index into the problem table
+    int32_t begin;  // first cell / face of the tile
+    int32_t local;  // tile index within its problem (cell tiles: dtpart slot)
+    int32_t end;    // one past the last cell / face of the tile
+};
+
+constexpr int WENO_TILE = 64;    // cells per WENO workgroup (5 waves: one per variable)
+constexpr int UPD_TILE = 64;     // cells per update / dt workgroup
+
+void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s);
+void launch_flux(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0, bool coloured,
+                 hipStream_t s);
+void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, hipStream_t s);
+void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, hipStream_t s);
+void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s);
+void launch_fill(double *p, double v, int64_t n, hipStream_t s);
+
+}  // namespace hgks

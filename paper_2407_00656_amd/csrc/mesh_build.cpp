@@ -1,0 +1,587 @@
+// Host precompute of everything the GPU step needs for a tetrahedral mesh
+// (Sec. 3.1 "Generation of geometric information" and Algorithm 1), laid out
+// for the gfx950 kernels.  Runs once per mesh on the host, multithreaded.
+//
+//  1. unwrap every cell around its first node (periodic axes), volume, centroid,
+//     central second moments by the vertex formula
+//        int_T (x-c)_a (x-c)_b dV = |T|/20 sum_q (v_q-c)_a (v_q-c)_b;
+//  2. faces: cell faces bucketed by their smallest node id and matched on the
+//     other two (face p of a cell is opposite its node p, Sec. 3.1 item 1);
+//  3. first-layer neighbours with integer periodic image shifts, then the
+//     16-slot two-layer stencil (Algorithm 1; the paper's tetrahedral
+//     sub-stencils of Sec. 2.3 then sit at fixed slots);
+//  4. least-squares rows of each stencil member in the cell's scaled, centred
+//     coordinates and their pseudo-inverses by Householder QR (Sec. 2.3:
+//     constraints (1/|Omega_k|) int P = Q_k, solved in the least-squares sense);
+//  5. Morton renumbering of the cells, faces ordered by left cell, Gauss points.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <thread>
+
+#include "hgks_internal.h"
+
+namespace hgks {
+
+int host_threads() {
+    int n = 0;
+    if (const char *e = std::getenv("OMP_NUM_THREADS")) n = std::atoi(e);
+    if (n <= 0) n = (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(n, 32));
+}
+
+template <class F>
+static void parallel_for(int64_t n, F &&f) {
+    int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n / 2048));
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t) {
+        int64_t b = n * t / nt, e = n * (t + 1) / nt;
+        th.emplace_back([&f, b, e] { f(b, e); });
+    }
+    for (auto &x : th) x.join();
+}
+
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+struct Member {            // a stencil member: cell id and integer periodic image shift
+    int32_t cell;
+    int8_t s[3];
+    bool operator==(const Member &o) const {
+        return cell == o.cell && s[0] == o.s[0] && s[1] == o.s[1] && s[2] == o.s[2];
+    }
+};
+
+// Quadratic basis order: xx, yy, zz, xy, xz, yz (indices into a symmetric 3x3)
+constexpr int QA[6] = {0, 1, 2, 0, 0, 1};
+constexpr int QB[6] = {0, 1, 2, 1, 2, 2};
+
+// Pseudo-inverse of a full-column-rank m x n matrix (row-major) by Householder QR:
+// P (n x m, row-major) = R^{-1} Q^T.  Returns false when a diagonal of R is
+// negligible against the largest (rank deficiency).
+bool pinv_qr(int m, int n, const double *A, double *P) {
+    double R[16 * 9], V[9][16], beta[9];
+    std::memcpy(R, A, sizeof(double) * m * n);
+    double rmax = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double nrm = 0.0;
+        for (int i = j; i < m; ++i) nrm += R[i * n + j] * R[i * n + j];
+        nrm = std::sqrt(nrm);
+        double alpha = R[j * n + j] >= 0 ? -nrm : nrm;
+        for (int i = 0; i < m; ++i) V[j][i] = i < j ? 0.0 : R[i * n + j];
+        V[j][j] -= alpha;
+        double vv = 0.0;
+        for (int i = j; i < m; ++i) vv += V[j][i] * V[j][i];
+        beta[j] = vv > 0.0 ? 2.0 / vv : 0.0;
+        for (int c = j; c < n; ++c) {
+            double s = 0.0;
+            for (int i = j; i < m; ++i) s += V[j][i] * R[i * n + c];
+            s *= beta[j];
+            for (int i = j; i < m; ++i) R[i * n + c] -= s * V[j][i];
+        }
+        rmax = std::max(rmax, std::fabs(R[j * n + j]));
+    }
+    for (int j = 0; j < n; ++j)
+        if (!(std::fabs(R[j * n + j]) > 1e-9 * rmax)) return false;
+    for (int k = 0; k < m; ++k) {
+        double y[16];
+        for (int i = 0; i < m; ++i) y[i] = i == k ? 1.0 : 0.0;
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int i = j; i < m; ++i) s += V[j][i] * y[i];
+            s *= beta[j];
+            for (int i = j; i < m; ++i) y[i] -= s * V[j][i];
+        }
+        for (int r = n - 1; r >= 0; --r) {
+            double s = y[r];
+            for (int c = r + 1; c < n; ++c) s -= R[r * n + c] * P[c * m + k];
+            P[r * m + k] = s / R[r * n + r];
+        }
+    }
+    return true;
+}
+
+uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+}  // namespace
+
+hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, int64_t nc, int npc,
+                       const int64_t *cn, const double *period_in, HostMesh &out, std::string &err) {
+    if (nn <= 0 || nc <= 0 || !xyz || !cn) {
+        err = "empty mesh";
+        return HGKS_E_INVALID_ARG;
+    }
+    if (npc != 4) {
+        err = "only tetrahedral cells (nodes_per_cell = 4) are supported";
+        return HGKS_E_INVALID_ARG;
+    }
+    if (nc >= (int64_t)1 << 30) {
+        err = "too many cells";
+        return HGKS_E_INVALID_ARG;
+    }
+    double per[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        per[a] = period_in ? period_in[a] : 0.0;
+        if (!(per[a] >= 0.0) || !std::isfinite(per[a])) {
+            err = "bad period";
+            return HGKS_E_INVALID_ARG;
+        }
+    }
+    for (int64_t k = 0; k < nc * 4; ++k)
+        if (cn[k] < 0 || cn[k] >= nn) {
+            err = "node id out of range";
+            return HGKS_E_INVALID_ARG;
+        }
+
+    // ---- 1. unwrapped vertices, volume, centroid, central second moments --------
+    std::vector<std::array<V3, 4>> vert(nc);
+    std::vector<V3> cen(nc);
+    std::vector<double> vol(nc);
+    std::vector<std::array<double, 6>> smom(nc);  // central second moments (xx,yy,zz,xy,xz,yz)
+    std::atomic<int> bad{0};
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        for (int64_t c = b; c < e; ++c) {
+            const double *x0 = xyz + 3 * cn[4 * c];
+            for (int q = 0; q < 4; ++q) {
+                const double *xq = xyz + 3 * cn[4 * c + q];
+                double d[3];
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = xq[a] - x0[a];
+                    if (per[a] > 0) d[a] -= per[a] * std::nearbyint(d[a] / per[a]);
+                }
+                vert[c][q] = {x0[0] + d[0], x0[1] + d[1], x0[2] + d[2]};
+            }
+            V3 e1 = vert[c][1] - vert[c][0], e2 = vert[c][2] - vert[c][0], e3 = vert[c][3] - vert[c][0];
+            double v6 = std::fabs(dot(e1, cross(e2, e3)));
+            double ext = std::max({std::fabs(e1.x) + std::fabs(e2.x) + std::fabs(e3.x),
+                                   std::fabs(e1.y) + std::fabs(e2.y) + std::fabs(e3.y),
+                                   std::fabs(e1.z) + std::fabs(e2.z) + std::fabs(e3.z)});
+            if (!(v6 > 6e-12 * ext * ext * ext)) bad = 1;
+            vol[c] = v6 / 6.0;
+            cen[c] = 0.25 * (vert[c][0] + vert[c][1] + vert[c][2] + vert[c][3]);
+            for (int d = 0; d < 6; ++d) {
+                double s = 0.0;
+                for (int q = 0; q < 4; ++q) {
+                    V3 w = vert[c][q] - cen[c];
+                    s += comp(w, QA[d]) * comp(w, QB[d]);
+                }
+                smom[c][d] = s / 20.0;
+            }
+        }
+    });
+    if (bad) {
+        err = "degenerate tetrahedron";
+        return HGKS_E_BAD_MESH;
+    }
+
+    // ---- 2. faces: bucket every cell face by its smallest node ------------------
+    std::vector<int64_t> bstart(nn + 1, 0);
+    auto face_nodes = [&](int64_t c, int p, int64_t k[3]) {
+        int t = 0;
+        for (int q = 0; q < 4; ++q)
+            if (q != p) k[t++] = cn[4 * c + q];
+        std::sort(k, k + 3);
+    };
+    for (int64_t c = 0; c < nc; ++c)
+        for (int p = 0; p < 4; ++p) {
+            int64_t k[3];
+            face_nodes(c, p, k);
+            bstart[k[0] + 1]++;
+        }
+    for (int64_t i = 0; i < nn; ++i) bstart[i + 1] += bstart[i];
+    std::vector<int64_t> bfill(bstart.begin(), bstart.end() - 1);
+    std::vector<int64_t> bent(nc * 4);  // entries: c*4+p
+    for (int64_t c = 0; c < nc; ++c)
+        for (int p = 0; p < 4; ++p) {
+            int64_t k[3];
+            face_nodes(c, p, k);
+            bent[bfill[k[0]]++] = c * 4 + p;
+        }
+    std::vector<int64_t> partner(nc * 4, -1);  // (c*4+p) -> (c'*4+p')
+    parallel_for(nn, [&](int64_t b, int64_t e) {
+        std::vector<std::pair<std::pair<int64_t, int64_t>, int64_t>> buf;
+        for (int64_t node = b; node < e; ++node) {
+            buf.clear();
+            for (int64_t s = bstart[node]; s < bstart[node + 1]; ++s) {
+                int64_t cp = bent[s], k[3];
+                face_nodes(cp / 4, (int)(cp % 4), k);
+                buf.push_back({{k[1], k[2]}, cp});
+            }
+            std::sort(buf.begin(), buf.end());
+            for (size_t s = 0; s < buf.size();) {
+                size_t t = s + 1;
+                while (t < buf.size() && buf[t].first == buf[s].first) ++t;
+                if (t - s != 2) {
+                    bad = t - s == 1 ? 1 : 2;
+                } else {
+                    partner[buf[s].second] = buf[s + 1].second;
+                    partner[buf[s + 1].second] = buf[s].second;
+                }
+                s = t;
+            }
+        }
+    });
+    if (bad) {
+        err = bad == 1 ? "boundary face (every face must be shared by two cells)" : "non-conforming face";
+        return HGKS_E_BAD_MESH;
+    }
+
+    // ---- 3. neighbours with integer image shifts --------------------------------
+    // nb[c][p] = cell across face p; nsh[c][p] = shift k such that that cell's
+    // coordinates + k*period are in c's frame.
+    std::vector<std::array<int32_t, 4>> nb(nc);
+    std::vector<std::array<std::array<int8_t, 3>, 4>> nsh(nc);
+    std::vector<double> asum(nc, 0.0);
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        for (int64_t c = b; c < e; ++c) {
+            double as = 0.0;
+            for (int p = 0; p < 4; ++p) {
+                int64_t o = partner[c * 4 + p];
+                int64_t c2 = o / 4;
+                nb[c][p] = (int32_t)c2;
+                int q0 = p == 0 ? 1 : 0;
+                int64_t node = cn[4 * c + q0];
+                int q2 = 0;
+                while (cn[4 * c2 + q2] != node) ++q2;
+                V3 d = vert[c][q0] - vert[c2][q2];
+                for (int a = 0; a < 3; ++a) {
+                    double k = per[a] > 0 ? std::nearbyint(comp(d, a) / per[a]) : 0.0;
+                    nsh[c][p][a] = (int8_t)k;
+                }
+                V3 t0 = vert[c][(p + 1) % 4], t1 = vert[c][(p + 2) % 4], t2 = vert[c][(p + 3) % 4];
+                as += 0.5 * std::sqrt(dot(cross(t1 - t0, t2 - t0), cross(t1 - t0, t2 - t0)));
+            }
+            asum[c] = as;
+        }
+    });
+
+    // ---- 4. stencils and pseudo-inverses ----------------------------------------
+    // 16 slots per cell (caller numbering for now)
+    std::vector<std::array<Member, SLOTS>> slot(nc);
+    std::vector<double> P0(nc * 9 * SLOTS), PS(nc * 72);
+    std::atomic<int> members_max{0}, members_min{1 << 30}, dups{0};
+    std::mutex mu;
+    double resid_max = 0.0;
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        double local_resid = 0.0;
+        int lmax = 0, lmin = 1 << 30, ldup = 0;
+        for (int64_t i = b; i < e; ++i) {
+            auto &S = slot[i];
+            for (int p = 0; p < 4; ++p) S[p] = {nb[i][p], {nsh[i][p][0], nsh[i][p][1], nsh[i][p][2]}};
+            for (int m = 0; m < 4; ++m) {
+                int32_t j = nb[i][m];
+                int t = 0;
+                for (int q = 0; q < 4; ++q) {
+                    Member x{nb[j][q], {(int8_t)(nsh[i][m][0] + nsh[j][q][0]), (int8_t)(nsh[i][m][1] + nsh[j][q][1]),
+                                        (int8_t)(nsh[i][m][2] + nsh[j][q][2])}};
+                    if (x.cell == i && x.s[0] == 0 && x.s[1] == 0 && x.s[2] == 0) continue;
+                    if (t < 3) S[4 + 3 * m + t] = x;
+                    ++t;
+                }
+                if (t != 3) bad = 3;
+            }
+            // least-squares rows in the scaled coordinates xi = (x - c_i)/h_i
+            const double h = std::cbrt(vol[i]);
+            auto row = [&](const Member &x, double r[9]) {
+                V3 sh = {x.s[0] * per[0], x.s[1] * per[1], x.s[2] * per[2]};
+                V3 d = cen[x.cell] + sh - cen[i];
+                r[0] = d.x / h;
+                r[1] = d.y / h;
+                r[2] = d.z / h;
+                for (int q = 0; q < 6; ++q)
+                    r[3 + q] = (smom[x.cell][q] + comp(d, QA[q]) * comp(d, QB[q]) - smom[i][q]) / (h * h);
+            };
+            // distinct members of the big stencil (self excluded by construction)
+            int first[SLOTS], nm = 0;
+            double A[SLOTS * 9];
+            Member uniq[SLOTS];
+            for (int s = 0; s < SLOTS; ++s) {
+                first[s] = -1;
+                for (int u = 0; u < nm; ++u)
+                    if (uniq[u] == S[s]) first[s] = -2 - u;
+                if (first[s] == -1) {
+                    uniq[nm] = S[s];
+                    row(S[s], &A[nm * 9]);
+                    first[s] = nm++;
+                } else {
+                    ++ldup;
+                }
+            }
+            lmax = std::max(lmax, nm);
+            lmin = std::min(lmin, nm);
+            double Pk[9 * SLOTS];
+            if (!pinv_qr(nm, 9, A, Pk)) {
+                bad = 4;
+                continue;
+            }
+            // residual |P A - I|
+            for (int r = 0; r < 9; ++r)
+                for (int c = 0; c < 9; ++c) {
+                    double s = 0.0;
+                    for (int k = 0; k < nm; ++k) s += Pk[r * nm + k] * A[k * 9 + c];
+                    local_resid = std::max(local_resid, std::fabs(s - (r == c ? 1.0 : 0.0)));
+                }
+            for (int r = 0; r < 9; ++r)
+                for (int s = 0; s < SLOTS; ++s) P0[(i * 9 + r) * SLOTS + s] = first[s] >= 0 ? Pk[r * nm + first[s]] : 0.0;
+            // the four linear sub-stencil fits (first-layer minus one, plus N(i_m))
+            for (int m = 0; m < 4; ++m) {
+                int sl[6] = {SUBFIRST[m][0], SUBFIRST[m][1], SUBFIRST[m][2], 4 + 3 * m, 5 + 3 * m, 6 + 3 * m};
+                double As[6 * 3], Ps[3 * 6];
+                int fs[6], ns = 0;
+                Member us[6];
+                for (int t = 0; t < 6; ++t) {
+                    fs[t] = -1;
+                    for (int u = 0; u < ns; ++u)
+                        if (us[u] == S[sl[t]]) fs[t] = -2;
+                    if (fs[t] == -1) {
+                        us[ns] = S[sl[t]];
+                        double r[9];
+                        row(S[sl[t]], r);
+                        As[ns * 3 + 0] = r[0];
+                        As[ns * 3 + 1] = r[1];
+                        As[ns * 3 + 2] = r[2];
+                        fs[t] = ns++;
+                    }
+                }
+                if (ns < 3 || !pinv_qr(ns, 3, As, Ps)) {
+                    bad = 4;
+                    continue;
+                }
+                for (int k = 0; k < 3; ++k)
+                    for (int t = 0; t < 6; ++t) PS[i * 72 + (m * 3 + k) * 6 + t] = fs[t] >= 0 ? Ps[k * ns + fs[t]] : 0.0;
+            }
+        }
+        std::lock_guard<std::mutex> g(mu);
+        resid_max = std::max(resid_max, local_resid);
+        members_max = std::max(members_max.load(), lmax);
+        members_min = std::min(members_min.load(), lmin);
+        dups += ldup;
+    });
+    if (bad == 3) {
+        err = "a neighbour does not have three other neighbours";
+        return HGKS_E_BAD_MESH;
+    }
+    if (bad == 4) {
+        err = "rank-deficient least-squares stencil";
+        return HGKS_E_BAD_MESH;
+    }
+
+    // ---- 5. renumbering ---------------------------------------------------------
+    std::vector<int64_t> perm(nc);
+    for (int64_t c = 0; c < nc; ++c) perm[c] = c;
+    if (prm.reorder) {
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = 1e300;
+            hi[a] = -1e300;
+        }
+        for (int64_t c = 0; c < nc; ++c)
+            for (int a = 0; a < 3; ++a) {
+                double x = comp(cen[c], a);
+                if (per[a] > 0) x -= per[a] * std::floor(x / per[a]);
+                lo[a] = std::min(lo[a], x);
+                hi[a] = std::max(hi[a], x);
+            }
+        std::vector<std::pair<uint64_t, int64_t>> key(nc);
+        parallel_for(nc, [&](int64_t b, int64_t e) {
+            for (int64_t c = b; c < e; ++c) {
+                uint64_t code = 0;
+                for (int a = 0; a < 3; ++a) {
+                    double x = comp(cen[c], a);
+                    if (per[a] > 0) x -= per[a] * std::floor(x / per[a]);
+                    double t = hi[a] > lo[a] ? (x - lo[a]) / (hi[a] - lo[a]) : 0.0;
+                    uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+                    code |= spread3(q) << a;
+                }
+                key[c] = {code, c};
+            }
+        });
+        std::sort(key.begin(), key.end());
+        for (int64_t c = 0; c < nc; ++c) perm[c] = key[c].second;
+    }
+    std::vector<int32_t> inv(nc);
+    for (int64_t c = 0; c < nc; ++c) inv[perm[c]] = (int32_t)c;
+
+    // ---- 6. faces in internal numbering: left = smaller internal id -------------
+    // counting sort by left cell, then by right cell
+    const int64_t nf = 2 * nc;
+    std::vector<int64_t> fstart(nc + 1, 0);
+    for (int64_t c = 0; c < nc; ++c)
+        for (int p = 0; p < 4; ++p) {
+            int64_t c2 = nb[c][p];
+            if (inv[c] < inv[c2]) fstart[inv[c] + 1]++;
+        }
+    for (int64_t c = 0; c < nc; ++c) fstart[c + 1] += fstart[c];
+    if (fstart[nc] != nf) {
+        err = "face count mismatch";
+        return HGKS_E_BAD_MESH;
+    }
+    struct FaceRec {
+        int32_t l, r;      // internal ids
+        int32_t cl;        // caller id of the left cell
+        int8_t pl;         // local face index in the left cell
+    };
+    std::vector<FaceRec> faces(nf);
+    {
+        std::vector<int64_t> fill(fstart.begin(), fstart.end() - 1);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int p = 0; p < 4; ++p) {
+                int64_t c2 = nb[c][p];
+                if (inv[c] < inv[c2]) faces[fill[inv[c]]++] = {inv[c], inv[c2], (int32_t)c, (int8_t)p};
+            }
+        parallel_for(nc, [&](int64_t b, int64_t e) {
+            for (int64_t c = b; c < e; ++c)
+                std::sort(faces.begin() + fstart[c], faces.begin() + fstart[c + 1],
+                          [](const FaceRec &x, const FaceRec &y) { return x.r < y.r || (x.r == y.r && x.pl < y.pl); });
+        });
+    }
+    // colour classes: no two faces of a class share a cell (greedy over the face order)
+    std::vector<int8_t> colour(nf, 0);
+    int ncol = 1;
+    {
+        std::vector<uint32_t> used(nc, 0);
+        for (int64_t f = 0; f < nf; ++f) {
+            uint32_t m = used[faces[f].l] | used[faces[f].r];
+            int k = 0;
+            while (m & (1u << k)) ++k;
+            colour[f] = (int8_t)k;
+            used[faces[f].l] |= 1u << k;
+            used[faces[f].r] |= 1u << k;
+            ncol = std::max(ncol, k + 1);
+        }
+    }
+    std::vector<int64_t> forder(nf);
+    for (int64_t f = 0; f < nf; ++f) forder[f] = f;
+    out.colour_offsets.assign(ncol + 1, 0);
+    if (prm.accumulation == HGKS_ACC_COLOURED) {
+        std::stable_sort(forder.begin(), forder.end(), [&](int64_t a, int64_t b) { return colour[a] < colour[b]; });
+    }
+    for (int64_t f = 0; f < nf; ++f) out.colour_offsets[colour[f] + 1]++;
+    for (int k = 0; k < ncol; ++k) out.colour_offsets[k + 1] += out.colour_offsets[k];
+
+    // ---- 7. pack device arrays --------------------------------------------------
+    out.nc = nc;
+    out.nf = nf;
+    out.perm = perm;
+    out.sten.assign((size_t)SLOTS * nc, 0);
+    out.pinv0.assign((size_t)144 * nc, 0.0);
+    out.pinvs.assign((size_t)72 * nc, 0.0);
+    out.cgeo.assign((size_t)CGEO * nc, 0.0);
+    out.cface.assign((size_t)4 * nc, 0);
+    out.fcell.assign((size_t)2 * nf, 0);
+    out.fgeo.assign((size_t)FGEO * nf, 0.0);
+    std::vector<int32_t> fpos(nf);
+    for (int64_t k = 0; k < nf; ++k) fpos[forder[k]] = (int32_t)k;
+    double closure = 0.0;
+    std::vector<double> cl_acc(3 * (size_t)nc, 0.0);
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        for (int64_t c = b; c < e; ++c) {
+            int64_t o = perm[c];
+            for (int s = 0; s < SLOTS; ++s) out.sten[(size_t)s * nc + c] = inv[slot[o][s].cell];
+            for (int r = 0; r < 9; ++r)
+                for (int s = 0; s < SLOTS; ++s)
+                    out.pinv0[(((size_t)(r * 8 + s / 2)) * nc + c) * 2 + (s & 1)] = P0[(o * 9 + r) * SLOTS + s];
+            for (int e2 = 0; e2 < 72; ++e2) out.pinvs[(((size_t)(e2 / 2)) * nc + c) * 2 + (e2 & 1)] = PS[o * 72 + e2];
+            double h = std::cbrt(vol[o]);
+            out.cgeo[0 * (size_t)nc + c] = 1.0 / h;
+            for (int q = 0; q < 6; ++q) out.cgeo[(size_t)(1 + q) * nc + c] = smom[o][q] / (h * h);
+            out.cgeo[7 * (size_t)nc + c] = 1.0 / vol[o];
+            out.cgeo[8 * (size_t)nc + c] = 6.0 * vol[o] / asum[o];
+        }
+    });
+    // faces
+    std::vector<int8_t> cfill(nc, 0);
+    for (int64_t k = 0; k < nf; ++k) {
+        const FaceRec &F = faces[forder[k]];
+        out.fcell[k] = F.l;
+        out.fcell[nf + k] = F.r;
+        out.cface[(size_t)cfill[F.l]++ * nc + F.l] = (int32_t)(k << 1);
+        out.cface[(size_t)cfill[F.r]++ * nc + F.r] = (int32_t)((k << 1) | 1);
+    }
+    parallel_for(nf, [&](int64_t b, int64_t e) {
+        for (int64_t k = b; k < e; ++k) {
+            const FaceRec &F = faces[forder[k]];
+            int64_t lo = F.cl;       // caller id of the left cell
+            int p = F.pl;
+            int64_t ro = nb[lo][p];
+            V3 tri[3];
+            int t = 0;
+            for (int q = 0; q < 4; ++q)
+                if (q != p) tri[t++] = vert[lo][q];
+            V3 nrm = cross(tri[1] - tri[0], tri[2] - tri[0]);
+            double len = std::sqrt(dot(nrm, nrm));
+            nrm = (1.0 / len) * nrm;
+            V3 fc = (1.0 / 3.0) * (tri[0] + tri[1] + tri[2]);
+            if (dot(nrm, fc - cen[lo]) < 0) nrm = -1.0 * nrm;
+            V3 shift = {nsh[lo][p][0] * per[0], nsh[lo][p][1] * per[1], nsh[lo][p][2] * per[2]};
+            V3 cr = cen[ro] + shift;   // right centroid in the left frame
+            if (!(dot(nrm, cr - fc) > 0.0)) bad = 5;   // both cells on one side: overlapping / folded
+            double *g = &out.fgeo[0];
+            g[0 * (size_t)nf + k] = nrm.x;
+            g[1 * (size_t)nf + k] = nrm.y;
+            g[2 * (size_t)nf + k] = nrm.z;
+            g[3 * (size_t)nf + k] = 0.5 * len;
+            for (int q = 0; q < 3; ++q) {
+                // 3-point degree-2 rule: barycentric permutations of (2/3, 1/6, 1/6)
+                V3 xg = (2.0 / 3.0) * tri[q] + (1.0 / 6.0) * (tri[(q + 1) % 3] + tri[(q + 2) % 3]);
+                V3 yl = xg - cen[lo], yr = xg - cr;
+                for (int a = 0; a < 3; ++a) {
+                    g[(size_t)(4 + 3 * q + a) * nf + k] = comp(yl, a);
+                    g[(size_t)(13 + 3 * q + a) * nf + k] = comp(yr, a);
+                }
+            }
+        }
+    });
+    if (bad == 5) {
+        err = "overlapping or folded cells (a face does not separate its two cells)";
+        return HGKS_E_BAD_MESH;
+    }
+    for (int64_t k = 0; k < nf; ++k) {
+        double S = out.fgeo[3 * (size_t)nf + k];
+        for (int a = 0; a < 3; ++a) {
+            double v = out.fgeo[(size_t)a * nf + k] * S;
+            cl_acc[3 * (size_t)out.fcell[k] + a] += v;
+            cl_acc[3 * (size_t)out.fcell[nf + k] + a] -= v;
+        }
+    }
+    for (double v : cl_acc) closure = std::max(closure, std::fabs(v));
+    for (int64_t c = 0; c < nc; ++c)
+        if (cfill[c] != 4) {
+            err = "cell without four faces";
+            return HGKS_E_BAD_MESH;
+        }
+    out.max_members = members_max;
+    out.min_members = members_min;
+    out.dup_slots = dups;
+    out.pinv_residual = resid_max;
+    out.closure = closure;
+    return HGKS_OK;
+}
+
+}  // namespace hgks

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (per conserved variable, normalised as in helpers.scaled_err):
+  FP64 path      <= 1e-12 after one step from an identical state;
+  FP32-mixed     <= 1e-5 relative L1 after the full run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2407_00656_amd import hgks
+from paper_2407_00656_amd import workloads as W
+from tests.helpers import advection_case, rel_l1, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_solver(mesh, q, **kw):
+    s = hgks.Solver(hgks.params(**kw))
+    s.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period)
+    s.init_state(q)
+    return s
+
+
+def oracle_params(**kw):
+    keep = {k: v for k, v in kw.items() if k in ("tau_mode", "tau_eps", "tau_C", "weno_eps", "gamma_lin", "cfl")}
+    return O.default_params(**keep)
+
+
+def per_step_parity(mesh, q0, nsteps, **kw):
+    om = O.Mesh.from_workload(mesh)
+    op = oracle_params(**kw)
+    s = make_solver(mesh, q0, **kw)
+    worst = np.zeros(5)
+    q = q0
+    for k in range(nsteps):
+        dt_gpu = s.step(1, want_dt=True)
+        q_gpu, _ = s.get_state()
+        q_orc, dt_orc = om.step(q, 1, params=op)
+        assert abs(dt_gpu - dt_orc) <= 1e-14 * dt_orc, (k, dt_gpu, dt_orc)
+        e = scaled_err(q_gpu, q_orc)
+        worst = np.maximum(worst, e)
+        assert np.all(e <= TOL64), (k, e)
+        q = q_gpu                    # next step starts from the same state on both sides
+    s.close()
+    return worst
+
+
+def test_fp64_config1_every_step():
+    """The accuracy-test box: 6*8^3 jittered tets, 20 CFL-0.3 steps, each step matched."""
+    say("case: fp64 N=8 20 steps")
+    mesh, case, q0 = advection_case(8)
+    worst = per_step_parity(mesh, q0, 20)
+    say("worst scaled error", worst)
+
+
+@pytest.mark.parametrize("n,seed", [(5, 101), (7, 102), (6, 103)])
+def test_fp64_odd_and_ragged_sizes(n, seed):
+    """6 n^3 cells with n odd / not a multiple of the tile sizes (ragged last tiles)."""
+    say(f"case: fp64 ragged N={n} seed={seed}")
+    mesh, case, q0 = advection_case(n, seed=seed, k=(1, 2, 1), vel=(0.8, -0.3, 0.5), amp=0.15)
+    assert mesh.n_cells % 64 != 0
+    per_step_parity(mesh, q0, 2)
+
+
+def test_fp64_tau_positive_branch():
+    say("case: fp64 tau_mode=1 N=6")
+    mesh, case, q0 = advection_case(6, seed=104, amp=0.2, vel=(1.0, 0.2, -0.4))
+    per_step_parity(mesh, q0, 2, tau_mode=1, tau_eps=0.05, tau_C=1.0)
+
+
+def test_fp64_coloured_accumulation():
+    say("case: fp64 coloured accumulation N=6, N=8")
+    for n in (6, 8):
+        mesh, case, q0 = advection_case(n, seed=105 + n)
+        per_step_parity(mesh, q0, 2, accumulation=hgks.ACC_COLOURED)
+
+
+def test_fp32_mixed_config1_full_run():
+    say("case: fp32-mixed N=8 20 steps vs oracle")
+    mesh, case, q0 = advection_case(8)
+    om = O.Mesh.from_workload(mesh)
+    vol = om.cells()[0]
+    q_orc, _ = om.step(q0, 20)
+    s = make_solver(mesh, q0, precision=hgks.FP32_MIXED)
+    s.step(20)
+    q32, _ = s.get_state()
+    err = rel_l1(q32, q_orc, vol)
+    say("relative L1 (fp32-mixed vs fp64 oracle)", err)
+    assert np.all(err <= TOL32), err
+
+
+def test_bitwise_determinism_and_restart():
+    say("case: determinism + checkpoint/restart N=6")
+    mesh, case, q0 = advection_case(6, seed=110, vel=(0.5, 1.0, -0.2))
+    for prec in (hgks.FP64, hgks.FP32_MIXED):
+        a = make_solver(mesh, q0, precision=prec)
+        a.step(6)
+        qa, ta = a.get_state()
+        b = make_solver(mesh, q0, precision=prec)
+        b.step(6)
+        qb, tb = b.get_state()
+        assert np.array_equal(qa, qb) and ta == tb
+        c = make_solver(mesh, q0, precision=prec)
+        c.step(3)
+        qm, tm = c.get_state()
+        d = make_solver(mesh, qm, precision=prec)
+        d.init_state(qm, tm)
+        d.step(3)
+        qd, td = d.get_state()
+        assert np.array_equal(qd, qa) and abs(td - ta) <= 1e-15 * ta
+        for x in (a, b, c, d):
+            x.close()
+
+
+def test_free_stream_and_conservation_on_gpu():
+    say("case: free stream + conservation N=8")
+    mesh = W.kuhn_box(8, seed=111)
+    vol = W.tet_volumes(mesh.cell_vertices)
+    qu = W.uniform_state(mesh.n_cells, rho=1.2, vel=(0.4, -0.9, 0.3), p=0.8)
+    for prec in (hgks.FP64, hgks.FP32_MIXED):
+        s = make_solver(mesh, qu, precision=prec)
+        s.step(5)
+        q, _ = s.get_state()
+        tol = 1e-13 if prec == hgks.FP64 else 1e-6
+        assert np.abs(q - qu).max() <= tol * np.abs(qu).max(), prec
+        s.close()
+    q0 = W.AdvectionCase(k=(2, 1, 1), vel=(0.3, 0.9, -0.6)).conservative(mesh)
+    s = make_solver(mesh, q0)
+    s.step(5)
+    q, _ = s.get_state()
+    t0, t1 = (vol[:, None] * q0).sum(0), (vol[:, None] * q).sum(0)
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * np.abs(vol[:, None] * q0).sum(0))
+
+
+def test_error_paths():
+    say("case: error paths")
+    mesh, case, q0 = advection_case(5, seed=112)
+    s = hgks.Solver()
+    with pytest.raises(hgks.HGKSError) as e:
+        s.init_state(q0)
+    assert e.value.status == hgks.E_STATE
+    s.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period)
+    with pytest.raises(hgks.HGKSError) as e:
+        s.step(1)
+    assert e.value.status == hgks.E_STATE
+    bad = q0.copy()
+    bad[3, 0] = -1.0
+    with pytest.raises(hgks.HGKSError) as e:
+        s.init_state(bad)
+    assert e.value.status == hgks.E_NONPHYSICAL
+    s.init_state(q0)
+    s.step(1, dt_fixed=50.0)                 # far past stability: the state blows up
+    with pytest.raises(hgks.HGKSError) as e:
+        s.get_state()
+    assert e.value.status == hgks.E_NONPHYSICAL
+    s.init_state(q0)                          # a fresh state clears the flag
+    s.step(1)
+    s.get_state()
+    s.close()
+
+
+def test_pool_alone_vs_mix_bitwise():
+    """Continuous batching: each problem's result is bitwise the same alone and in a
+    mixed pooled launch (different sizes, precisions and collision-time modes)."""
+    say("case: pool alone vs mix")
+    cases = [(6, 120, dict()), (8, 121, dict(precision=hgks.FP32_MIXED)), (5, 122, dict(tau_mode=1)),
+             (7, 123, dict())]
+    alone, solvers = [], []
+    for n, seed, kw in cases:
+        mesh, case, q0 = advection_case(n, seed=seed, vel=(0.7, 0.1, -0.5))
+        s = make_solver(mesh, q0, **kw)
+        s.step(3)
+        alone.append(s.get_state()[0])
+        s.close()
+        solvers.append(make_solver(mesh, q0, **kw))
+    pool = hgks.Pool()
+    slots = [pool.add(s) for s in solvers]
+    pool.step(slots, 1)
+    pool.step(slots[::-1], 2)
+    for k, s in enumerate(solvers):
+        q, _ = s.get_state()
+        assert np.array_equal(q, alone[k]), k
+    used, n = pool.used()
+    assert n == 4 and used == sum(s.footprint() for s in solvers)
+    for sl in slots:
+        pool.remove(sl)
+    pool.close()
+    for s in solvers:
+        s.close()
+
+
+def test_pool_admission_budget():
+    say("case: pool budget")
+    mesh, case, q0 = advection_case(5, seed=124)
+    a = make_solver(mesh, q0)
+    b = make_solver(mesh, q0)
+    assert a.footprint() == hgks.pool_footprint(hgks.params(), mesh.n_cells)
+    pool = hgks.Pool(hbm_budget=a.footprint() + b.footprint() // 2)
+    pool.add(a)
+    with pytest.raises(hgks.HGKSError) as e:
+        pool.add(b)
+    assert e.value.status == hgks.E_OOM
+    pool.close()
+
+
+def test_full_size_config2_sampled_parity():
+    """6*64^3 = 1,572,864 tets in the launch configuration the benchmark times:
+    one GPU step against the oracle's step of 48 sampled cells, plus the CFL dt."""
+    say("case: fp64 N=64 sampled parity")
+    mesh, case, q0 = advection_case(64, seed=W.SEED_ADVECTION + 64)
+    s = make_solver(mesh, q0)
+    dt_gpu = s.step(1, want_dt=True)
+    q_gpu, _ = s.get_state()
+    s.close()
+    om = O.Mesh.from_workload(mesh)
+    dt_orc = om.cfl_dt(q0)
+    assert abs(dt_gpu - dt_orc) <= 1e-14 * dt_orc
+    rng = np.random.default_rng(64)
+    cells = np.concatenate([[0, mesh.n_cells - 1], rng.choice(mesh.n_cells, 46, replace=False)])
+    ref = om.step_sample(q0, dt_orc, cells)
+    e = scaled_err(q_gpu[cells], ref)
+    say("worst scaled error (sample)", e)
+    assert np.all(e <= TOL64), e
+
+
+def test_full_size_config2_fp32_mixed_vs_fp64():
+    """Config 2 in full: 100 steps at 6*64^3; FP32-mixed against the FP64 path,
+    whose every step matches the oracle."""
+    say("case: N=64 100 steps fp64 vs fp32-mixed")
+    mesh, case, q0 = advection_case(64, seed=W.SEED_ADVECTION + 64)
+    vol = W.tet_volumes(mesh.cell_vertices)
+    out = {}
+    for prec in (hgks.FP64, hgks.FP32_MIXED):
+        s = make_solver(mesh, q0, precision=prec)
+        s.step(100)
+        out[prec] = s.get_state()
+        s.close()
+    err = rel_l1(out[hgks.FP32_MIXED][0], out[hgks.FP64][0], vol)
+    say("relative L1 fp32-mixed vs fp64 after 100 steps", err)
+    assert np.all(err <= TOL32), err
+    assert out[hgks.FP32_MIXED][1] == pytest.approx(out[hgks.FP64][1], rel=1e-5)

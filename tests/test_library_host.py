@@ -1,0 +1,96 @@
+"""CPU-side checks of the HIP library: it loads, exports the whole C ABI, and its
+host mesh precompute agrees with the oracle's independent connectivity."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2407_00656_amd import hgks
+from paper_2407_00656_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "hgks.h")).read()
+    names = sorted(set(re.findall(r"^(?:const\s+)?\w+\s*\*?\s*(hgks_[a-z0-9_]+)\s*\(", header, re.M)))
+    assert len(names) >= 20
+    L = hgks.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_stencils_match_oracle_and_pinv_is_a_left_inverse():
+    m = W.kuhn_box(8)
+    r = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period)
+    st = r["stats"]
+    assert st["n_faces"] == 2 * m.n_cells
+    assert st["max_members"] == 14 and st["min_members"] == 14
+    assert st["pinv_residual"] < 1e-12
+    assert st["closure"] < 1e-14
+    perm = r["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(m.n_cells))
+    om = O.Mesh.from_workload(m)
+    nb = om.neighbors()
+    sten = r["sten"]
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(m.n_cells)
+    for c in range(0, m.n_cells, 5):
+        o = perm[c]
+        mem, _, subs = om.stencil(o)
+        slots = perm[sten[:, c]]
+        assert set(slots.tolist()) == set(mem.tolist())
+        # slots 0..3 are the face neighbours across faces opposite nodes 0..3
+        assert list(slots[:4]) == list(nb[o])
+        # sub-stencil m = three first-layer slots + slots 4+3m..6+3m
+        first = [[0, 1, 2], [0, 1, 3], [1, 2, 3], [2, 0, 3]]
+        for s in range(4):
+            lib_sub = set(slots[first[s]].tolist()) | set(slots[4 + 3 * s:7 + 3 * s].tolist())
+            assert lib_sub == set(subs[s].tolist())
+
+
+def test_renumbering_is_off_when_asked():
+    m = W.kuhn_box(6)
+    r = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period, hgks.params(reorder=0))
+    assert np.array_equal(r["perm"], np.arange(m.n_cells))
+
+
+def test_colouring_classes_share_no_cell():
+    m = W.kuhn_box(6)
+    r = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period, hgks.params(accumulation=hgks.ACC_COLOURED))
+    assert 4 <= r["stats"]["n_colours"] <= 7
+
+
+def test_bad_meshes_are_rejected():
+    m = W.kuhn_box(4)
+    cells = m.cell_nodes.copy()
+    cells[0, 3] = cells[0, 2]                          # repeated node: flat tetrahedron
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.inspect_mesh(m.nodes, cells, m.period)
+    assert e.value.status in (hgks.E_BAD_MESH,)
+    box = W.kuhn_box(4, periodic=(False, True, True))    # boundary faces on x = 0 and x = 2
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.inspect_mesh(box.nodes, box.cell_nodes, box.period)
+    assert e.value.status == hgks.E_BAD_MESH
+    with pytest.raises(hgks.HGKSError) as e:             # wrapped cells without their period
+        hgks.inspect_mesh(m.nodes, m.cell_nodes, (0.0, 0.0, 0.0))
+    assert e.value.status == hgks.E_BAD_MESH
+    with pytest.raises(hgks.HGKSError) as e:             # hexahedra are not supported
+        hgks.inspect_mesh(m.nodes, np.zeros((4, 8), dtype=np.int64), m.period)
+    assert e.value.status == hgks.E_INVALID_ARG
+    bad = m.cell_nodes.copy()
+    bad[5, 1] = m.n_nodes + 3
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.inspect_mesh(m.nodes, bad, m.period)
+    assert e.value.status == hgks.E_INVALID_ARG
+
+
+def test_oracle_sampled_step_equals_full_step():
+    m = W.kuhn_box(6, seed=3)
+    om = O.Mesh.from_workload(m)
+    q = W.AdvectionCase(k=(1, 2, 1), vel=(0.5, 1.0, 0.2)).conservative(m)
+    q1, dt = om.step(q, 1)
+    cells = np.array([0, 7, 333, m.n_cells - 1])
+    assert np.array_equal(om.step_sample(q, dt, cells), q1[cells])
