@@ -18,10 +18,11 @@
 //   fcell  int32  [2][nf]        left, right cell of each face (normal points left->right)
 //   fgeo   double [22][nf]       n(3), S, Gauss-point offsets from the left centroid
 //                                [3][3], offsets from the right centroid [3][3]
-//   C      double [50][nc]       reconstruction: per variable (c0, g(3), H(6)) of
+//   C      double [25][nc][2]    reconstruction: per variable (c0, g(3), H(6)) of
 //                                P(y) = c0 + g.y + H_xx y_x^2 + ... + H_yz y_y y_z,
-//                                y = x - centroid (FP32 in the mixed form, where c0
-//                                holds the deviation from the cell mean)
+//                                y = x - centroid, stored as five coefficient pairs
+//                                (k, k+1) per variable (FP32 pairs in the mixed form,
+//                                where c0 holds the deviation from the cell mean)
 //   FF     double [10][nf]       per face S * sum_G w_G (F, dF/dt)
 #pragma once
 

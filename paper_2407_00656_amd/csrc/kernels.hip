@@ -27,7 +27,46 @@
 #include "hgks_internal.h"
 #include "kernels.h"
 
+#ifndef HGKS_WENO_CELLS
+#define HGKS_WENO_CELLS 32
+#endif
+
 namespace hgks {
+
+// ----------------------------------------------------------------------------
+// memory helpers: global loads / stores with a wave-uniform 64-bit base (scalar
+// registers) and a 32-bit per-lane byte offset, so the compiler emits the
+// "vector offset + scalar base" form of global_load / global_store instead of
+// generic (flat) accesses with 64-bit per-lane address arithmetic.
+// ----------------------------------------------------------------------------
+struct alignas(16) d2 {
+    double x, y;
+};
+struct alignas(8) f2 {
+    float x, y;
+};
+
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ T ldg(const void *base, uint32_t off) {
+    return *(gptr<const T>)((gptr<const char>)base + off);
+}
+template <class T>
+__device__ __forceinline__ void stg(void *base, uint32_t off, const T &v) {
+    *(gptr<T>)((gptr<char>)base + off) = v;
+}
+#else
+template <class T>
+__device__ __forceinline__ T ldg(const void *base, uint32_t off) {
+    return *(const T *)((const char *)base + off);
+}
+template <class T>
+__device__ __forceinline__ void stg(void *base, uint32_t off, const T &v) {
+    *(T *)((char *)base + off) = v;
+}
+#endif
 
 // ----------------------------------------------------------------------------
 // precision helpers
@@ -40,6 +79,9 @@ __device__ __forceinline__ double hg_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float hg_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double hg_abs(double x) { return fabs(x); }
 __device__ __forceinline__ float hg_abs(float x) { return fabsf(x); }
+// reciprocal: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32
+__device__ __forceinline__ double hg_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float hg_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ----------------------------------------------------------------------------
 // WENO reconstruction
@@ -53,9 +95,11 @@ __device__ __forceinline__ T quad_form(const T M[6], T g0, T g1, T g2) {
     return M[0] * g0 * g0 + M[1] * g1 * g1 + M[2] * g2 * g2 + T(2) * (M[3] * g0 * g1 + M[4] * g0 * g2 + M[5] * g1 * g2);
 }
 
-template <class T, class OUT>
-__device__ __forceinline__ void weno_combine(const ProbDesc &P, int i, int nc, double qi, const double a64[9],
-                                             const double b64[4][3], OUT *C) {
+// Smoothness indicators, WENO-Z weights and the combined polynomial of one
+// variable of one cell, written as five coefficient pairs.
+template <class T, class PAIR>
+__device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint32_t nc, double qi, const double a64[9],
+                                             const double b64[4][3], PAIR *C, bool store) {
     // basis order: x, y, z, xx, yy, zz, xy, xz, yz (scaled coordinates xi = (x-c)/h)
     T a[9], b[4][3], M[6];
 #pragma unroll
@@ -65,7 +109,7 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, int i, int nc, d
 #pragma unroll
         for (int k = 0; k < 3; ++k) b[m][k] = (T)b64[m][k];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) M[q] = (T)P.cgeo[(size_t)(1 + q) * nc + i];
+    for (int q = 0; q < 6; ++q) M[q] = (T)ldg<double>(P.cgeo + (size_t)(1 + q) * nc, i * 8u);
     // smoothness indicators in scaled coordinates:
     //   beta_0 = sum_j mean((d_j P0)^2) + sum_{|l|=2} (d^l P0)^2,  beta_m = |grad P_m|^2
     // mean((a_j + g_j.xi)^2) = a_j^2 + g_j^T M g_j since the mean of xi is zero
@@ -91,7 +135,7 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, int i, int nc, d
 #pragma unroll
     for (int m = 0; m < 4; ++m) al[m] = w[1 + m] * inv - w[0] * inv * gl / g0;
     // combined polynomial in y = x - centroid
-    const T ih = (T)P.cgeo[i], ih2 = ih * ih;
+    const T ih = (T)ldg<double>(P.cgeo, i * 8u), ih2 = ih * ih;
     T c[10];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[1 + k] = (s0 * a[k] + al[0] * b[0][k] + al[1] * b[1][k] + al[2] * b[2][k] + al[3] * b[3][k]) * ih;
@@ -102,45 +146,92 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, int i, int nc, d
         dev -= cq * M[q];
         c[4 + q] = cq * ih2;
     }
-    if constexpr (sizeof(OUT) == 8)
+    if constexpr (sizeof(T) == 8)
         c[0] = (T)(qi + (double)dev);
     else
         c[0] = dev;  // FP32 form: deviation from the FP64 cell mean
+    if (!store) return;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) C[(size_t)k * nc + i] = (OUT)c[k];
+    for (int k = 0; k < 5; ++k) {
+        PAIR pr;
+        pr.x = c[2 * k];
+        pr.y = c[2 * k + 1];
+        stg<PAIR>(C + (size_t)k * nc, i * (uint32_t)sizeof(PAIR), pr);
+    }
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(5 * WENO_TILE) void k_weno(const ProbDesc *__restrict__ probs,
-                                                         const Tile *__restrict__ tiles, int stage) {
-    const Tile tl = tiles[blockIdx.x];
+// Pseudo-inverse pair rows: 72 of the big stencil (row r, slots 2s, 2s+1 at pair
+// r*8+s), then 36 of the sub-stencils.  A workgroup handles WC cells: all its
+// threads first copy the WC cells' 108 pair rows into LDS (every value is read
+// from HBM once), one barrier, then lane (v, c) forms variable v of cell c from
+// LDS.  Five variables x WC cells are spread over whole waves; spare lanes only
+// help with the copy.
+constexpr int WPAIRS0 = 72, WPAIRS = 108;
+
+template <int WC>
+constexpr int weno_threads() { return (5 * WC + 63) / 64 * 64; }
+
+template <bool MIXED, int WC>
+__global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__restrict__ probs,
+                                                              const Tile *__restrict__ tiles, int stage) {
+    constexpr int NT = weno_threads<WC>();
+    constexpr int SPLIT = WENO_TILE / WC;              // workgroups per cell tile
+    __shared__ d2 stage_buf[WPAIRS][WC];
+    const Tile tl = tiles[blockIdx.x / SPLIT];
     const ProbDesc &P = probs[tl.prob];
-    const int v = __builtin_amdgcn_readfirstlane(threadIdx.x / WENO_TILE);
-    const int i = tl.begin + (int)(threadIdx.x % WENO_TILE);
-    if (i >= tl.end) return;
-    const int nc = P.nc;
-    const double *__restrict__ Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)v * nc;
-    const double qi = Qv[i];
-    double d[SLOTS];
+    const uint32_t nc = (uint32_t)P.nc;
+    const uint32_t c0 = tl.begin + (blockIdx.x % SPLIT) * WC;   // first cell of this workgroup
+    const uint32_t last = (uint32_t)tl.end - 1;
+    const d2 *p0 = reinterpret_cast<const d2 *>(P.pinv0);
+    const d2 *ps = reinterpret_cast<const d2 *>(P.pinvs);
+    // 1. copy the pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the tile) into LDS
+    constexpr int PER = (WPAIRS * WC + NT - 1) / NT;
+    d2 reg[PER];
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) d[s] = Qv[P.sten[(size_t)s * nc + i]] - qi;
-    const double2 *__restrict__ p0 = reinterpret_cast<const double2 *>(P.pinv0);
-    const double2 *__restrict__ ps = reinterpret_cast<const double2 *>(P.pinvs);
-    // quadratic on the big stencil: a = Pinv0 (Q_k - Q_i)
-    double a[9];
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t e = threadIdx.x + k * NT;
+        if (e < (uint32_t)(WPAIRS * WC)) {
+            const uint32_t row = e / WC, c = min(c0 + e % WC, last);
+            const d2 *base = row < (uint32_t)WPAIRS0 ? p0 + (size_t)row * nc : ps + (size_t)(row - WPAIRS0) * nc;
+            reg[k] = ldg<d2>(base, c * 16u);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t e = threadIdx.x + k * NT;
+        if (e < (uint32_t)(WPAIRS * WC)) stage_buf[e / WC][e % WC] = reg[k];
+    }
+    // 2. this lane's variable and cell; gather the stencil differences meanwhile
+    const uint32_t v = threadIdx.x / WC, cl = threadIdx.x % WC;
+    const bool active = v < 5u;
+    const uint32_t i0 = c0 + cl;
+    const bool ok = active && i0 <= last;
+    const uint32_t i = min(i0, last);
+    const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)(active ? v : 0u) * nc;
+    double qi = 0.0, d[SLOTS];
+    if (active) {
+        qi = ldg<double>(Qv, i * 8u);
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const uint32_t j = (uint32_t)ldg<int32_t>(P.sten + (size_t)s * nc, i * 4u);
+            d[s] = ldg<double>(Qv, j * 8u) - qi;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    // 3. a = Pinv0 (Q_k - Q_i) on the big stencil; b^m = Pinv_m (Q_k - Q_i) on sub-stencil m
+    double a[9], b[4][3];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         double acc = 0.0;
 #pragma unroll
         for (int s2 = 0; s2 < SLOTS / 2; ++s2) {
-            const double2 pp = p0[(size_t)(r * 8 + s2) * nc + i];
+            const d2 pp = stage_buf[r * 8 + s2][cl];
             acc = fma(pp.x, d[2 * s2], acc);
             acc = fma(pp.y, d[2 * s2 + 1], acc);
         }
         a[r] = acc;
     }
-    // linear polynomials on the four sub-stencils
-    double b[4][3];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -148,16 +239,16 @@ __global__ __launch_bounds__(5 * WENO_TILE) void k_weno(const ProbDesc *__restri
             double acc = 0.0;
 #pragma unroll
             for (int t2 = 0; t2 < 3; ++t2) {
-                const double2 pp = ps[(size_t)((m * 3 + k) * 3 + t2) * nc + i];
+                const d2 pp = stage_buf[WPAIRS0 + (m * 3 + k) * 3 + t2][cl];
                 acc = fma(pp.x, d[sub_slot(m, 2 * t2)], acc);
                 acc = fma(pp.y, d[sub_slot(m, 2 * t2 + 1)], acc);
             }
             b[m][k] = acc;
         }
     if constexpr (MIXED)
-        weno_combine<float>(P, i, nc, qi, a, b, P.C32 + (size_t)v * NCOEF * nc);
+        weno_combine<float>(P, i, nc, qi, a, b, reinterpret_cast<f2 *>(P.C32) + (size_t)v * 5 * nc, ok);
     else
-        weno_combine<double>(P, i, nc, qi, a, b, P.C + (size_t)v * NCOEF * nc);
+        weno_combine<double>(P, i, nc, qi, a, b, reinterpret_cast<d2 *>(P.C) + (size_t)v * 5 * nc, ok);
 }
 
 // ----------------------------------------------------------------------------
@@ -168,6 +259,33 @@ struct Mom {                 // normalised moments <u^n>, <v^n>, <w^n>, <xi^2>, 
     T u[7], v[7], w[7], xi2, xi4;
 };
 
+// A Maxwellian state in the local frame, with the constants its micro-slope
+// solve needs (no divisions there): i2l = 1/(2 lam) = p/rho.
+template <class T>
+struct State {
+    T rho, ir, U, V, W, p, i2l, lam;
+    T tl, c4, e2;            // 2 lam, 4 lam^2/(K+3), |U|^2 + (K+3)/(2 lam)
+};
+
+template <class T>
+__device__ __forceinline__ State<T> make_state(const T q[5], T gam, T Kp3, T c4k) {
+    State<T> s;
+    s.rho = q[0];
+    const T ir = hg_rcp(q[0]);
+    s.ir = ir;
+    s.U = q[1] * ir;
+    s.V = q[2] * ir;
+    s.W = q[3] * ir;
+    const T q2 = s.U * s.U + s.V * s.V + s.W * s.W;
+    s.p = (gam - T(1)) * (q[4] - T(0.5) * s.rho * q2);
+    s.i2l = s.p * ir;
+    s.lam = T(0.5) * s.rho * hg_rcp(s.p);
+    s.tl = T(2) * s.lam;
+    s.c4 = c4k * s.lam * s.lam;
+    s.e2 = q2 + Kp3 * s.i2l;
+    return s;
+}
+
 template <class T>
 __device__ __forceinline__ void mom_full(T U, T i2l, T *m) {
     m[0] = T(1);
@@ -176,25 +294,25 @@ __device__ __forceinline__ void mom_full(T U, T i2l, T *m) {
     for (int n = 2; n < 7; ++n) m[n] = U * m[n - 1] + T(n - 1) * i2l * m[n - 2];
 }
 
-// <u^n> over u > 0 (sgn = +1) or u < 0 (sgn = -1)
+// <u^n> over u > 0 (sgn = +1) or u < 0 (sgn = -1):
+//   <u^0> = erfc(-sgn sqrt(lam) U)/2, <u^1> = U <u^0> + sgn exp(-lam U^2)/(2 sqrt(pi lam))
 template <class T>
-__device__ __forceinline__ void mom_half(T U, T lam, T i2l, T sgn, T *m) {
-    const T sl = hg_sqrt(lam);
-    const T e = hg_exp(-lam * U * U) * (T(0.5) / (sl * T(1.7724538509055160273)));  // / (2 sqrt(pi lam))
-    m[0] = T(0.5) * hg_erfc(-sgn * sl * U);
-    m[1] = U * m[0] + sgn * e;
+__device__ __forceinline__ void mom_half(const State<T> &s, T sgn, T *m) {
+    const T sl = hg_sqrt(s.lam);
+    const T e = hg_exp(-s.lam * s.U * s.U) * (T(0.28209479177387814347) * hg_rcp(sl));   // 1/(2 sqrt(pi))
+    m[0] = T(0.5) * hg_erfc(-sgn * sl * s.U);
+    m[1] = s.U * m[0] + sgn * e;
 #pragma unroll
-    for (int n = 2; n < 7; ++n) m[n] = U * m[n - 1] + T(n - 1) * i2l * m[n - 2];
+    for (int n = 2; n < 7; ++n) m[n] = s.U * m[n - 1] + T(n - 1) * s.i2l * m[n - 2];
 }
 
 template <class T>
-__device__ __forceinline__ void mom_state(T U, T V, T W, T lam, T K, Mom<T> &M) {
-    const T i2l = T(0.5) / lam;
-    mom_full(U, i2l, M.u);
-    mom_full(V, i2l, M.v);
-    mom_full(W, i2l, M.w);
-    M.xi2 = K * i2l;
-    M.xi4 = K * (K + T(2)) * i2l * i2l;
+__device__ __forceinline__ void mom_state(const State<T> &s, T K, Mom<T> &M) {
+    mom_full(s.U, s.i2l, M.u);
+    mom_full(s.V, s.i2l, M.v);
+    mom_full(s.W, s.i2l, M.w);
+    M.xi2 = K * s.i2l;
+    M.xi4 = K * (K + T(2)) * s.i2l * s.i2l;
 }
 
 // <u^P v^Q w^R (a.psi) psi>, psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2)
@@ -226,31 +344,28 @@ __device__ __forceinline__ void u_psi(const Mom<T> &M, T out[5]) {
     out[4] = T(0.5) * (M.u[3] + M.u[1] * (M.v[2] + M.w[2] + M.xi2));
 }
 
-// Solve <(a.psi) psi> = b for a, closed form of the 5x5 moment system.
+// Solve <(a.psi) psi> = b for a: closed form of the 5x5 moment system.
 template <class T>
-__device__ __forceinline__ void slope(const T b[5], T U, T V, T W, T lam, T Kp3, T a[5]) {
-    const T q2 = U * U + V * V + W * W;
-    const T e2 = q2 + Kp3 * T(0.5) / lam;
-    const T R1 = b[1] - U * b[0], R2 = b[2] - V * b[0], R3 = b[3] - W * b[0];
-    const T R4 = T(2) * b[4] - e2 * b[0];
-    a[4] = T(4) * lam * lam / Kp3 * (R4 - T(2) * (U * R1 + V * R2 + W * R3));
-    const T tl = T(2) * lam;
-    a[1] = tl * R1 - U * a[4];
-    a[2] = tl * R2 - V * a[4];
-    a[3] = tl * R3 - W * a[4];
-    a[0] = b[0] - U * a[1] - V * a[2] - W * a[3] - T(0.5) * a[4] * e2;
+__device__ __forceinline__ void slope(const T b[5], const State<T> &s, T a[5]) {
+    const T R1 = b[1] - s.U * b[0], R2 = b[2] - s.V * b[0], R3 = b[3] - s.W * b[0];
+    const T R4 = T(2) * b[4] - s.e2 * b[0];
+    a[4] = s.c4 * (R4 - T(2) * (s.U * R1 + s.V * R2 + s.W * R3));
+    a[1] = s.tl * R1 - s.U * a[4];
+    a[2] = s.tl * R2 - s.V * a[4];
+    a[3] = s.tl * R3 - s.W * a[4];
+    a[0] = b[0] - s.U * a[1] - s.V * a[2] - s.W * a[3] - T(0.5) * a[4] * s.e2;
 }
 
+// <a_1 u + a_2 v + a_3 w + A> = 0  =>  <(A.psi) psi> = -sum_j <u_j (a_j.psi) psi>
 template <class T>
-__device__ __forceinline__ void time_slope(const Mom<T> &M, const T a[3][5], T U, T V, T W, T lam, T Kp3, T A[5]) {
-    // <a_1 u + a_2 v + a_3 w + A> = 0  =>  <(A.psi) psi> = -sum_j <u_j (a_j.psi) psi>
+__device__ __forceinline__ void time_slope(const Mom<T> &M, const T a[3][5], const State<T> &s, T A[5]) {
     T t0[5], t1[5], t2[5], b[5];
     apsi<T, 1, 0, 0>(M, a[0], t0);
     apsi<T, 0, 1, 0>(M, a[1], t1);
     apsi<T, 0, 0, 1>(M, a[2], t2);
 #pragma unroll
     for (int k = 0; k < 5; ++k) b[k] = -(t0[k] + t1[k] + t2[k]);
-    slope(b, U, V, W, lam, Kp3, A);
+    slope(b, s, A);
 }
 
 // Time-integral weights q0..q5 of Eq. (flux) over [0, d].
@@ -269,192 +384,251 @@ __device__ __forceinline__ void q_coef(T d, T tau, T q[6]) {
     q[5] = -tau * tau * (T(1) - E);
 }
 
-// Flux F^n and dF^n/dt through a face point with unit normal n (global frame),
-// from the reconstructed left / right states and gradients (global frame).
-template <class T, bool TAU0>
-__device__ __forceinline__ void gks_flux(const T ql[5], const T gl[5][3], const T qr[5], const T gr[5][3],
-                                         const T n[3], T dt, const ProbDesc &P, T F[5], T dF[5]) {
-    const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma;
-    // local frame (n, t1, t2): t1 = n x e*, e* the axis least aligned with n
-    T t1[3];
-    {
-        const T ax = hg_abs(n[0]), ay = hg_abs(n[1]), az = hg_abs(n[2]);
-        if (ax <= ay && ax <= az) {
-            const T s = T(1) / hg_sqrt(n[1] * n[1] + n[2] * n[2]);
-            t1[0] = T(0); t1[1] = n[2] * s; t1[2] = -n[1] * s;
-        } else if (ay <= az) {
-            const T s = T(1) / hg_sqrt(n[0] * n[0] + n[2] * n[2]);
-            t1[0] = -n[2] * s; t1[1] = T(0); t1[2] = n[0] * s;
-        } else {
-            const T s = T(1) / hg_sqrt(n[0] * n[0] + n[1] * n[1]);
-            t1[0] = n[1] * s; t1[1] = -n[0] * s; t1[2] = T(0);
-        }
-    }
-    const T t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
-    const T *e[3] = {n, t1, t2};
-    auto rot = [&](const T q[5], T o[5]) {
-        o[0] = q[0];
-        o[1] = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
-        o[2] = q[1] * t1[0] + q[2] * t1[1] + q[3] * t1[2];
-        o[3] = q[1] * t2[0] + q[2] * t2[1] + q[3] * t2[2];
-        o[4] = q[4];
-    };
-    T Ql[5], Qr[5];
-    rot(ql, Ql);
-    rot(qr, Qr);
-    // primitives
-    const T rl = Ql[0], Ul = Ql[1] / rl, Vl = Ql[2] / rl, Wl = Ql[3] / rl;
-    const T pl = (gam - T(1)) * (Ql[4] - T(0.5) * rl * (Ul * Ul + Vl * Vl + Wl * Wl));
-    const T laml = T(0.5) * rl / pl, i2ll = pl / rl;
-    const T rr = Qr[0], Ur = Qr[1] / rr, Vr = Qr[2] / rr, Wr = Qr[3] / rr;
-    const T pr = (gam - T(1)) * (Qr[4] - T(0.5) * rr * (Ur * Ur + Vr * Vr + Wr * Wr));
-    const T lamr = T(0.5) * rr / pr, i2lr = pr / rr;
-    // half-space moments: left gas moving right (u > 0), right gas moving left (u < 0)
-    T ml[7], mr[7];
-    mom_half(Ul, laml, i2ll, T(1), ml);
-    mom_half(Ur, lamr, i2lr, T(-1), mr);
-    // equilibrium at the interface from the compatibility condition
-    const T rho0 = rl * ml[0] + rr * mr[0];
-    const T mu0 = rl * ml[1] + rr * mr[1];
-    const T mv0 = rl * ml[0] * Vl + rr * mr[0] * Vr;
-    const T mw0 = rl * ml[0] * Wl + rr * mr[0] * Wr;
-    const T E0 = T(0.5) * (rl * (ml[2] + ml[0] * (Vl * Vl + Wl * Wl + (K + T(2)) * i2ll)) +
-                           rr * (mr[2] + mr[0] * (Vr * Vr + Wr * Wr + (K + T(2)) * i2lr)));
-    const T U0 = mu0 / rho0, V0 = mv0 / rho0, W0 = mw0 / rho0;
-    const T lam0 = Kp3 * rho0 / (T(4) * (E0 - T(0.5) * rho0 * (U0 * U0 + V0 * V0 + W0 * W0)));
-    Mom<T> M0;
-    mom_state(U0, V0, W0, lam0, K, M0);
-    // directional derivatives along (n, t1, t2), momentum rotated into the frame
-    T Dl[3][5], Dr[3][5], a0[3][5];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        T dl[5], dr[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            dl[q] = gl[q][0] * e[j][0] + gl[q][1] * e[j][1] + gl[q][2] * e[j][2];
-            dr[q] = gr[q][0] * e[j][0] + gr[q][1] * e[j][1] + gr[q][2] * e[j][2];
-        }
-        rot(dl, Dl[j]);
-        rot(dr, Dr[j]);
-        T b0[5];
-        const T ir0 = T(0.5) / rho0;    // dQ0 = (dQ_l + dQ_r) / 2, b = dQ0 / rho0
-#pragma unroll
-        for (int q = 0; q < 5; ++q) b0[q] = (Dl[j][q] + Dr[j][q]) * ir0;
-        slope(b0, U0, V0, W0, lam0, Kp3, a0[j]);
-    }
-    T A0[5];
-    time_slope(M0, a0, U0, V0, W0, lam0, Kp3, A0);
-    T up0[5], uA0[5];
-    u_psi(M0, up0);
-    apsi<T, 1, 0, 0>(M0, A0, uA0);
-    T Fl[5], dFl[5];
-    if constexpr (TAU0) {
-        // tau = 0: f = g0 (1 + A t), so F^n = rho0 <u psi>, dF^n = rho0 <u (A.psi) psi>
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            Fl[k] = rho0 * up0[k];
-            dFl[k] = rho0 * uA0[k];
-        }
+// Local frame (n, t1, t2): t1 = n x e* / |n x e*| with e* the axis least aligned with n.
+template <class T>
+__device__ __forceinline__ void frame(const T n[3], T t1[3], T t2[3]) {
+    const T ax = hg_abs(n[0]), ay = hg_abs(n[1]), az = hg_abs(n[2]);
+    if (ax <= ay && ax <= az) {
+        const T s = hg_rcp(hg_sqrt(n[1] * n[1] + n[2] * n[2]));
+        t1[0] = T(0); t1[1] = n[2] * s; t1[2] = -n[1] * s;
+    } else if (ay <= az) {
+        const T s = hg_rcp(hg_sqrt(n[0] * n[0] + n[2] * n[2]));
+        t1[0] = -n[2] * s; t1[1] = T(0); t1[2] = n[0] * s;
     } else {
-        // left / right initial distributions: slopes and time slopes from their own moments
-        Mom<T> Ml, Mr;
-        mom_state(Ul, Vl, Wl, laml, K, Ml);
-        mom_state(Ur, Vr, Wr, lamr, K, Mr);
-        T al[3][5], ar[3][5], Al[5], Ar[5];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            T bl[5], br[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                bl[q] = Dl[j][q] / rl;
-                br[q] = Dr[j][q] / rr;
-            }
-            slope(bl, Ul, Vl, Wl, laml, Kp3, al[j]);
-            slope(br, Ur, Vr, Wr, lamr, Kp3, ar[j]);
-        }
-        time_slope(Ml, al, Ul, Vl, Wl, laml, Kp3, Al);
-        time_slope(Mr, ar, Ur, Vr, Wr, lamr, Kp3, Ar);
-        // half-space versions of the left / right moments
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            Ml.u[k] = ml[k];
-            Mr.u[k] = mr[k];
-        }
-        T e01[5], el0[5], el1[5], el2[5], er0[5], er1[5], er2[5], t[5];
-        apsi<T, 2, 0, 0>(M0, a0[0], e01);
-        apsi<T, 1, 1, 0>(M0, a0[1], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) e01[k] += t[k];
-        apsi<T, 1, 0, 1>(M0, a0[2], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) e01[k] += t[k];
-        u_psi(Ml, el0);
-        apsi<T, 2, 0, 0>(Ml, al[0], el1);
-        apsi<T, 1, 1, 0>(Ml, al[1], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) el1[k] += t[k];
-        apsi<T, 1, 0, 1>(Ml, al[2], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) el1[k] += t[k];
-        apsi<T, 1, 0, 0>(Ml, Al, el2);
-        u_psi(Mr, er0);
-        apsi<T, 2, 0, 0>(Mr, ar[0], er1);
-        apsi<T, 1, 1, 0>(Mr, ar[1], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) er1[k] += t[k];
-        apsi<T, 1, 0, 1>(Mr, ar[2], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) er1[k] += t[k];
-        apsi<T, 1, 0, 0>(Mr, Ar, er2);
-        T tau = T(0);
-        if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
-        // F^n, dF^n from int_0^dt and int_0^(dt/2) (Eq. expansion-1):
-        //   F = (4 I(dt/2) - I(dt)) / dt,  dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
-        T q1[6], qh[6], cF[6], cD[6];
-        q_coef(dt, tau, q1);
-        q_coef(T(0.5) * dt, tau, qh);
-        const T idt = T(1) / dt;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            cF[k] = (T(4) * qh[k] - q1[k]) * idt;
-            cD[k] = T(4) * (q1[k] - T(2) * qh[k]) * idt * idt;
-        }
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            Fl[k] = rho0 * (cF[0] * up0[k] + cF[1] * e01[k] + cF[2] * uA0[k]) +
-                    rl * (cF[3] * el0[k] + cF[4] * el1[k] + cF[5] * el2[k]) +
-                    rr * (cF[3] * er0[k] + cF[4] * er1[k] + cF[5] * er2[k]);
-            dFl[k] = rho0 * (cD[0] * up0[k] + cD[1] * e01[k] + cD[2] * uA0[k]) +
-                     rl * (cD[3] * el0[k] + cD[4] * el1[k] + cD[5] * el2[k]) +
-                     rr * (cD[3] * er0[k] + cD[4] * er1[k] + cD[5] * er2[k]);
-        }
+        const T s = hg_rcp(hg_sqrt(n[0] * n[0] + n[1] * n[1]));
+        t1[0] = n[1] * s; t1[1] = -n[0] * s; t1[2] = T(0);
     }
-    // back to the global frame
-    F[0] = Fl[0];
-    dF[0] = dFl[0];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        F[1 + a] = Fl[1] * n[a] + Fl[2] * t1[a] + Fl[3] * t2[a];
-        dF[1 + a] = dFl[1] * n[a] + dFl[2] * t1[a] + dFl[3] * t2[a];
-    }
-    F[4] = Fl[4];
-    dF[4] = dFl[4];
+    t2[0] = n[1] * t1[2] - n[2] * t1[1];
+    t2[1] = n[2] * t1[0] - n[0] * t1[2];
+    t2[2] = n[0] * t1[1] - n[1] * t1[0];
 }
 
-// Value and gradient of a cell's reconstruction at offset y from its centroid.
 template <class T>
-__device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, int c, const T y[3], T q[5], T g[5][3]) {
-    const int nc = P.nc;
+__device__ __forceinline__ void rot_in(const T q[5], const T n[3], const T t1[3], const T t2[3], T o[5]) {
+    o[0] = q[0];
+    o[1] = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    o[2] = q[1] * t1[0] + q[2] * t1[1] + q[3] * t1[2];
+    o[3] = q[1] * t2[0] + q[2] * t2[1] + q[3] * t2[2];
+    o[4] = q[4];
+}
+
+template <class T>
+__device__ __forceinline__ void rot_out(const T f[5], const T n[3], const T t1[3], const T t2[3], T o[5]) {
+    o[0] = f[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[1 + a] = f[1] * n[a] + f[2] * t1[a] + f[3] * t2[a];
+    o[4] = f[4];
+}
+
+// Directional derivative of the five (global-frame) variables along e, rotated into the frame.
+template <class T>
+__device__ __forceinline__ void dir_deriv(const T g[5][3], const T e[3], const T n[3], const T t1[3], const T t2[3],
+                                          T scale, T o[5]) {
+    T d[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) d[q] = (g[q][0] * e[0] + g[q][1] * e[1] + g[q][2] * e[2]) * scale;
+    rot_in(d, n, t1, t2, o);
+}
+
+// The interface equilibrium: compatibility condition Q0 = int_{u>0} psi g_l + int_{u<0} psi g_r.
+template <class T>
+__device__ __forceinline__ State<T> collide(const State<T> &l, const State<T> &r, const T ml[7], const T mr[7], T K,
+                                            T gam, T Kp3, T c4k) {
+    const T rho0 = l.rho * ml[0] + r.rho * mr[0];
+    const T mu0 = l.rho * ml[1] + r.rho * mr[1];
+    const T mv0 = l.rho * ml[0] * l.V + r.rho * mr[0] * r.V;
+    const T mw0 = l.rho * ml[0] * l.W + r.rho * mr[0] * r.W;
+    const T E0 = T(0.5) * (l.rho * (ml[2] + ml[0] * (l.V * l.V + l.W * l.W + (K + T(2)) * l.i2l)) +
+                           r.rho * (mr[2] + mr[0] * (r.V * r.V + r.W * r.W + (K + T(2)) * r.i2l)));
+    const T q0[5] = {rho0, mu0, mv0, mw0, E0};
+    return make_state(q0, gam, Kp3, c4k);
+}
+
+// Directional derivative of the Euler flux along axis j of the local frame:
+// dF_j(Q)[v] for the state (rho, u, E/rho + p/rho = H) and a perturbation v of the
+// conservative variables.
+template <class T>
+__device__ __forceinline__ void euler_jvp(int j, T gm1, const T u[3], T H, const T v[5], T out[5]) {
+    const T uv = u[0] * v[1] + u[1] * v[2] + u[2] * v[3];
+    const T dp = gm1 * (v[4] - uv + T(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * v[0]);
+    const T vmj = v[1 + j], uj = u[j];
+    out[0] = vmj;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[1 + a] = u[a] * vmj + uj * v[1 + a] - uj * u[a] * v[0] + (a == j ? dp : T(0));
+    out[4] = (v[4] + dp) * uj + H * (vmj - uj * v[0]);
+}
+
+// tau = 0 (smooth flow, Sec. 5.1): f = g0 (1 + A t) with g0 the Maxwellian of the
+// collided state Q0.  Its moments are exactly those of the Euler equations at Q0:
+//   F^n  = rho0 <u psi>_0           = F_Euler,n(Q0)
+//   dF^n = rho0 <u (A.psi) psi>_0   = dF_Euler,n/dQ (Q0) . Q_t,
+//   Q_t  = rho0 <(A.psi) psi>_0     = -sum_j dF_Euler,j/dQ (Q0) . dQ0/dx_j,
+// because A g0 is the time derivative of g0 once <a_j u_j + A> = 0 fixes A, and
+// the micro-slopes a_j of g0 represent dQ0/dx_j = (dQ_l + dQ_r)/2.  Only the
+// collision itself needs the half-space moments.
+template <class T>
+__device__ __forceinline__ void gks_flux_tau0(const T ql[5], const T qr[5], const T gsum[5][3], const T n[3],
+                                              const ProbDesc &P, T F[5], T dF[5]) {
+    const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma, c4k = T(4) / Kp3, gm1 = gam - T(1);
+    T t1[3], t2[3];
+    frame(n, t1, t2);
+    T Ql[5], Qr[5];
+    rot_in(ql, n, t1, t2, Ql);
+    rot_in(qr, n, t1, t2, Qr);
+    const State<T> sl = make_state(Ql, gam, Kp3, c4k), sr = make_state(Qr, gam, Kp3, c4k);
+    T ml[7], mr[7];
+    mom_half(sl, T(1), ml);
+    mom_half(sr, T(-1), mr);
+    const State<T> s0 = collide(sl, sr, ml, mr, K, gam, Kp3, c4k);
+    const T u0[3] = {s0.U, s0.V, s0.W};
+    const T E0 = T(0.5) * s0.rho * (s0.U * s0.U + s0.V * s0.V + s0.W * s0.W) + s0.p / gm1;
+    const T H0 = (E0 + s0.p) * s0.ir;
+    // Q_t = -sum_j A_j dQ0/dx_j, derivatives taken along (n, t1, t2) and rotated in
+    const T *e[3] = {n, t1, t2};
+    T Qt[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T d0[5], jv[5];
+        dir_deriv(gsum, e[j], n, t1, t2, T(0.5), d0);
+        euler_jvp(j, gm1, u0, H0, d0, jv);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Qt[k] -= jv[k];
+    }
+    T Fl[5], dFl[5];
+    const T mn = s0.rho * s0.U;
+    Fl[0] = mn;
+    Fl[1] = mn * s0.U + s0.p;
+    Fl[2] = mn * s0.V;
+    Fl[3] = mn * s0.W;
+    Fl[4] = (E0 + s0.p) * s0.U;
+    euler_jvp(0, gm1, u0, H0, Qt, dFl);
+    rot_out(Fl, n, t1, t2, F);
+    rot_out(dFl, n, t1, t2, dF);
+}
+
+// General collision time (Eq. flux with tau > 0): the equilibrium part and both
+// initial (left / right) parts, fitted linearly in time over [0, dt].
+template <class T>
+__device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], const T qr[5], const T gr[5][3],
+                                              const T n[3], T dt, const ProbDesc &P, T F[5], T dF[5]) {
+    const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma, c4k = T(4) / Kp3;
+    T t1[3], t2[3];
+    frame(n, t1, t2);
+    T Ql[5], Qr[5];
+    rot_in(ql, n, t1, t2, Ql);
+    rot_in(qr, n, t1, t2, Qr);
+    const State<T> sl = make_state(Ql, gam, Kp3, c4k), sr = make_state(Qr, gam, Kp3, c4k);
+    T ml[7], mr[7];
+    mom_half(sl, T(1), ml);
+    mom_half(sr, T(-1), mr);
+    const State<T> s0 = collide(sl, sr, ml, mr, K, gam, Kp3, c4k);
+    Mom<T> M0, Ml, Mr;
+    mom_state(s0, K, M0);
+    mom_state(sl, K, Ml);
+    mom_state(sr, K, Mr);
+    const T *e[3] = {n, t1, t2};
+    const T irl = sl.ir, irr = sr.ir, half_ir0 = T(0.5) * s0.ir;
+    T a0[3][5], al[3][5], ar[3][5];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T dl[5], dr[5], b[5];
+        dir_deriv(gl, e[j], n, t1, t2, T(1), dl);
+        dir_deriv(gr, e[j], n, t1, t2, T(1), dr);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) b[q] = (dl[q] + dr[q]) * half_ir0;
+        slope(b, s0, a0[j]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) b[q] = dl[q] * irl;
+        slope(b, sl, al[j]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) b[q] = dr[q] * irr;
+        slope(b, sr, ar[j]);
+    }
+    T A0[5], Al[5], Ar[5];
+    time_slope(M0, a0, s0, A0);
+    time_slope(Ml, al, sl, Al);
+    time_slope(Mr, ar, sr, Ar);
+    // the initial parts act on their half spaces
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        Ml.u[k] = ml[k];
+        Mr.u[k] = mr[k];
+    }
+    T up0[5], e01[5], uA0[5], el0[5], el1[5], el2[5], er0[5], er1[5], er2[5], t[5];
+    u_psi(M0, up0);
+    apsi<T, 1, 0, 0>(M0, A0, uA0);
+    apsi<T, 2, 0, 0>(M0, a0[0], e01);
+    apsi<T, 1, 1, 0>(M0, a0[1], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) e01[k] += t[k];
+    apsi<T, 1, 0, 1>(M0, a0[2], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) e01[k] += t[k];
+    u_psi(Ml, el0);
+    apsi<T, 2, 0, 0>(Ml, al[0], el1);
+    apsi<T, 1, 1, 0>(Ml, al[1], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) el1[k] += t[k];
+    apsi<T, 1, 0, 1>(Ml, al[2], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) el1[k] += t[k];
+    apsi<T, 1, 0, 0>(Ml, Al, el2);
+    u_psi(Mr, er0);
+    apsi<T, 2, 0, 0>(Mr, ar[0], er1);
+    apsi<T, 1, 1, 0>(Mr, ar[1], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) er1[k] += t[k];
+    apsi<T, 1, 0, 1>(Mr, ar[2], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) er1[k] += t[k];
+    apsi<T, 1, 0, 0>(Mr, Ar, er2);
+    T tau = T(0);
+    if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(sl.p - sr.p) / (sl.p + sr.p) * dt;
+    // F^n, dF^n from int_0^dt and int_0^(dt/2) (Eq. expansion-1):
+    //   F = (4 I(dt/2) - I(dt)) / dt,  dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
+    T q1[6], qh[6], cF[6], cD[6];
+    q_coef(dt, tau, q1);
+    q_coef(T(0.5) * dt, tau, qh);
+    const T idt = T(1) / dt;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        cF[k] = (T(4) * qh[k] - q1[k]) * idt;
+        cD[k] = T(4) * (q1[k] - T(2) * qh[k]) * idt * idt;
+    }
+    T Fl[5], dFl[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        Fl[k] = s0.rho * (cF[0] * up0[k] + cF[1] * e01[k] + cF[2] * uA0[k]) +
+                sl.rho * (cF[3] * el0[k] + cF[4] * el1[k] + cF[5] * el2[k]) +
+                sr.rho * (cF[3] * er0[k] + cF[4] * er1[k] + cF[5] * er2[k]);
+        dFl[k] = s0.rho * (cD[0] * up0[k] + cD[1] * e01[k] + cD[2] * uA0[k]) +
+                 sl.rho * (cD[3] * el0[k] + cD[4] * el1[k] + cD[5] * el2[k]) +
+                 sr.rho * (cD[3] * er0[k] + cD[4] * er1[k] + cD[5] * er2[k]);
+    }
+    rot_out(Fl, n, t1, t2, F);
+    rot_out(dFl, n, t1, t2, dF);
+}
+
+// Value and gradient of a cell's reconstruction at offset y from its centroid;
+// ADD accumulates the gradient into g (tau = 0 needs only the sum of both sides).
+template <class T, bool ADD>
+__device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32_t c, const T y[3], T q[5], T g[5][3]) {
+    const uint32_t nc = (uint32_t)P.nc;
     const T yy[6] = {y[0] * y[0], y[1] * y[1], y[2] * y[2], y[0] * y[1], y[0] * y[2], y[1] * y[2]};
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         T cf[10];
-        if constexpr (sizeof(T) == 8) {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) cf[k] = P.C[(size_t)(v * NCOEF + k) * nc + c];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 10; ++k) cf[k] = P.C32[(size_t)(v * NCOEF + k) * nc + c];
+        for (int k = 0; k < 5; ++k) {
+            if constexpr (sizeof(T) == 8) {
+                const d2 pr = ldg<d2>(reinterpret_cast<const d2 *>(P.C) + (size_t)(v * 5 + k) * nc, c * 16u);
+                cf[2 * k] = pr.x;
+                cf[2 * k + 1] = pr.y;
+            } else {
+                const f2 pr = ldg<f2>(reinterpret_cast<const f2 *>(P.C32) + (size_t)(v * 5 + k) * nc, c * 8u);
+                cf[2 * k] = pr.x;
+                cf[2 * k + 1] = pr.y;
+            }
         }
         T val = cf[0] + cf[1] * y[0] + cf[2] * y[1] + cf[3] * y[2];
 #pragma unroll
@@ -463,12 +637,17 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, int c,
             q[v] = val;
         } else {
             // FP32 form: FP64 cell mean plus FP32 deviation, rounded once
-            const double mean = (stage == 1 ? P.Q : P.Qs)[(size_t)v * nc + c];
+            const double mean = ldg<double>((stage == 1 ? P.Q : P.Qs) + (size_t)v * nc, c * 8u);
             q[v] = (float)(mean + (double)val);
         }
-        g[v][0] = cf[1] + T(2) * cf[4] * y[0] + cf[7] * y[1] + cf[8] * y[2];
-        g[v][1] = cf[2] + T(2) * cf[5] * y[1] + cf[7] * y[0] + cf[9] * y[2];
-        g[v][2] = cf[3] + T(2) * cf[6] * y[2] + cf[8] * y[0] + cf[9] * y[1];
+        const T gx = cf[1] + T(2) * cf[4] * y[0] + cf[7] * y[1] + cf[8] * y[2];
+        const T gy = cf[2] + T(2) * cf[5] * y[1] + cf[7] * y[0] + cf[9] * y[2];
+        const T gz = cf[3] + T(2) * cf[6] * y[2] + cf[8] * y[0] + cf[9] * y[1];
+        if constexpr (ADD) {
+            g[v][0] += gx; g[v][1] += gy; g[v][2] += gz;
+        } else {
+            g[v][0] = gx; g[v][1] = gy; g[v][2] = gz;
+        }
     }
 }
 
@@ -479,32 +658,40 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
     __shared__ double red[3][10][FACE_TILE];
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
-    const int lane = (int)(threadIdx.x % FACE_TILE);
-    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / FACE_TILE);   // Gauss point
-    const int f = tl.begin + lane;
-    const bool ok = f < tl.end;
-    const int nf = P.nf;
+    const uint32_t lane = threadIdx.x % FACE_TILE;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / FACE_TILE);   // Gauss point of this wave
+    const uint32_t f = tl.begin + lane;
+    const bool ok = f < (uint32_t)tl.end;
+    const uint32_t nf = (uint32_t)P.nf;
     double out[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) out[k] = 0.0;
-    int l = 0, r = 0;
+    uint32_t l = 0, r = 0;
     if (ok) {
-        l = P.fcell[f];
-        r = P.fcell[nf + f];
+        l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
+        r = (uint32_t)ldg<int32_t>(P.fcell + nf, f * 4u);
         const double *fg = P.fgeo;
-        const T n[3] = {(T)fg[f], (T)fg[(size_t)nf + f], (T)fg[(size_t)2 * nf + f]};
-        const double S = fg[(size_t)3 * nf + f];
+        const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
+                        (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+        const double S = ldg<double>(fg + (size_t)3 * nf, f * 8u);
         T yl[3], yr[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            yl[a] = (T)fg[(size_t)(4 + 3 * g + a) * nf + f];
-            yr[a] = (T)fg[(size_t)(13 + 3 * g + a) * nf + f];
+            yl[a] = (T)ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
+            yr[a] = (T)ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
         }
-        T qL[5], gL[5][3], qR[5], gR[5][3];
-        recon_point<T>(P, stage, l, yl, qL, gL);
-        recon_point<T>(P, stage, r, yr, qR, gR);
         T F[5], dF[5];
-        gks_flux<T, TAU0>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+        if constexpr (TAU0) {
+            T qL[5], qR[5], gs[5][3];
+            recon_point<T, false>(P, stage, l, yl, qL, gs);
+            recon_point<T, true>(P, stage, r, yr, qR, gs);
+            gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
+        } else {
+            T qL[5], gL[5][3], qR[5], gR[5][3];
+            recon_point<T, false>(P, stage, l, yl, qL, gL);
+            recon_point<T, false>(P, stage, r, yr, qR, gR);
+            gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+        }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
@@ -520,11 +707,11 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
         for (int k = 0; k < 10; ++k) {
             const double s = red[0][k][lane] + red[1][k][lane] + red[2][k][lane];
             if constexpr (COLOURED) {
-                const size_t nc = (size_t)P.nc;
-                P.acc[k * nc + l] -= s;   // no other face of this colour touches l or r
-                P.acc[k * nc + r] += s;
+                double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
+                stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - s);
+                stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + s);
             } else {
-                P.FF[(size_t)k * nf + f] = s;
+                stg<double>(P.FF + (size_t)k * nf, f * 8u, s);
             }
         }
     }
@@ -539,14 +726,15 @@ __device__ __forceinline__ double wave_min(double x) {
     return x;
 }
 
-__device__ __forceinline__ double cfl_bound(const ProbDesc &P, int i, const double q[5], bool &ok) {
+// h / (|U| + c) of a cell, and whether its state is physical (rho > 0, p > 0, finite)
+__device__ __forceinline__ double cfl_bound(const ProbDesc &P, uint32_t i, const double q[5], bool &ok) {
     const double rho = q[0], ir = 1.0 / rho;
     const double u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
     const double p = (P.gamma - 1.0) * (q[4] - 0.5 * rho * (u * u + v * v + w * w));
     ok = rho > 0.0 && p > 0.0 && isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
          isfinite(q[4]);
     const double c = sqrt(P.gamma * p * ir);
-    return P.cgeo[(size_t)8 * P.nc + i] / (sqrt(u * u + v * v + w * w) + c);
+    return ldg<double>(P.cgeo + (size_t)8 * P.nc, i * 8u) / (sqrt(u * u + v * v + w * w) + c);
 }
 
 template <int STAGE, bool COLOURED>
@@ -554,51 +742,54 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
                                                       const Tile *__restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
-    const int nc = P.nc;
-    const int i = tl.begin + (int)threadIdx.x;
+    const uint32_t nc = (uint32_t)P.nc;
+    const uint32_t i = tl.begin + threadIdx.x;
     double bound = DBL_MAX;
-    if (i < tl.end) {
+    if (i < (uint32_t)tl.end) {
         double s[10];
         if constexpr (COLOURED) {
 #pragma unroll
             for (int k = 0; k < 10; ++k) {
-                s[k] = P.acc[(size_t)k * nc + i];
-                P.acc[(size_t)k * nc + i] = 0.0;
+                double *acc = P.acc + (size_t)k * nc;
+                s[k] = ldg<double>(acc, i * 8u);
+                stg<double>(acc, i * 8u, 0.0);
             }
         } else {
-            const int nf = P.nf;
+            const uint32_t nf = (uint32_t)P.nf;
 #pragma unroll
             for (int k = 0; k < 10; ++k) s[k] = 0.0;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int code = P.cface[(size_t)p * nc + i];
-                const int f = code >> 1;
-                const double sg = (code & 1) ? 1.0 : -1.0;   // normal points out of the left cell
+            for (int p = 0; p < 4; ++p) {       // the cell's four faces, fixed order
+                const uint32_t code = (uint32_t)ldg<int32_t>(P.cface + (size_t)p * nc, i * 4u);
+                const uint32_t f = code >> 1;
+                const double sg = (code & 1u) ? 1.0 : -1.0;   // the normal points out of the left cell
 #pragma unroll
-                for (int k = 0; k < 10; ++k) s[k] = fma(sg, P.FF[(size_t)k * nf + f], s[k]);
+                for (int k = 0; k < 10; ++k) s[k] = fma(sg, ldg<double>(P.FF + (size_t)k * nf, f * 8u), s[k]);
             }
         }
-        const double iv = P.cgeo[(size_t)7 * nc + i];
+        const double iv = ldg<double>(P.cgeo + (size_t)7 * nc, i * 8u);
         const double dt = P.dt[0];
         double qn[5];
         bool ok;
         if constexpr (STAGE == 1) {
+            // Q* = Q + dt/2 L + dt^2/8 dL,   R = Q + dt L + dt^2/6 dL
             const double h2 = 0.5 * dt, h8 = 0.125 * dt * dt, h6 = dt * dt * (1.0 / 6.0);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double q = P.Q[(size_t)v * nc + i];
+                const double q = ldg<double>(P.Q + (size_t)v * nc, i * 8u);
                 const double L = s[v] * iv, dL = s[5 + v] * iv;
                 qn[v] = q + h2 * L + h8 * dL;
-                P.Qs[(size_t)v * nc + i] = qn[v];
-                P.R[(size_t)v * nc + i] = q + dt * L + h6 * dL;
+                stg<double>(P.Qs + (size_t)v * nc, i * 8u, qn[v]);
+                stg<double>(P.R + (size_t)v * nc, i * 8u, q + dt * L + h6 * dL);
             }
             cfl_bound(P, i, qn, ok);
         } else {
+            // Q^{n+1} = R + dt^2/3 dL(Q*)
             const double h3 = dt * dt * (1.0 / 3.0);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                qn[v] = P.R[(size_t)v * nc + i] + h3 * (s[5 + v] * iv);
-                P.Q[(size_t)v * nc + i] = qn[v];
+                qn[v] = ldg<double>(P.R + (size_t)v * nc, i * 8u) + h3 * (s[5 + v] * iv);
+                stg<double>(P.Q + (size_t)v * nc, i * 8u, qn[v]);
             }
             bound = cfl_bound(P, i, qn, ok);
         }
@@ -614,12 +805,12 @@ __global__ __launch_bounds__(UPD_TILE) void k_dt_local(const ProbDesc *__restric
                                                         const Tile *__restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
-    const int i = tl.begin + (int)threadIdx.x;
+    const uint32_t i = tl.begin + threadIdx.x;
     double bound = DBL_MAX;
-    if (i < tl.end) {
+    if (i < (uint32_t)tl.end) {
         double q[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = P.Q[(size_t)v * P.nc + i];
+        for (int v = 0; v < 5; ++v) q[v] = ldg<double>(P.Q + (size_t)v * P.nc, i * 8u);
         bool ok;
         bound = cfl_bound(P, i, q, ok);
         if (!ok) P.flag[0] = 1;
@@ -628,16 +819,26 @@ __global__ __launch_bounds__(UPD_TILE) void k_dt_local(const ProbDesc *__restric
     if (threadIdx.x == 0) P.dtpart[tl.local] = bound;
 }
 
-__global__ __launch_bounds__(256) void k_dt_final(const ProbDesc *__restrict__ probs, double dt_fixed) {
-    __shared__ double part[4];
+__global__ __launch_bounds__(1024) void k_dt_final(const ProbDesc *__restrict__ probs, double dt_fixed) {
+    __shared__ double part[16];
     const ProbDesc &P = probs[blockIdx.x];
-    double m = DBL_MAX;
-    for (int k = threadIdx.x; k < P.n_cell_tiles; k += 256) m = fmin(m, P.dtpart[k]);
-    m = wave_min(m);
+    double m0 = DBL_MAX, m1 = DBL_MAX, m2 = DBL_MAX, m3 = DBL_MAX;   // four independent chains
+    const uint32_t n = (uint32_t)P.n_cell_tiles;
+    uint32_t k = threadIdx.x;
+    for (; k + 3 * 1024 < n; k += 4 * 1024) {
+        m0 = fmin(m0, ldg<double>(P.dtpart, k * 8u));
+        m1 = fmin(m1, ldg<double>(P.dtpart, (k + 1024) * 8u));
+        m2 = fmin(m2, ldg<double>(P.dtpart, (k + 2048) * 8u));
+        m3 = fmin(m3, ldg<double>(P.dtpart, (k + 3072) * 8u));
+    }
+    for (; k < n; k += 1024) m0 = fmin(m0, ldg<double>(P.dtpart, k * 8u));
+    double m = wave_min(fmin(fmin(m0, m1), fmin(m2, m3)));
     if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        m = fmin(fmin(part[0], part[1]), fmin(part[2], part[3]));
+#pragma unroll
+        for (int w = 1; w < 16; ++w) m = fmin(m, part[w]);
+        m = fmin(m, part[0]);
         const double dt = dt_fixed > 0.0 ? dt_fixed : P.cfl * m;
         P.dt[0] = dt;
         P.time[0] += dt;
@@ -652,12 +853,15 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 // ----------------------------------------------------------------------------
 // launch wrappers
 // ----------------------------------------------------------------------------
+constexpr int WENO_CELLS = HGKS_WENO_CELLS;     // cells per WENO workgroup (32 or 64)
+
 void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
     if (ntiles <= 0) return;
+    dim3 g(ntiles * (WENO_TILE / WENO_CELLS)), b(weno_threads<WENO_CELLS>());
     if (mixed)
-        hipLaunchKernelGGL(k_weno<true>, dim3(ntiles), dim3(5 * WENO_TILE), 0, s, probs, tiles, stage);
+        hipLaunchKernelGGL((k_weno<true, WENO_CELLS>), g, b, 0, s, probs, tiles, stage);
     else
-        hipLaunchKernelGGL(k_weno<false>, dim3(ntiles), dim3(5 * WENO_TILE), 0, s, probs, tiles, stage);
+        hipLaunchKernelGGL((k_weno<false, WENO_CELLS>), g, b, 0, s, probs, tiles, stage);
 }
 
 void launch_flux(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0, bool coloured,
@@ -694,7 +898,7 @@ void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, hipSt
 
 void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s) {
     if (nprobs <= 0) return;
-    hipLaunchKernelGGL(k_dt_final, dim3(nprobs), dim3(256), 0, s, probs, dt_fixed);
+    hipLaunchKernelGGL(k_dt_final, dim3(nprobs), dim3(1024), 0, s, probs, dt_fixed);
 }
 
 void launch_fill(double *p, double v, int64_t n, hipStream_t s) {
