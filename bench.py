@@ -9,7 +9,14 @@ path (the headline value) and for the FP32-mixed form, the roofline position
 of the dominant kernel (per-kernel HIP events inside the timed region), and the
 CPU oracle timed on this host.
 
-    python bench.py [--steps K] [--warmup W] [--n N] [--no-cpu-baseline]
+The serve loop (continuous batching of many smaller solves) runs last: a
+seeded stream of requests (Kuhn boxes of 6 N^3 cells, N ~ U{8..48}, random
+smooth data, Mach 0.1-2, FP64 or FP32-mixed, 200 steps each) is served twice,
+first all at once to measure the loop's capacity, then with Poisson arrivals
+at 0.8 of that capacity; the line reports p50/p99 latency (arrival to result
+on the host, host mesh precompute included) and aggregate cell-updates/s.
+
+    python bench.py [--steps K] [--warmup W] [--n N] [--no-cpu-baseline] [--serve R]
 """
 from __future__ import annotations
 
@@ -104,6 +111,32 @@ def cpu_baseline(n_sample: int = 32):
                       f"(same advection data), {el:.1f} s"}
 
 
+def serve_bench(count: int, steps: int, budget_gb: float):
+    """Closed-loop capacity, then Poisson arrivals at 0.8 of it (requests/s)."""
+    from paper_2407_00656_amd import serve
+    from paper_2407_00656_amd import workloads as W
+    reqs = W.serve_requests(count, seed=2407, n_range=(8, 48), steps=steps, rate=1.0)
+    for r in reqs:
+        r.arrival = 0.0
+    budget = int(budget_gb * 1e9)
+    burst = serve.run(reqs, budget, workers=4)
+    capacity = burst["requests"] / burst["makespan_s"]
+    rate = 0.8 * capacity
+    reqs = W.serve_requests(count, seed=2407, n_range=(8, 48), steps=steps, rate=rate)
+    res = serve.run(reqs, budget, workers=4)
+    errs = serve.exact_errors(res["jobs"])
+    cells = [j.mesh.n_cells for j in res["jobs"]]
+    return {"requests": res["requests"], "steps_each": steps, "n_range": [8, 48],
+            "cells_mean": round(float(sum(cells)) / len(cells), 1),
+            "precision_mix_fp32": sum(j.req.precision for j in res["jobs"]),
+            "rate_req_per_s": round(rate, 4), "capacity_req_per_s": round(capacity, 4),
+            "p50_s": round(res["p50_s"], 4), "p99_s": round(res["p99_s"], 4),
+            "cell_updates_per_s": round(res["cell_updates_per_s"], 1),
+            "cell_updates_per_gpu_busy_s": round(res["cell_updates_per_busy_s"], 1),
+            "ticks": res["ticks"], "hbm_budget_GB": budget_gb,
+            "rel_L1_rho_vs_exact_max": max(errs)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +145,9 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serve-loop run (0 skips it)")
+    ap.add_argument("--serve-steps", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (x5) to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -172,6 +208,11 @@ def main():
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(32 if n >= 32 else n)
 
+    srv = None
+    if args.serve > 0:
+        print("bench: serve loop", file=sys.stderr, flush=True)
+        srv = serve_bench(args.serve, args.serve_steps, args.serve_budget_gb)
+
     out = {
         "metric": "cell-updates/s per S2O4 step on 1 MI355X (FP64 vs FP32-mixed); serve p50/p99",
         "value": round(value, 1),
@@ -193,6 +234,7 @@ def main():
             "value": round(nc * args.steps / r32["seconds"], 1),
             "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
             "speedup_vs_fp64": round(r64["seconds"] / r32["seconds"], 3)},
+        "serve": srv,
         "kernels": kernels,
         "setup_s": round(r64["setup_s"], 2),
         "footprint_GB": round(r64["footprint"] / 1e9, 3),

@@ -26,6 +26,7 @@
 
 #include "hgks_internal.h"
 #include "kernels.h"
+#include "erfcx_table.h"
 
 #ifndef HGKS_WENO_CELLS
 #define HGKS_WENO_CELLS 32
@@ -71,17 +72,49 @@ __device__ __forceinline__ void stg(void *base, uint32_t off, const T &v) {
 // ----------------------------------------------------------------------------
 // precision helpers
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ double hg_erfc(double x) { return erfc(x); }
-__device__ __forceinline__ float hg_erfc(float x) { return erfcf(x); }
 __device__ __forceinline__ double hg_exp(double x) { return exp(x); }
 __device__ __forceinline__ float hg_exp(float x) { return expf(x); }
-__device__ __forceinline__ double hg_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float hg_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double hg_abs(double x) { return fabs(x); }
 __device__ __forceinline__ float hg_abs(float x) { return fabsf(x); }
-// reciprocal: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32
-__device__ __forceinline__ double hg_rcp(double x) { return 1.0 / x; }
+// Reciprocal and reciprocal square root.  FP64: the hardware estimate refined by
+// two Newton steps, e <- 1 - x r, r <- r + r e (and the analogous step for x^-1/2),
+// which leaves a few ulp of error instead of the correctly rounded result that
+// costs twice the instructions.  FP32: the hardware estimate (1 ulp).
+__device__ __forceinline__ double hg_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 __device__ __forceinline__ float hg_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double hg_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);     // 1 - x y^2
+        y = fma(0.5 * y, e, y);                   // y (1 + e/2)
+    }
+    return y;
+}
+__device__ __forceinline__ float hg_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// erfcx(a) = exp(a^2) erfc(a) for a >= 0: Chebyshev series in t = (a - k)/(a + k),
+// summed by Clenshaw's recurrence (the coefficients come from gen_erfcx_table.py).
+template <class T>
+__device__ __forceinline__ T erfcx_pos(T a) {
+    constexpr int NT = sizeof(T) == 8 ? ERFCX_TERMS_F64 : ERFCX_TERMS_F32;
+    const T t = (a - T(ERFCX_K)) * hg_rcp(a + T(ERFCX_K));
+    const T t2 = t + t;
+    T b1 = T(0), b2 = T(0);
+#pragma unroll
+    for (int j = NT - 1; j >= 1; --j) {
+        const T b = fma(t2, b1, T(ERFCX_CHEB[j]) - b2);
+        b2 = b1;
+        b1 = b;
+    }
+    return fma(t, b1, T(ERFCX_CHEB[0]) - b2);
+}
 
 // ----------------------------------------------------------------------------
 // WENO reconstruction
@@ -126,14 +159,14 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
     T w[5], ws = T(0);
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-        w[m] = (m == 0 ? g0 : gl) * (T(1) + tauZ / (beta[m] + eps));
+        w[m] = (m == 0 ? g0 : gl) * (T(1) + tauZ * hg_rcp(beta[m] + eps));
         ws += w[m];
     }
-    const T inv = T(1) / ws;
-    const T s0 = w[0] * inv / g0;
+    const T inv = hg_rcp(ws);
+    const T s0 = w[0] * inv * hg_rcp(g0);
     T al[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) al[m] = w[1 + m] * inv - w[0] * inv * gl / g0;
+    for (int m = 0; m < 4; ++m) al[m] = w[1 + m] * inv - s0 * gl;
     // combined polynomial in y = x - centroid
     const T ih = (T)ldg<double>(P.cgeo, i * 8u), ih2 = ih * ih;
     T c[10];
@@ -294,16 +327,22 @@ __device__ __forceinline__ void mom_full(T U, T i2l, T *m) {
     for (int n = 2; n < 7; ++n) m[n] = U * m[n - 1] + T(n - 1) * i2l * m[n - 2];
 }
 
-// <u^n> over u > 0 (sgn = +1) or u < 0 (sgn = -1):
-//   <u^0> = erfc(-sgn sqrt(lam) U)/2, <u^1> = U <u^0> + sgn exp(-lam U^2)/(2 sqrt(pi lam))
-template <class T>
-__device__ __forceinline__ void mom_half(const State<T> &s, T sgn, T *m) {
-    const T sl = hg_sqrt(s.lam);
-    const T e = hg_exp(-s.lam * s.U * s.U) * (T(0.28209479177387814347) * hg_rcp(sl));   // 1/(2 sqrt(pi))
-    m[0] = T(0.5) * hg_erfc(-sgn * sl * s.U);
-    m[1] = s.U * m[0] + sgn * e;
+// <u^n>, n < NM, over u > 0 (sgn = +1) or u < 0 (sgn = -1) of the normalised
+// Maxwellian with mean U and lam = rho / (2p), i2l = 1/(2 lam):
+//   <u^0> = erfc(-sgn sqrt(lam) U)/2,  <u^1> = U <u^0> + sgn exp(-lam U^2)/(2 sqrt(pi lam)),
+//   <u^n> = U <u^(n-1)> + (n-1)/(2 lam) <u^(n-2)>.
+// erfc(z) = exp(-z^2) erfcx(|z|) for z >= 0 and 2 - exp(-z^2) erfcx(|z|) for z < 0,
+// so one exponential serves both of the first two moments.
+template <class T, int NM>
+__device__ __forceinline__ void mom_half(T U, T lam, T i2l, T sgn, T *m) {
+    const T rs = hg_rsqrt(lam);                       // 1/sqrt(lam)
+    const T x = lam * rs * U;                         // sqrt(lam) U
+    const T e = hg_exp(-lam * U * U);
+    const T ee = e * erfcx_pos(hg_abs(x));
+    m[0] = T(0.5) * (sgn * x <= T(0) ? ee : T(2) - ee);
+    m[1] = U * m[0] + sgn * e * (T(0.28209479177387814347) * rs);   // 1/(2 sqrt(pi))
 #pragma unroll
-    for (int n = 2; n < 7; ++n) m[n] = s.U * m[n - 1] + T(n - 1) * s.i2l * m[n - 2];
+    for (int n = 2; n < NM; ++n) m[n] = U * m[n - 1] + T(n - 1) * i2l * m[n - 2];
 }
 
 template <class T>
@@ -389,13 +428,13 @@ template <class T>
 __device__ __forceinline__ void frame(const T n[3], T t1[3], T t2[3]) {
     const T ax = hg_abs(n[0]), ay = hg_abs(n[1]), az = hg_abs(n[2]);
     if (ax <= ay && ax <= az) {
-        const T s = hg_rcp(hg_sqrt(n[1] * n[1] + n[2] * n[2]));
+        const T s = hg_rsqrt(n[1] * n[1] + n[2] * n[2]);
         t1[0] = T(0); t1[1] = n[2] * s; t1[2] = -n[1] * s;
     } else if (ay <= az) {
-        const T s = hg_rcp(hg_sqrt(n[0] * n[0] + n[2] * n[2]));
+        const T s = hg_rsqrt(n[0] * n[0] + n[2] * n[2]);
         t1[0] = -n[2] * s; t1[1] = T(0); t1[2] = n[0] * s;
     } else {
-        const T s = hg_rcp(hg_sqrt(n[0] * n[0] + n[1] * n[1]));
+        const T s = hg_rsqrt(n[0] * n[0] + n[1] * n[1]);
         t1[0] = n[1] * s; t1[1] = -n[0] * s; t1[2] = T(0);
     }
     t2[0] = n[1] * t1[2] - n[2] * t1[1];
@@ -444,66 +483,102 @@ __device__ __forceinline__ State<T> collide(const State<T> &l, const State<T> &r
     return make_state(q0, gam, Kp3, c4k);
 }
 
-// Directional derivative of the Euler flux along axis j of the local frame:
-// dF_j(Q)[v] for the state (rho, u, E/rho + p/rho = H) and a perturbation v of the
-// conservative variables.
+// tau = 0 (smooth flow, Sec. 5.1): f = g0 (1 + A t) with g0 the Maxwellian of the
+// collided state Q0.  Its moments are exactly those of the Euler equations at Q0:
+//   F^n  = rho0 <u_n psi>_0           = F_Euler,n(Q0)
+//   dF^n = rho0 <u_n (A.psi) psi>_0   = dF_Euler,n/dQ (Q0) . Q_t,
+//   Q_t  = rho0 <(A.psi) psi>_0       = -sum_j dF_Euler,j/dQ (Q0) . dQ0/dx_j,
+// because A g0 is the time derivative of g0 once <a.u + A> = 0 fixes A, and the
+// micro-slopes of g0 represent dQ0/dx_j = (dQ_l + dQ_r)/2.  Only the collision
+// itself needs the half-space moments, and those only along the face normal, so
+// the whole evaluation stays in the global frame: the tangential velocity of each
+// side is carried by its Maxwellian unchanged.
+
+// A side's state in the global frame with the velocity component along n.
 template <class T>
-__device__ __forceinline__ void euler_jvp(int j, T gm1, const T u[3], T H, const T v[5], T out[5]) {
+struct SideG {
+    T rho, u[3], q2, i2l, lam, un;
+};
+
+template <class T>
+__device__ __forceinline__ SideG<T> side_state(const T q[5], const T n[3], T gm1) {
+    SideG<T> s;
+    s.rho = q[0];
+    const T ir = hg_rcp(q[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s.u[a] = q[1 + a] * ir;
+    s.q2 = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    const T p = gm1 * (q[4] - T(0.5) * s.rho * s.q2);
+    s.i2l = p * ir;
+    s.lam = T(0.5) * s.rho * hg_rcp(p);
+    s.un = s.u[0] * n[0] + s.u[1] * n[1] + s.u[2] * n[2];
+    return s;
+}
+
+// d F_Euler,d / dQ (Q0) . v for the direction d (|d| = 1), with u, |u|^2, H of Q0.
+template <class T>
+__device__ __forceinline__ void euler_jvp_dir(const T d[3], T gm1, const T u[3], T u2, T H, const T v[5], T out[5]) {
     const T uv = u[0] * v[1] + u[1] * v[2] + u[2] * v[3];
-    const T dp = gm1 * (v[4] - uv + T(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * v[0]);
+    const T dp = gm1 * (v[4] - uv + T(0.5) * u2 * v[0]);
+    const T vmd = v[1] * d[0] + v[2] * d[1] + v[3] * d[2];
+    const T ud = u[0] * d[0] + u[1] * d[1] + u[2] * d[2];
+    out[0] = vmd;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[1 + a] = u[a] * vmd + ud * (v[1 + a] - u[a] * v[0]) + d[a] * dp;
+    out[4] = (v[4] + dp) * ud + H * (vmd - ud * v[0]);
+}
+
+// The same along coordinate axis j.
+template <class T>
+__device__ __forceinline__ void euler_jvp_axis(int j, T gm1, const T u[3], T u2, T H, const T v[5], T out[5]) {
+    const T uv = u[0] * v[1] + u[1] * v[2] + u[2] * v[3];
+    const T dp = gm1 * (v[4] - uv + T(0.5) * u2 * v[0]);
     const T vmj = v[1 + j], uj = u[j];
     out[0] = vmj;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) out[1 + a] = u[a] * vmj + uj * v[1 + a] - uj * u[a] * v[0] + (a == j ? dp : T(0));
+    for (int a = 0; a < 3; ++a) out[1 + a] = u[a] * vmj + uj * (v[1 + a] - u[a] * v[0]) + (a == j ? dp : T(0));
     out[4] = (v[4] + dp) * uj + H * (vmj - uj * v[0]);
 }
 
-// tau = 0 (smooth flow, Sec. 5.1): f = g0 (1 + A t) with g0 the Maxwellian of the
-// collided state Q0.  Its moments are exactly those of the Euler equations at Q0:
-//   F^n  = rho0 <u psi>_0           = F_Euler,n(Q0)
-//   dF^n = rho0 <u (A.psi) psi>_0   = dF_Euler,n/dQ (Q0) . Q_t,
-//   Q_t  = rho0 <(A.psi) psi>_0     = -sum_j dF_Euler,j/dQ (Q0) . dQ0/dx_j,
-// because A g0 is the time derivative of g0 once <a_j u_j + A> = 0 fixes A, and
-// the micro-slopes a_j of g0 represent dQ0/dx_j = (dQ_l + dQ_r)/2.  Only the
-// collision itself needs the half-space moments.
 template <class T>
 __device__ __forceinline__ void gks_flux_tau0(const T ql[5], const T qr[5], const T gsum[5][3], const T n[3],
                                               const ProbDesc &P, T F[5], T dF[5]) {
-    const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma, c4k = T(4) / Kp3, gm1 = gam - T(1);
-    T t1[3], t2[3];
-    frame(n, t1, t2);
-    T Ql[5], Qr[5];
-    rot_in(ql, n, t1, t2, Ql);
-    rot_in(qr, n, t1, t2, Qr);
-    const State<T> sl = make_state(Ql, gam, Kp3, c4k), sr = make_state(Qr, gam, Kp3, c4k);
-    T ml[7], mr[7];
-    mom_half(sl, T(1), ml);
-    mom_half(sr, T(-1), mr);
-    const State<T> s0 = collide(sl, sr, ml, mr, K, gam, Kp3, c4k);
-    const T u0[3] = {s0.U, s0.V, s0.W};
-    const T E0 = T(0.5) * s0.rho * (s0.U * s0.U + s0.V * s0.V + s0.W * s0.W) + s0.p / gm1;
-    const T H0 = (E0 + s0.p) * s0.ir;
-    // Q_t = -sum_j A_j dQ0/dx_j, derivatives taken along (n, t1, t2) and rotated in
-    const T *e[3] = {n, t1, t2};
+    const T K = (T)P.K, gam = (T)P.gamma, gm1 = gam - T(1);
+    const SideG<T> sl = side_state(ql, n, gm1), sr = side_state(qr, n, gm1);
+    T ml[3], mr[3];
+    mom_half<T, 3>(sl.un, sl.lam, sl.i2l, T(1), ml);
+    mom_half<T, 3>(sr.un, sr.lam, sr.i2l, T(-1), mr);
+    // Q0 = int_{u_n>0} psi g_l + int_{u_n<0} psi g_r
+    const T wl = sl.rho * ml[0], wr = sr.rho * mr[0];
+    const T rho0 = wl + wr;
+    const T sn = sl.rho * (ml[1] - sl.un * ml[0]) + sr.rho * (mr[1] - sr.un * mr[0]);
+    T mom0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mom0[a] = wl * sl.u[a] + wr * sr.u[a] + sn * n[a];
+    const T E0 = T(0.5) * (sl.rho * ml[2] + wl * (sl.q2 - sl.un * sl.un + (K + T(2)) * sl.i2l) +
+                           sr.rho * mr[2] + wr * (sr.q2 - sr.un * sr.un + (K + T(2)) * sr.i2l));
+    const T ir0 = hg_rcp(rho0);
+    const T u0[3] = {mom0[0] * ir0, mom0[1] * ir0, mom0[2] * ir0};
+    const T u20 = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+    const T p0 = gm1 * (E0 - T(0.5) * rho0 * u20);
+    const T H0 = (E0 + p0) * ir0;
+    // Q_t = -sum_j A_j dQ0/dx_j
     T Qt[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         T d0[5], jv[5];
-        dir_deriv(gsum, e[j], n, t1, t2, T(0.5), d0);
-        euler_jvp(j, gm1, u0, H0, d0, jv);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) Qt[k] -= jv[k];
+        for (int q = 0; q < 5; ++q) d0[q] = T(0.5) * gsum[q][j];
+        euler_jvp_axis(j, gm1, u0, u20, H0, d0, jv);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Qt[q] -= jv[q];
     }
-    T Fl[5], dFl[5];
-    const T mn = s0.rho * s0.U;
-    Fl[0] = mn;
-    Fl[1] = mn * s0.U + s0.p;
-    Fl[2] = mn * s0.V;
-    Fl[3] = mn * s0.W;
-    Fl[4] = (E0 + s0.p) * s0.U;
-    euler_jvp(0, gm1, u0, H0, Qt, dFl);
-    rot_out(Fl, n, t1, t2, F);
-    rot_out(dFl, n, t1, t2, dF);
+    const T un0 = u0[0] * n[0] + u0[1] * n[1] + u0[2] * n[2];
+    F[0] = rho0 * un0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[1 + a] = F[0] * u0[a] + p0 * n[a];
+    F[4] = (E0 + p0) * un0;
+    euler_jvp_dir(n, gm1, u0, u20, H0, Qt, dF);
 }
 
 // General collision time (Eq. flux with tau > 0): the equilibrium part and both
@@ -519,8 +594,8 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     rot_in(qr, n, t1, t2, Qr);
     const State<T> sl = make_state(Ql, gam, Kp3, c4k), sr = make_state(Qr, gam, Kp3, c4k);
     T ml[7], mr[7];
-    mom_half(sl, T(1), ml);
-    mom_half(sr, T(-1), mr);
+    mom_half<T, 7>(sl.U, sl.lam, sl.i2l, T(1), ml);
+    mom_half<T, 7>(sr.U, sr.lam, sr.i2l, T(-1), mr);
     const State<T> s0 = collide(sl, sr, ml, mr, K, gam, Kp3, c4k);
     Mom<T> M0, Ml, Mr;
     mom_state(s0, K, M0);
