@@ -726,6 +726,112 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32
     }
 }
 
+// Values at the three Gauss points y[p] and gradients of the five variables of one
+// cell's reconstruction, evaluated while its coefficients stream in, so that each
+// coefficient is loaded once per face.  ADD accumulates the gradients.
+template <class T, bool ADD>
+__device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t c, const T y[3][3], T q[3][5],
+                                          T g[3][5][3]) {
+    const uint32_t nc = (uint32_t)P.nc;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        T cf[10];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            if constexpr (sizeof(T) == 8) {
+                const d2 pr = ldg<d2>(reinterpret_cast<const d2 *>(P.C) + (size_t)(v * 5 + k) * nc, c * 16u);
+                cf[2 * k] = pr.x;
+                cf[2 * k + 1] = pr.y;
+            } else {
+                const f2 pr = ldg<f2>(reinterpret_cast<const f2 *>(P.C32) + (size_t)(v * 5 + k) * nc, c * 8u);
+                cf[2 * k] = pr.x;
+                cf[2 * k + 1] = pr.y;
+            }
+        }
+        double mean = 0.0;
+        if constexpr (sizeof(T) == 4) mean = ldg<double>((stage == 1 ? P.Q : P.Qs) + (size_t)v * nc, c * 8u);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const T *yp = y[p];
+            T val = cf[0] + cf[1] * yp[0] + cf[2] * yp[1] + cf[3] * yp[2];
+            val += cf[4] * (yp[0] * yp[0]);
+            val += cf[5] * (yp[1] * yp[1]);
+            val += cf[6] * (yp[2] * yp[2]);
+            val += cf[7] * (yp[0] * yp[1]);
+            val += cf[8] * (yp[0] * yp[2]);
+            val += cf[9] * (yp[1] * yp[2]);
+            if constexpr (sizeof(T) == 8)
+                q[p][v] = val;
+            else  // FP32 form: FP64 cell mean plus FP32 deviation, rounded once
+                q[p][v] = (float)(mean + (double)val);
+            const T gx = cf[1] + T(2) * cf[4] * yp[0] + cf[7] * yp[1] + cf[8] * yp[2];
+            const T gy = cf[2] + T(2) * cf[5] * yp[1] + cf[7] * yp[0] + cf[9] * yp[2];
+            const T gz = cf[3] + T(2) * cf[6] * yp[2] + cf[8] * yp[0] + cf[9] * yp[1];
+            if constexpr (ADD) {
+                g[p][v][0] += gx; g[p][v][1] += gy; g[p][v][2] += gz;
+            } else {
+                g[p][v][0] = gx; g[p][v][1] = gy; g[p][v][2] = gz;
+            }
+        }
+    }
+}
+
+// tau = 0: one lane per face, the three Gauss points in turn.  Each lane reads
+// both cells' reconstruction records once and evaluates them at all three points
+// (the per-face loads are scattered on the right-hand side, so the address units,
+// not the arithmetic, bound this kernel: loading every record byte once per face
+// rather than once per Gauss point is what counts), then evaluates the three
+// Gauss-point fluxes and writes S * sum_G w_G (F, dF).  No LDS and no barriers.
+template <bool MIXED, bool COLOURED>
+__global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restrict__ probs,
+                                                       const Tile *__restrict__ tiles, int stage) {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    const Tile tl = tiles[blockIdx.x];
+    const ProbDesc &P = probs[tl.prob];
+    const uint32_t f = tl.begin + threadIdx.x;
+    if (f >= (uint32_t)tl.end) return;
+    const uint32_t nf = (uint32_t)P.nf;
+    const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
+    const uint32_t r = (uint32_t)ldg<int32_t>(P.fcell + nf, f * 4u);
+    const double *fg = P.fgeo;
+    const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
+                    (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+    const double S = ldg<double>(fg + (size_t)3 * nf, f * 8u);
+    T yl[3][3], yr[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            yl[p][a] = (T)ldg<double>(fg + (size_t)(4 + 3 * p + a) * nf, f * 8u);
+            yr[p][a] = (T)ldg<double>(fg + (size_t)(13 + 3 * p + a) * nf, f * 8u);
+        }
+    T qL[3][5], qR[3][5], gs[3][5][3];
+    recon_gp3<T, false>(P, stage, l, yl, qL, gs);
+    recon_gp3<T, true>(P, stage, r, yr, qR, gs);
+    const double w = S * (1.0 / 3.0);          // three Gauss points of equal weight
+    double out[10];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        T F[5], dF[5];
+        gks_flux_tau0<T>(qL[p], qR[p], gs[p], n, P, F, dF);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            out[k] = p == 0 ? w * (double)F[k] : out[k] + w * (double)F[k];
+            out[5 + k] = p == 0 ? w * (double)dF[k] : out[5 + k] + w * (double)dF[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        if constexpr (COLOURED) {
+            double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
+            stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - out[k]);
+            stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + out[k]);
+        } else {
+            stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
+        }
+    }
+}
+
 template <bool MIXED, bool TAU0, bool COLOURED>
 __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restrict__ probs,
                                                          const Tile *__restrict__ tiles, int stage) {
@@ -942,15 +1048,18 @@ void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage
 void launch_flux(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0, bool coloured,
                  hipStream_t s) {
     if (ntiles <= 0) return;
-    dim3 g(ntiles), b(3 * FACE_TILE);
-#define HGKS_FLUX(M, T0, CO) hipLaunchKernelGGL((k_flux<M, T0, CO>), g, b, 0, s, probs, tiles, stage)
-    if (coloured) {
-        if (mixed) { if (tau0) HGKS_FLUX(true, true, true); else HGKS_FLUX(true, false, true); }
-        else { if (tau0) HGKS_FLUX(false, true, true); else HGKS_FLUX(false, false, true); }
-    } else {
-        if (mixed) { if (tau0) HGKS_FLUX(true, true, false); else HGKS_FLUX(true, false, false); }
-        else { if (tau0) HGKS_FLUX(false, true, false); else HGKS_FLUX(false, false, false); }
+    if (tau0) {
+        dim3 g(ntiles), b(FACE_TILE);
+#define HGKS_FLUX0(M, CO) hipLaunchKernelGGL((k_flux_t0<M, CO>), g, b, 0, s, probs, tiles, stage)
+        if (coloured) { if (mixed) HGKS_FLUX0(true, true); else HGKS_FLUX0(false, true); }
+        else { if (mixed) HGKS_FLUX0(true, false); else HGKS_FLUX0(false, false); }
+#undef HGKS_FLUX0
+        return;
     }
+    dim3 g(ntiles), b(3 * FACE_TILE);
+#define HGKS_FLUX(M, CO) hipLaunchKernelGGL((k_flux<M, false, CO>), g, b, 0, s, probs, tiles, stage)
+    if (coloured) { if (mixed) HGKS_FLUX(true, true); else HGKS_FLUX(false, true); }
+    else { if (mixed) HGKS_FLUX(true, false); else HGKS_FLUX(false, false); }
 #undef HGKS_FLUX
 }
 
