@@ -35,15 +35,16 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
 
 # Algorithmic bytes each kernel must move, per unit (cell or face), FP64 form:
 #   weno   per cell: 16 stencil ids (64) + own state (40) + big-stencil pseudo-inverse
-#          9x16 (1152) + sub-stencil pseudo-inverses 4x3x6 (576) + 1/h and second
-#          moments (56) + reconstruction written (400)                       = 2288
+#          9x16 (1152) + 1/h and second moments (56) + own centroid (24) + slot image
+#          codes (16) + reconstruction written (400)                           = 1752
+#          (the sub-stencil fits are formed on the device from the centroids)
 #   flux   per face: cells (8) + normal, area, Gauss offsets (176) + flux written (80)
 #          = 264, plus per cell the reconstruction read once (400)
 #   update per cell: face ids (16) + its faces' fluxes (2 faces' worth, 160) + 1/|V|
 #          and h (16) + state traffic (stage 1: 3 x 40, stage 2: 2 x 40)       ~ 292
 def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool) -> float:
     if kernel == "weno":
-        return nc * (64 + 40 + 1152 + 576 + 56 + (200 if mixed else 400))
+        return nc * (64 + 40 + 1152 + 56 + 24 + 16 + (200 if mixed else 400))
     if kernel == "flux":
         return nf * 264 + nc * ((200 + 40) if mixed else 400)
     if kernel == "update":

@@ -38,7 +38,7 @@ void xcd_order(std::vector<T> &tiles, size_t b, size_t e) {
 }
 
 struct Layout {
-    size_t sten, pinv0, pinvs, cgeo, cface, fcell, fgeo, Q, Qs, R, C, C32, FF, acc, dtpart, scal, desc, tiles, total;
+    size_t sten, pinv0, cen, sshift, cgeo, cface, fcell, fgeo, Q, Qs, R, C, C32, FF, acc, dtpart, scal, desc, tiles, total;
 };
 
 Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, bool mixed, bool coloured) {
@@ -47,7 +47,8 @@ Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, bool mixed
     auto take = [&](size_t bytes) { size_t p = o; o += up(bytes); return p; };
     L.sten = take((size_t)SLOTS * nc * 4);
     L.pinv0 = take((size_t)144 * nc * 8);
-    L.pinvs = take((size_t)72 * nc * 8);
+    L.cen = take((size_t)3 * nc * 8);
+    L.sshift = take((size_t)4 * nc * 4);
     L.cgeo = take((size_t)CGEO * nc * 8);
     L.cface = take((size_t)4 * nc * 4);
     L.fcell = take((size_t)2 * nf * 4);
@@ -305,7 +306,9 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     D.n_cell_tiles = (int32_t)ct.size();
     D.sten = (const int32_t *)(B + L.sten);
     D.pinv0 = (const double *)(B + L.pinv0);
-    D.pinvs = (const double *)(B + L.pinvs);
+    D.cen = (const double *)(B + L.cen);
+    D.sshift = (const uint32_t *)(B + L.sshift);
+    for (int a = 0; a < 3; ++a) D.per[a] = (period && period[a] > 0.0) ? period[a] : 0.0;
     D.cgeo = (const double *)(B + L.cgeo);
     D.cface = (const int32_t *)(B + L.cface);
     D.fcell = (const int32_t *)(B + L.fcell);
@@ -343,7 +346,8 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     };
     HIPCHK(c, h2d(D.sten, hm.sten.data(), hm.sten.size() * 4));
     HIPCHK(c, h2d(D.pinv0, hm.pinv0.data(), hm.pinv0.size() * 8));
-    HIPCHK(c, h2d(D.pinvs, hm.pinvs.data(), hm.pinvs.size() * 8));
+    HIPCHK(c, h2d(D.cen, hm.cen.data(), hm.cen.size() * 8));
+    HIPCHK(c, h2d(D.sshift, hm.sshift.data(), hm.sshift.size() * 4));
     HIPCHK(c, h2d(D.cgeo, hm.cgeo.data(), hm.cgeo.size() * 8));
     HIPCHK(c, h2d(D.cface, hm.cface.data(), hm.cface.size() * 4));
     HIPCHK(c, h2d(D.fcell, hm.fcell.data(), hm.fcell.size() * 4));

@@ -10,8 +10,11 @@
 //                                zero weight), so sub-stencil membership is static
 //   pinv0  double [72][nc][2]    big-stencil pseudo-inverse, 9 rows x 16 slots;
 //                                element (r, s) in pair r*8 + s/2, lane s%2
-//   pinvs  double [36][nc][2]    sub-stencil pseudo-inverses, 4 x 3 rows x 6 members;
-//                                element ((m*3+k)*6+t) in pair e/2, lane e%2
+//   cen    double [3][nc]        cell centroids (the sub-stencil fits are formed on
+//                                the device from them)
+//   sshift uint32 [4][nc]        periodic image of each stencil slot: byte s%4 of word
+//                                s/4 holds (sx+2) + 5 (sy+2) + 25 (sz+2), the member
+//                                sits at its centroid + (sx, sy, sz) * period
 //   cgeo   double [9][nc]        1/h, scaled second moments (xx,yy,zz,xy,xz,yz),
 //                                1/|Omega|, h_dt = 6|Omega|/sum S
 //   cface  int32  [4][nc]        (face << 1) | (cell is the face's right cell)
@@ -51,7 +54,8 @@ struct HostMesh {
     std::vector<int64_t> perm;      // internal cell c holds caller cell perm[c]
     std::vector<int32_t> sten;      // [16][nc]
     std::vector<double> pinv0;      // [72][nc][2]
-    std::vector<double> pinvs;      // [36][nc][2]
+    std::vector<double> cen;        // [3][nc]
+    std::vector<uint32_t> sshift;   // [4][nc]
     std::vector<double> cgeo;       // [9][nc]
     std::vector<int32_t> cface;     // [4][nc]
     std::vector<int32_t> fcell;     // [2][nf]

@@ -14,7 +14,8 @@ struct ProbDesc {
     int32_t n_cell_tiles, pad0;
     const int32_t *sten;
     const double *pinv0;
-    const double *pinvs;
+    const double *cen;            // centroids [3][nc]
+    const uint32_t *sshift;       // periodic image codes of the stencil slots [4][nc]
     const double *cgeo;
     const int32_t *cface;
     const int32_t *fcell;
@@ -30,6 +31,7 @@ struct ProbDesc {
     double *dt;         // [0] dt of the current step
     double *time;       // [0] simulated time
     int32_t *flag;      // [0] non-physical state seen
+    double per[3];                // period per axis (0: not periodic)
     double gamma, K, weno_eps, gamma_lin, cfl, tau_eps, tau_C;
     int32_t tau_mode, mixed;
 };

@@ -1,15 +1,16 @@
 // HIP kernels of the HGKS S2O4 step for gfx950 (CDNA4, 64-lane wavefronts).
 //
 //   k_weno     third-order least-squares WENO per cell (Sec. 2.3).  A workgroup
-//              holds 64 cells and five waves, one per conserved variable: the
-//              non-linear weights are per variable, so the waves never talk to
-//              each other and each lane keeps only 9 + 12 accumulators.  The
-//              pseudo-inverses stream from HBM once (the five waves of a
-//              workgroup read the same lines, served by L1/L2).
-//   k_flux     gas-kinetic flux at the face Gauss points (Sec. 2.1 Eq. flux,
-//              Sec. 2.2 time fit).  A workgroup holds 64 faces and three waves,
-//              one per Gauss point; the three contributions meet in LDS and one
-//              wave writes S * sum_G w_G (F, dF) per face.
+//              takes WC cells: its threads first copy the cells' pseudo-inverse
+//              rows into LDS (streamed from HBM once, the dominant traffic of the
+//              step), then lane (v, c) forms variable v of cell c.  The non-linear
+//              weights are per variable, so lanes never talk to each other.
+//   k_flux_t0  gas-kinetic flux at tau = 0 (Sec. 2.1 Eq. flux, Sec. 2.2 time
+//              fit, Sec. 5.1): one lane per face loads both reconstruction
+//              records once, evaluates them at the three Gauss points and writes
+//              S * sum_G w_G (F, dF).
+//   k_flux     the same for tau > 0: one wave per Gauss point, the three
+//              contributions summed through LDS.
 //   k_update   S2O4 stage update (Sec. 2.2).  Each cell gathers its four face
 //              fluxes in a fixed order: deterministic, no atomics.  The second
 //              stage also forms the next step's CFL bound per tile.
@@ -29,7 +30,7 @@
 #include "erfcx_table.h"
 
 #ifndef HGKS_WENO_CELLS
-#define HGKS_WENO_CELLS 32
+#define HGKS_WENO_CELLS 16
 #endif
 
 namespace hgks {
@@ -58,7 +59,16 @@ template <class T>
 __device__ __forceinline__ void stg(void *base, uint32_t off, const T &v) {
     *(gptr<T>)((gptr<char>)base + off) = v;
 }
+// Streaming load: the data is used once, so it should not displace reusable lines.
+__device__ __forceinline__ d2 ldg_stream(const void *base, uint32_t off) {
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    const v2d v = __builtin_nontemporal_load((gptr<const v2d>)((gptr<const char>)base + off));
+    return {v.x, v.y};
+}
 #else
+__device__ __forceinline__ d2 ldg_stream(const void *base, uint32_t off) {
+    return *(const d2 *)((const char *)base + off);
+}
 template <class T>
 __device__ __forceinline__ T ldg(const void *base, uint32_t off) {
     return *(const T *)((const char *)base + off);
@@ -193,12 +203,72 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
     }
 }
 
-// Pseudo-inverse pair rows: 72 of the big stencil (row r, slots 2s, 2s+1 at pair
-// r*8+s), then 36 of the sub-stencils.  A workgroup handles WC cells: all its
-// threads first copy the WC cells' 108 pair rows into LDS (every value is read
-// from HBM once), one barrier, then lane (v, c) forms variable v of cell c from
-// LDS.  Five variables x WC cells are spread over whole waves; spare lanes only
-// help with the copy.
+// The linear least-squares fit of sub-stencil m of cell i (Sec. 2.3), formed on the
+// device: member t (slot s(m, t)) has the row a_t = (c_k + image shift - c_i)/h_i,
+// the mean of the scaled linear basis over the member (the basis has zero mean over
+// the cell itself), and the pseudo-inverse is (A^T A)^-1 A^T over the distinct
+// members; a member met twice gets a zero column.  The 3x3 normal matrix is
+// inverted through its adjugate.  out[k][t]: row k (d/dxi_k), member t.
+__device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, uint32_t m, double out[3][6]) {
+    const size_t nc = (size_t)P.nc;
+    // first-layer slots of sub-stencil m, four bits each: SUBFIRST[m][t]
+    constexpr uint64_t FIRST = (uint64_t)SUBFIRST[0][0] | (uint64_t)SUBFIRST[0][1] << 4 |
+                               (uint64_t)SUBFIRST[0][2] << 8 | (uint64_t)SUBFIRST[1][0] << 12 |
+                               (uint64_t)SUBFIRST[1][1] << 16 | (uint64_t)SUBFIRST[1][2] << 20 |
+                               (uint64_t)SUBFIRST[2][0] << 24 | (uint64_t)SUBFIRST[2][1] << 28 |
+                               (uint64_t)SUBFIRST[2][2] << 32 | (uint64_t)SUBFIRST[3][0] << 36 |
+                               (uint64_t)SUBFIRST[3][1] << 40 | (uint64_t)SUBFIRST[3][2] << 44;
+    const double ih = P.cgeo[i];
+    const double ci[3] = {P.cen[i], P.cen[nc + i], P.cen[2 * nc + i]};
+    const uint32_t w0 = P.sshift[i], w1 = P.sshift[nc + i], w2 = P.sshift[2 * nc + i], w3 = P.sshift[3 * nc + i];
+    double A[6][3];
+    int32_t id[6];
+    uint32_t code[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const uint32_t sl = t < 3 ? (uint32_t)(FIRST >> (12 * m + 4 * t)) & 15u : 4u + 3u * m + (uint32_t)(t - 3);
+        const uint32_t wsel = sl >> 2;
+        const uint32_t word = wsel == 0 ? w0 : (wsel == 1 ? w1 : (wsel == 2 ? w2 : w3));
+        code[t] = (word >> (8 * (sl & 3u))) & 0xFFu;
+        id[t] = P.sten[sl * nc + i];
+        const int sh[3] = {(int)(code[t] % 5u) - 2, (int)((code[t] / 5u) % 5u) - 2, (int)(code[t] / 25u) - 2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A[t][a] = (P.cen[a * nc + (size_t)id[t]] + (double)sh[a] * P.per[a] - ci[a]) * ih;
+    }
+    bool dup[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        dup[t] = false;
+#pragma unroll
+        for (int u = 0; u < t; ++u) dup[t] = dup[t] || (id[u] == id[t] && code[u] == code[t]);
+    }
+    double n00 = 0, n01 = 0, n02 = 0, n11 = 0, n12 = 0, n22 = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const double x = dup[t] ? 0.0 : A[t][0], y = dup[t] ? 0.0 : A[t][1], z = dup[t] ? 0.0 : A[t][2];
+        n00 = fma(x, x, n00); n01 = fma(x, y, n01); n02 = fma(x, z, n02);
+        n11 = fma(y, y, n11); n12 = fma(y, z, n12); n22 = fma(z, z, n22);
+    }
+    const double c00 = n11 * n22 - n12 * n12, c01 = n02 * n12 - n01 * n22, c02 = n01 * n12 - n02 * n11;
+    const double c11 = n00 * n22 - n02 * n02, c12 = n01 * n02 - n00 * n12, c22 = n00 * n11 - n01 * n01;
+    const double idet = 1.0 / (n00 * c00 + n01 * c01 + n02 * c02);
+    const double inv[3][3] = {{c00 * idet, c01 * idet, c02 * idet},
+                              {c01 * idet, c11 * idet, c12 * idet},
+                              {c02 * idet, c12 * idet, c22 * idet}};
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            out[k][t] = dup[t] ? 0.0 : inv[k][0] * A[t][0] + inv[k][1] * A[t][1] + inv[k][2] * A[t][2];
+}
+
+// Pseudo-inverse pair rows in LDS: 72 of the big stencil (row r, slots 2s, 2s+1 at
+// pair r*8+s), then 36 of the sub-stencils (row k of sub-stencil m, members 2u,
+// 2u+1 at pair 72+(m*3+k)*3+u).  A workgroup handles WC cells: its threads copy
+// the WC cells' big-stencil rows from HBM (streamed, each value read once) while
+// 4 WC of them form the sub-stencil fits from the centroids, one barrier, then
+// lane (v, c) forms variable v of cell c from LDS.  Five variables x WC cells are
+// spread over whole waves; spare lanes only help with the copy.
 constexpr int WPAIRS0 = 72, WPAIRS = 108;
 
 template <int WC>
@@ -209,6 +279,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
                                                               const Tile *__restrict__ tiles, int stage) {
     constexpr int NT = weno_threads<WC>();
     constexpr int SPLIT = WENO_TILE / WC;              // workgroups per cell tile
+    static_assert(4 * WC <= NT, "one sub-stencil fit per thread");
     __shared__ d2 stage_buf[WPAIRS][WC];
     const Tile tl = tiles[blockIdx.x / SPLIT];
     const ProbDesc &P = probs[tl.prob];
@@ -216,23 +287,31 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     const uint32_t c0 = tl.begin + (blockIdx.x % SPLIT) * WC;   // first cell of this workgroup
     const uint32_t last = (uint32_t)tl.end - 1;
     const d2 *p0 = reinterpret_cast<const d2 *>(P.pinv0);
-    const d2 *ps = reinterpret_cast<const d2 *>(P.pinvs);
-    // 1. copy the pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the tile) into LDS
-    constexpr int PER = (WPAIRS * WC + NT - 1) / NT;
+    // 1. stream the big-stencil pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the tile)
+    constexpr int PER = (WPAIRS0 * WC + NT - 1) / NT;
     d2 reg[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(WPAIRS * WC)) {
+        if (e < (uint32_t)(WPAIRS0 * WC)) {
             const uint32_t row = e / WC, c = min(c0 + e % WC, last);
-            const d2 *base = row < (uint32_t)WPAIRS0 ? p0 + (size_t)row * nc : ps + (size_t)(row - WPAIRS0) * nc;
-            reg[k] = ldg<d2>(base, c * 16u);
+            reg[k] = ldg_stream(p0 + (size_t)row * nc, c * 16u);
         }
+    }
+    // 2. the sub-stencil fits: thread (m, c) for m < 4
+    if (threadIdx.x < 4u * WC) {
+        const uint32_t m = threadIdx.x / WC, cs = threadIdx.x % WC;
+        double ps[3][6];
+        sub_stencil_pinv(P, min(c0 + cs, last), m, ps);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) stage_buf[WPAIRS0 + (m * 3 + k) * 3 + u][cs] = d2{ps[k][2 * u], ps[k][2 * u + 1]};
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(WPAIRS * WC)) stage_buf[e / WC][e % WC] = reg[k];
+        if (e < (uint32_t)(WPAIRS0 * WC)) stage_buf[e / WC][e % WC] = reg[k];
     }
     // 2. this lane's variable and cell; gather the stencil differences meanwhile
     const uint32_t v = threadIdx.x / WC, cl = threadIdx.x % WC;
@@ -786,7 +865,9 @@ template <bool MIXED, bool COLOURED>
 __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restrict__ probs,
                                                        const Tile *__restrict__ tiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
-    const Tile tl = tiles[blockIdx.x];
+    // tiles in reverse order: the reconstruction records written last by the WENO
+    // pass are the likeliest still to sit in the last-level cache
+    const Tile tl = tiles[gridDim.x - 1 - blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
     const uint32_t f = tl.begin + threadIdx.x;
     if (f >= (uint32_t)tl.end) return;
@@ -1034,7 +1115,7 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 // ----------------------------------------------------------------------------
 // launch wrappers
 // ----------------------------------------------------------------------------
-constexpr int WENO_CELLS = HGKS_WENO_CELLS;     // cells per WENO workgroup (32 or 64)
+constexpr int WENO_CELLS = HGKS_WENO_CELLS;     // cells per WENO workgroup (16, 32 or 64)
 
 void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
     if (ntiles <= 0) return;

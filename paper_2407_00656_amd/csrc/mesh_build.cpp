@@ -491,7 +491,8 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
     out.perm = perm;
     out.sten.assign((size_t)SLOTS * nc, 0);
     out.pinv0.assign((size_t)144 * nc, 0.0);
-    out.pinvs.assign((size_t)72 * nc, 0.0);
+    out.cen.assign((size_t)3 * nc, 0.0);
+    out.sshift.assign((size_t)4 * nc, 0u);
     out.cgeo.assign((size_t)CGEO * nc, 0.0);
     out.cface.assign((size_t)4 * nc, 0);
     out.fcell.assign((size_t)2 * nf, 0);
@@ -507,7 +508,12 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             for (int r = 0; r < 9; ++r)
                 for (int s = 0; s < SLOTS; ++s)
                     out.pinv0[(((size_t)(r * 8 + s / 2)) * nc + c) * 2 + (s & 1)] = P0[(o * 9 + r) * SLOTS + s];
-            for (int e2 = 0; e2 < 72; ++e2) out.pinvs[(((size_t)(e2 / 2)) * nc + c) * 2 + (e2 & 1)] = PS[o * 72 + e2];
+            for (int a = 0; a < 3; ++a) out.cen[(size_t)a * nc + c] = comp(cen[o], a);
+            for (int s = 0; s < SLOTS; ++s) {
+                const Member &x = slot[o][s];
+                const uint32_t code = (uint32_t)((x.s[0] + 2) + 5 * (x.s[1] + 2) + 25 * (x.s[2] + 2));
+                out.sshift[(size_t)(s / 4) * nc + c] |= code << (8 * (s % 4));
+            }
             double h = std::cbrt(vol[o]);
             out.cgeo[0 * (size_t)nc + c] = 1.0 / h;
             for (int q = 0; q < 6; ++q) out.cgeo[(size_t)(1 + q) * nc + c] = smom[o][q] / (h * h);
