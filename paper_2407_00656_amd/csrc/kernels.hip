@@ -281,10 +281,25 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     constexpr int SPLIT = WENO_TILE / WC;              // workgroups per cell tile
     static_assert(4 * WC <= NT, "one sub-stencil fit per thread");
     __shared__ d2 stage_buf[WPAIRS][WC];
-    const Tile tl = tiles[blockIdx.x / SPLIT];
+    // Workgroups go to the eight XCDs round-robin by id, and the tile table is laid
+    // out so that XCD x owns a contiguous run of tiles when each tile has one
+    // workgroup.  A tile here has SPLIT workgroups, so renumber: XCD x takes a
+    // contiguous run of (tile, part) units in cell order, and the tile's slot in
+    // the table is found by inverting that layout.
+    const uint32_t nb = gridDim.x, xcd = blockIdx.x & 7u;
+    const uint32_t bx = xcd * (nb >> 3) + min(xcd, nb & 7u) + (blockIdx.x >> 3);
+    const uint32_t jt = bx / SPLIT, nt = nb / SPLIT;
+    uint32_t kt = jt;
+    if (nt >= 16u) {
+        const uint32_t q8 = nt >> 3, r8 = nt & 7u, big = r8 * (q8 + 1u);
+        const uint32_t xx = jt < big ? jt / (q8 + 1u) : r8 + (jt - big) / q8;
+        const uint32_t qq = jt < big ? jt % (q8 + 1u) : (jt - big) % q8;
+        kt = 8u * qq + xx;
+    }
+    const Tile tl = tiles[kt];
     const ProbDesc &P = probs[tl.prob];
     const uint32_t nc = (uint32_t)P.nc;
-    const uint32_t c0 = tl.begin + (blockIdx.x % SPLIT) * WC;   // first cell of this workgroup
+    const uint32_t c0 = tl.begin + (bx % SPLIT) * WC;   // first cell of this workgroup
     const uint32_t last = (uint32_t)tl.end - 1;
     const d2 *p0 = reinterpret_cast<const d2 *>(P.pinv0);
     // 1. stream the big-stencil pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the tile)
