@@ -24,7 +24,9 @@
  *     normal equations + Cholesky;
  *   - the slopes of the equilibrium state use dQ0 = (dQ_l + dQ_r)/2;
  *   - tau = 0 (smooth flow, Sec. 5.1) or tau = eps*dt + C*|pl-pr|/(pl+pr)*dt;
- *   - dt = CFL * min_i h_i / (|U_i| + c_i), h_i = 6|Omega_i| / sum_p S_ip.
+ *   - dt = CFL * min_i h_i / (|U_i| + c_i), h_i = 6|Omega_i| / sum_p S_ip;
+ *   - positivity fallback at Gauss points (a non-physical reconstructed side takes
+ *     its cell average with zero gradient), which acts only at discontinuities.
  *
  * Conventions: cells are 0-based; face p of a tetrahedron is the one opposite
  * its node p (Sec. 3.1 item 1); the neighbour across face p is "i_{p+1}" of
@@ -870,6 +872,24 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
  * cell's four faces runs in local face order, so the result does not depend on
  * the thread count.
  */
+/*
+ * Positivity fallback (not in the paper, which has no limiter): a side whose
+ * reconstructed state at the Gauss point has rho <= 0 or p <= 0 takes its cell
+ * average with zero gradient there.  It never acts in smooth flow; at a strong
+ * discontinuity (the shock tube) the quadratic reconstruction would otherwise
+ * hand the flux a state with negative pressure on the first step.
+ */
+static void gauss_point_fallback(const orc_params *p, const double *qcell, double *v, double g[5][3]) {
+    const double rho = v[0];
+    const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+    const double pr = (p->gamma - 1.0) * (v[4] - ke);
+    if (rho > 0.0 && pr > 0.0) return;
+    for (int q = 0; q < 5; ++q) {
+        v[q] = qcell[q];
+        g[q][0] = g[q][1] = g[q][2] = 0.0;
+    }
+}
+
 int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, double *L, double *dL) {
     orc_weno *W = malloc(sizeof(orc_weno) * m->nc);
     double (*FF)[10] = malloc(sizeof(double[10]) * m->nf);   /* S * sum_G w_G (F, dF) per face */
@@ -889,6 +909,8 @@ int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, 
                 for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
                 weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
                 weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+                gauss_point_fallback(p, Q + 5 * l, vl, gl);
+                gauss_point_fallback(p, Q + 5 * r, vr, gr);
                 int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
                 if (r_ > rc) rc = r_;
                 for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
@@ -1071,6 +1093,8 @@ static int rhs_subset(const orc_mesh *m, const orc_params *p, const double *Q, d
                 for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
                 weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
                 weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+                gauss_point_fallback(p, Q + 5 * l, vl, gl);
+                gauss_point_fallback(p, Q + 5 * r, vr, gr);
                 int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
                 if (r_ > rc) rc = r_;
                 for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }

@@ -80,31 +80,38 @@ class TetMesh:
         return int(self.nodes.shape[0])
 
 
-def kuhn_box(n: int, box: float = 2.0, jitter: float = 0.1, seed: int = SEED_ADVECTION,
+def kuhn_box(n, box=2.0, jitter: float = 0.1, seed: int = SEED_ADVECTION,
              periodic=(True, True, True)) -> TetMesh:
-    """6*n^3 Kuhn tetrahedra in [0, box]^3, jittered from `seed`."""
-    if n < 4:
-        raise ValueError("kuhn_box needs n >= 4 (two-layer stencils must not wrap onto themselves)")
+    """6 nx ny nz Kuhn tetrahedra in [0, Lx] x [0, Ly] x [0, Lz], jittered from `seed`.
+
+    `n` is the number of cubes per axis (an int for a cubic lattice, or a triple) and
+    `box` the box length (a float, or a triple).  Interior nodes move by
+    U(-jitter h_a, jitter h_a) per component a; nodes on the box faces do not move.
+    """
+    nv = np.array([n, n, n] if np.isscalar(n) else list(n), dtype=np.int64)
+    bv = np.array([box, box, box] if np.isscalar(box) else list(box), dtype=np.float64)
+    if np.any(nv < 4):
+        raise ValueError("kuhn_box needs n >= 4 per axis (two-layer stencils must not wrap onto themselves)")
     periodic = tuple(bool(p) for p in periodic)
-    h = box / n
-    dims = np.array([n if p else n + 1 for p in periodic], dtype=np.int64)
+    h = bv / nv
+    dims = np.array([nv[a] if periodic[a] else nv[a] + 1 for a in range(3)], dtype=np.int64)
     ix, iy, iz = np.meshgrid(np.arange(dims[0]), np.arange(dims[1]), np.arange(dims[2]), indexing="ij")
     idx = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)          # node id order
-    nodes = idx.astype(np.float64) * h
-    interior = np.all((idx % n) != 0, axis=1)
+    nodes = idx.astype(np.float64) * h[None, :]
+    interior = np.all((idx % nv[None, :]) != 0, axis=1)
     if jitter > 0.0:
         u = uniform01(seed, 3 * idx.shape[0]).reshape(-1, 3)
-        nodes = nodes + np.where(interior[:, None], (2.0 * u - 1.0) * jitter * h, 0.0)
+        nodes = nodes + np.where(interior[:, None], (2.0 * u - 1.0) * jitter * h[None, :], 0.0)
 
     def node_id(a, b, c):
         return (a * dims[1] + b) * dims[2] + c
 
-    ci, cj, ck = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ci, cj, ck = np.meshgrid(np.arange(nv[0]), np.arange(nv[1]), np.arange(nv[2]), indexing="ij")
     base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)          # cube order (i, j, k)
     n_cubes = base.shape[0]
     cell_nodes = np.empty((n_cubes, 6, 4), dtype=np.int64)
     cell_vertices = np.empty((n_cubes, 6, 4, 3), dtype=np.float64)
-    period = np.array([box if p else 0.0 for p in periodic])
+    period = np.array([bv[a] if periodic[a] else 0.0 for a in range(3)])
     for s, perm in enumerate(KUHN_PERMS):
         off = np.zeros(3, dtype=np.int64)
         for v in range(4):
@@ -115,14 +122,17 @@ def kuhn_box(n: int, box: float = 2.0, jitter: float = 0.1, seed: int = SEED_ADV
             wrap = np.zeros_like(lat)
             for a in range(3):
                 if periodic[a]:
-                    wrap[:, a] = lat[:, a] // n
-            li = lat - wrap * n
+                    wrap[:, a] = lat[:, a] // nv[a]
+            li = lat - wrap * nv[None, :]
             nid = node_id(li[:, 0], li[:, 1], li[:, 2])
             cell_nodes[:, s, v] = nid
             cell_vertices[:, s, v, :] = nodes[nid] + wrap * period
+    cubic = bool(np.all(nv == nv[0]) and np.all(bv == bv[0]))
     return TetMesh(nodes=nodes, cell_nodes=cell_nodes.reshape(-1, 4),
                    period=period, cell_vertices=cell_vertices.reshape(-1, 4, 3),
-                   n=n, box=box, meta={"seed": seed, "jitter": jitter, "periodic": periodic})
+                   n=int(nv[0]) if cubic else 0, box=float(bv[0]) if cubic else 0.0,
+                   meta={"seed": seed, "jitter": jitter, "periodic": periodic, "n": tuple(int(x) for x in nv),
+                         "box": tuple(float(x) for x in bv)})
 
 
 def tet_rule(npts: int):
@@ -218,6 +228,48 @@ def uniform_state(n_cells: int, rho=1.0, vel=(0.3, -0.2, 0.5), p=1.0, gamma=1.4)
     q[:, 1:4] = rho * u
     q[:, 4] = p / (gamma - 1.0) + 0.5 * rho * float(u @ u)
     return q
+
+
+@dataclass
+class SodCase:
+    """Sod's shock tube along x ((rho, p) = (1, 1) | (0.125, 0.1), zero velocity,
+    gamma 1.4; the shock-tube workload of this build, not a case of the paper), laid
+    out periodically: the high state fills
+    [x0, x0 + half) of the period [0, 2 half) and the low state the rest, so the
+    slab [x0 + half/2, x0 + 3 half/2) holds one standard tube with its diaphragm at
+    x0 + half and the other half its mirror image.  Until the waves of the two
+    diaphragms meet (t < half / (2 * shock speed), 0.286 for half = 1) the
+    solution on each half equals the tube with transmissive ends.  Each cell takes
+    the state on its centroid's side (no cut-cell averaging)."""
+    rho_l: float = 1.0
+    p_l: float = 1.0
+    rho_r: float = 0.125
+    p_r: float = 0.1
+    x0: float = 0.5
+    half: float = 1.0
+    gamma: float = 1.4
+
+    def high(self, x: np.ndarray) -> np.ndarray:
+        xm = np.mod(x - self.x0, 2.0 * self.half)
+        return xm < self.half
+
+    def conservative(self, mesh: TetMesh) -> np.ndarray:
+        cx = mesh.cell_vertices[:, :, 0].mean(axis=1)
+        hi = self.high(cx)
+        rho = np.where(hi, self.rho_l, self.rho_r)
+        p = np.where(hi, self.p_l, self.p_r)
+        q = np.zeros((cx.shape[0], 5))
+        q[:, 0] = rho
+        q[:, 4] = p / (self.gamma - 1.0)
+        return q
+
+
+def sod_box(nx: int, ny: int, nz: int, jitter: float = 0.1, seed: int = SEED_ADVECTION + 7):
+    """The periodic doubled Sod tube: [0, 2] x [0, ny/nx * 2] x [0, nz/nx * 2] with cubes
+    of edge 2/nx, every axis periodic."""
+    h = 2.0 / nx
+    mesh = kuhn_box((nx, ny, nz), (2.0, ny * h, nz * h), jitter, seed)
+    return mesh, SodCase()
 
 
 def error_norms(mesh_volumes: np.ndarray, num: np.ndarray, exact: np.ndarray) -> dict:
