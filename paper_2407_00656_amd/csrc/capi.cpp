@@ -197,10 +197,10 @@ void enqueue_step(hgks_ctx *c, double dt_fixed) {
         if (col) {
             for (size_t k = 0; k + 1 < c->colour_tiles.size(); ++k) {
                 int t0 = c->colour_tiles[k], t1 = c->colour_tiles[k + 1];
-                timed(c, 2, [&] { launch_flux(c->d_desc, c->d_ftiles + t0, t1 - t0, stage, mixed, tau0, true, s); });
+                timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles + t0, t1 - t0, stage, mixed, tau0, true, s); });
             }
         } else {
-            timed(c, 2, [&] { launch_flux(c->d_desc, c->d_ftiles, c->n_ftiles, stage, mixed, tau0, false, s); });
+            timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles, c->n_ftiles, stage, mixed, tau0, false, s); });
         }
         timed(c, 3, [&] { launch_update(c->d_desc, c->d_ctiles, c->n_ctiles, stage, col, s); });
     }
@@ -384,10 +384,10 @@ hgks_status hgks_init_state(hgks_ctx *c, const double *q, double t0) {
     }
     HIPCHK(c, hipSetDevice(c->device));
     double scal[3] = {0.0, t0, 0.0};
-    int32_t zero = 0;
+    int32_t zero[2] = {0, 0};     // non-physical flag, flux fix-up flag
     HIPCHK(c, hipMemcpyAsync(c->desc.Q, soa.data(), soa.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->desc.dt, scal, 16, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->desc.flag, &zero, 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->desc.flag, zero, 8, hipMemcpyHostToDevice, c->stream));
     launch_dt_local(c->d_desc, c->d_ctiles, c->n_ctiles, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -671,7 +671,7 @@ hgks_status hgks_pool_step(hgks_pool *p, const int *slots, int n, int32_t nsteps
         launch_dt_final(p->d_probs, p->nprobs, 0.0, s);
         for (int stage = 1; stage <= 2; ++stage) {
             for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.mixed, s);
-            for (auto &g : p->groups) launch_flux(p->d_probs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.mixed, g.tau0, false, s);
+            for (auto &g : p->groups) launch_flux(p->d_probs, p->nprobs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.mixed, g.tau0, false, s);
             launch_update(p->d_probs, p->d_ct, p->n_ct, stage, false, s);
         }
     }

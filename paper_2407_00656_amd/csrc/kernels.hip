@@ -108,6 +108,9 @@ __device__ __forceinline__ double hg_rsqrt(double x) {
     return y;
 }
 __device__ __forceinline__ float hg_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+// the bare hardware estimate (NaN for x < 0, infinity at 0)
+__device__ __forceinline__ double hg_rsq_raw(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float hg_rsq_raw(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // erfcx(a) = exp(a^2) erfc(a) for a >= 0: Chebyshev series in t = (a - k)/(a + k),
 // summed by Clenshaw's recurrence (the coefficients come from gen_erfcx_table.py).
@@ -604,7 +607,10 @@ __device__ __forceinline__ SideG<T> side_state(const T q[5], const T n[3], T gm1
     s.q2 = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
     const T p = gm1 * (q[4] - T(0.5) * s.rho * s.q2);
     s.i2l = p * ir;
-    s.lam = T(0.5) * s.rho * hg_rcp(p);
+    // lam <= 0 (p <= 0 with rho > 0) makes the half-space moments NaN; rho <= 0 is
+    // sent the same way (0 * rho^-1/2 is NaN for rho <= 0), so every non-physical
+    // side yields a non-finite flux
+    s.lam = T(0.5) * s.rho * hg_rcp(p) + T(0) * hg_rsq_raw(s.rho);
     s.un = s.u[0] * n[0] + s.u[1] * n[1] + s.u[2] * n[2];
     return s;
 }
@@ -778,6 +784,23 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     rot_out(dFl, n, t1, t2, dF);
 }
 
+// Positivity fallback (not in the paper, which has no limiter): at a Gauss point
+// where the reconstructed state of either side has rho <= 0 or p <= 0, the point
+// is first order: both gradients are zero and each non-physical side takes its
+// cell average.  It acts only at strong discontinuities.
+template <class T>
+__device__ __forceinline__ bool physical_point(const T q[5]) {
+    // p > 0  <=>  2 rho E > |rho u|^2 (for rho > 0); no division needed
+    return q[0] > T(0) && T(2) * q[0] * q[4] > q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+}
+
+template <class T>
+__device__ __forceinline__ void cell_mean(const ProbDesc &P, int stage, uint32_t c, T q[5]) {
+    const double *Qa = stage == 1 ? P.Q : P.Qs;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = (T)ldg<double>(Qa + (size_t)v * P.nc, c * 8u);
+}
+
 // Value and gradient of a cell's reconstruction at offset y from its centroid;
 // ADD accumulates the gradient into g (tau = 0 needs only the sum of both sides).
 template <class T, bool ADD>
@@ -870,6 +893,44 @@ __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t
     }
 }
 
+// The tau = 0 flux of face f with the positivity fallback, one Gauss point at a
+// time from reloaded inputs (only faces that need it come here).
+template <class T>
+__device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage, uint32_t f, uint32_t l,
+                                                             uint32_t r, double out[10]) {
+    const uint32_t nf = (uint32_t)P.nf;
+    const double *fg = P.fgeo;
+    const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
+                    (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+    const double w = ldg<double>(fg + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
+#pragma unroll 1
+    for (int p = 0; p < 3; ++p) {
+        T yl[3], yr[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            yl[a] = (T)ldg<double>(fg + (size_t)(4 + 3 * p + a) * nf, f * 8u);
+            yr[a] = (T)ldg<double>(fg + (size_t)(13 + 3 * p + a) * nf, f * 8u);
+        }
+        T qL[5], qR[5], gs[5][3];
+        recon_point<T, false>(P, stage, l, yl, qL, gs);
+        recon_point<T, true>(P, stage, r, yr, qR, gs);
+        const bool okL = physical_point(qL), okR = physical_point(qR);
+        if (!(okL && okR)) {
+            if (!okL) cell_mean(P, stage, l, qL);
+            if (!okR) cell_mean(P, stage, r, qR);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gs[v][0] = gs[v][1] = gs[v][2] = T(0);
+        }
+        T F[5], dF[5];
+        gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            out[k] = p == 0 ? w * (double)F[k] : out[k] + w * (double)F[k];
+            out[5 + k] = p == 0 ? w * (double)dF[k] : out[5 + k] + w * (double)dF[k];
+        }
+    }
+}
+
 // tau = 0: one lane per face, the three Gauss points in turn.  Each lane reads
 // both cells' reconstruction records once and evaluates them at all three points
 // (the per-face loads are scattered on the right-hand side, so the address units,
@@ -916,6 +977,9 @@ __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restric
             out[5 + k] = p == 0 ? w * (double)dF[k] : out[5 + k] + w * (double)dF[k];
         }
     }
+    if constexpr (COLOURED) {      // this mode accumulates at once: take the fallback inline
+        if (!(out[0] == out[0])) flux_face_fallback<T>(P, stage, f, l, r, out);
+    }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         if constexpr (COLOURED) {
@@ -925,6 +989,46 @@ __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restric
         } else {
             stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
         }
+    }
+    if constexpr (!COLOURED) {
+        // the fix-up pass has work: a non-finite face (flag cleared by the stage update)
+        const uint64_t bad = __ballot(!(out[0] - out[0] == 0.0));
+        if (bad != 0 && threadIdx.x == 0) P.flag[1] = 1;
+    }
+}
+
+// Faces whose tau = 0 flux came out non-finite had a non-physical reconstructed
+// side at some Gauss point (rho <= 0 or p <= 0 make lam <= 0, and the half-space
+// moments then return NaN); they are recomputed here with the positivity
+// fallback.  The flux kernel raises flag[1] of the problem when it wrote such a
+// face (the stage update clears it); with the flag clear, as in smooth flow, the
+// pass reads one word per tile.
+// Each workgroup (one wave) walks tiles with a grid stride, so the scan is a
+// few waves per SIMD reading one double per face; the recomputation is rare and
+// may use scratch memory.
+template <bool MIXED>
+__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) void k_flux_fix(
+    const ProbDesc *__restrict__ probs, int nprobs, const Tile *__restrict__ tiles, int ntiles, int stage) {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    // one look at every problem's flag: nothing to do in any of them is the common case
+    bool any = false;
+    for (int k = threadIdx.x; k < nprobs; k += FACE_TILE) any = any || ldg<int32_t>(probs[k].flag, 4u) != 0;
+    if (__ballot(any) == 0) return;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const ProbDesc &P = probs[tl.prob];
+        if (ldg<int32_t>(P.flag, 4u) == 0) continue;   // no non-finite face in this problem
+        const uint32_t f = tl.begin + threadIdx.x;
+        if (f >= (uint32_t)tl.end) continue;
+        const uint32_t nf = (uint32_t)P.nf;
+        const double f0 = ldg<double>(P.FF, f * 8u);
+        if (f0 - f0 == 0.0) continue;            // finite
+        const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
+        const uint32_t r = (uint32_t)ldg<int32_t>(P.fcell + nf, f * 4u);
+        double out[10];
+        flux_face_fallback<T>(P, stage, f, l, r, out);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
     }
 }
 
@@ -967,6 +1071,16 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
             T qL[5], gL[5][3], qR[5], gR[5][3];
             recon_point<T, false>(P, stage, l, yl, qL, gL);
             recon_point<T, false>(P, stage, r, yr, qR, gR);
+            const bool okL = physical_point(qL), okR = physical_point(qR);
+            if (!(okL && okR)) {
+                if (!okL) cell_mean(P, stage, l, qL);
+                if (!okR) cell_mean(P, stage, r, qR);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    gL[v][0] = gL[v][1] = gL[v][2] = T(0);
+                    gR[v][0] = gR[v][1] = gR[v][2] = T(0);
+                }
+            }
             gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
         }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
@@ -1072,6 +1186,7 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
         }
         if (!ok) P.flag[0] = 1;
     }
+    if (tl.local == 0 && threadIdx.x == 0) P.flag[1] = 0;   // the flux fix-up flag of this stage is spent
     if constexpr (STAGE == 2) {
         bound = wave_min(bound);
         if (threadIdx.x == 0) P.dtpart[tl.local] = bound;
@@ -1141,8 +1256,21 @@ void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage
         hipLaunchKernelGGL((k_weno<false, WENO_CELLS>), g, b, 0, s, probs, tiles, stage);
 }
 
-void launch_flux(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0, bool coloured,
-                 hipStream_t s) {
+// Compute units of the current device (queried once per device).
+static int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0,
+                 bool coloured, hipStream_t s) {
     if (ntiles <= 0) return;
     if (tau0) {
         dim3 g(ntiles), b(FACE_TILE);
@@ -1150,6 +1278,11 @@ void launch_flux(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage
         if (coloured) { if (mixed) HGKS_FLUX0(true, true); else HGKS_FLUX0(false, true); }
         else { if (mixed) HGKS_FLUX0(true, false); else HGKS_FLUX0(false, false); }
 #undef HGKS_FLUX0
+        if (!coloured) {
+            const dim3 gf(std::min(ntiles, 8 * device_cus()));
+            if (mixed) hipLaunchKernelGGL((k_flux_fix<true>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
+            else hipLaunchKernelGGL((k_flux_fix<false>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
+        }
         return;
     }
     dim3 g(ntiles), b(3 * FACE_TILE);
