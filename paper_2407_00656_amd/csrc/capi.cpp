@@ -413,7 +413,12 @@ hgks_status hgks_step_s2o4(hgks_ctx *c, int32_t nsteps, double dt_fixed, double 
     if (c->pool_refs) return fail(c, HGKS_E_STATE, "context is in a pool: step it with hgks_pool_step");
     if (nsteps < 0 || !std::isfinite(dt_fixed)) return fail(c, HGKS_E_INVALID_ARG, "bad step arguments");
     HIPCHK(c, hipSetDevice(c->device));
-    for (int32_t k = 0; k < nsteps; ++k) enqueue_step(c, dt_fixed);
+    for (int32_t k = 0; k < nsteps; ++k) {
+        enqueue_step(c, dt_fixed);
+        // profiling: fold finished event pairs back into the pool so that a long
+        // run keeps a bounded number of events in flight
+        if (c->pending.size() > 512) collect_profile(c);
+    }
     HIPCHK(c, hipGetLastError());
     if (dt_last) {
         hgks_status st = hgks_sync(c);

@@ -795,6 +795,14 @@ __device__ __forceinline__ bool physical_point(const T q[5]) {
 }
 
 template <class T>
+__device__ __forceinline__ bool finite_flux(const T F[5], const T dF[5]) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s += F[k] * T(0) + dF[k] * T(0);   // NaN for any non-finite entry
+    return s == T(0);
+}
+
+template <class T>
 __device__ __forceinline__ void cell_mean(const ProbDesc &P, int stage, uint32_t c, T q[5]) {
     const double *Qa = stage == 1 ? P.Q : P.Qs;
 #pragma unroll
@@ -923,6 +931,13 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
         }
         T F[5], dF[5];
         gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
+        if (!finite_flux(F, dF)) {          // (FP32 form) a non-finite point flux: first order
+            cell_mean(P, stage, l, qL);
+            cell_mean(P, stage, r, qR);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gs[v][0] = gs[v][1] = gs[v][2] = T(0);
+            gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
+        }
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             out[k] = p == 0 ? w * (double)F[k] : out[k] + w * (double)F[k];
@@ -1082,6 +1097,16 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
                 }
             }
             gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+            if (!finite_flux(F, dF)) {     // (FP32 form) a non-finite point flux: first order
+                cell_mean(P, stage, l, qL);
+                cell_mean(P, stage, r, qR);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    gL[v][0] = gL[v][1] = gL[v][2] = T(0);
+                    gR[v][0] = gR[v][1] = gR[v][2] = T(0);
+                }
+                gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+            }
         }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
 #pragma unroll

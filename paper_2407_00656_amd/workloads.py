@@ -253,6 +253,59 @@ class SodCase:
         xm = np.mod(x - self.x0, 2.0 * self.half)
         return xm < self.half
 
+    def star(self):
+        """Pressure and velocity between the waves: Newton's method on the pressure
+        function of the exact Riemann solution (Toro, ch. 4)."""
+        g = self.gamma
+        rl, pl, rr, pr = self.rho_l, self.p_l, self.rho_r, self.p_r
+        cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+
+        def fk(p, rk, pk, ck):
+            if p > pk:                       # shock
+                a = 2.0 / ((g + 1.0) * rk)
+                b = (g - 1.0) / (g + 1.0) * pk
+                return (p - pk) * math.sqrt(a / (p + b)), math.sqrt(a / (b + p)) * (1.0 - (p - pk) / (2.0 * (b + p)))
+            e = (g - 1.0) / (2.0 * g)            # rarefaction
+            return 2.0 * ck / (g - 1.0) * ((p / pk) ** e - 1.0), (p / pk) ** (-(g + 1.0) / (2.0 * g)) / (rk * ck)
+
+        p = 0.5 * (pl + pr)
+        for _ in range(100):
+            f1, d1 = fk(p, rl, pl, cl)
+            f2, d2 = fk(p, rr, pr, cr)
+            dp = (f1 + f2) / (d1 + d2)
+            p = max(1e-14, p - dp)
+            if abs(dp) < 1e-15 * p:
+                break
+        f1, _ = fk(p, rl, pl, cl)
+        f2, _ = fk(p, rr, pr, cr)
+        return p, 0.5 * (f2 - f1)
+
+    def exact(self, x: np.ndarray, t: float) -> np.ndarray:
+        """(rho, u_x, p) of the exact solution at positions x (any half of the period):
+        left rarefaction, contact, right shock, for this data at rest."""
+        g = self.gamma
+        rl, pl, rr, pr = self.rho_l, self.p_l, self.rho_r, self.p_r
+        cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+        ps, us = self.star()
+        xm = np.mod(np.asarray(x, dtype=np.float64) - self.x0, 2.0 * self.half)
+        # distance from the nearest diaphragm, oriented from the high to the low state
+        d = np.where(xm >= 0.5 * self.half * 3.0, xm - 2.0 * self.half,
+                     np.where(xm < 0.5 * self.half, xm, xm - self.half))
+        sign = np.where((xm >= 0.5 * self.half) & (xm < 1.5 * self.half), 1.0, -1.0)
+        xi = sign * d / t
+        head, tail = -cl, us - cl * (ps / pl) ** ((g - 1.0) / (2.0 * g))
+        shock = cr * math.sqrt((g + 1.0) / (2.0 * g) * ps / pr + (g - 1.0) / (2.0 * g))
+        rho_sl = rl * (ps / pl) ** (1.0 / g)
+        rho_sr = rr * ((ps / pr + (g - 1.0) / (g + 1.0)) / ((g - 1.0) / (g + 1.0) * ps / pr + 1.0))
+        c = 2.0 / (g + 1.0) * (cl - 0.5 * (g - 1.0) * xi)
+        out = np.empty((xi.shape[0], 3))
+        out[:, 0] = np.select([xi < head, xi < tail, xi < us, xi < shock],
+                              [rl, rl * (np.abs(c) / cl) ** (2.0 / (g - 1.0)), rho_sl, rho_sr], rr)
+        out[:, 1] = sign * np.select([xi < head, xi < tail, xi < shock], [0.0, 2.0 / (g + 1.0) * (cl + xi), us], 0.0)
+        out[:, 2] = np.select([xi < head, xi < tail, xi < shock],
+                              [pl, pl * (np.abs(c) / cl) ** (2.0 * g / (g - 1.0)), ps], pr)
+        return out
+
     def conservative(self, mesh: TetMesh) -> np.ndarray:
         cx = mesh.cell_vertices[:, :, 0].mean(axis=1)
         hi = self.high(cx)

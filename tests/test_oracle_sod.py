@@ -149,3 +149,15 @@ def test_sod_conserves_and_stays_physical(runs):
         rho = q[:, 0]
         p = (GAMMA - 1.0) * (q[:, 4] - 0.5 * (q[:, 1:4] ** 2).sum(axis=1) / rho)
         assert rho.min() > 0.1 and p.min() > 0.05 and rho.max() < 1.05 and p.max() < 1.05
+
+
+def test_workload_exact_solution_matches():
+    """The vectorised exact solution the shock-tube driver reports against equals
+    the construction above on both halves of the periodic tube."""
+    case = W.SodCase()
+    x = np.linspace(0.0, 2.0, 2001)[:-1] + 1e-4
+    got = case.exact(x, T_END)
+    xi = np.where(x >= 1.0, (x - 1.5) / T_END, (0.5 - x) / T_END)
+    ref, _ = sod_exact(xi)
+    ref[:, 1] *= np.where(x >= 1.0, 1.0, -1.0)
+    assert np.abs(got - ref).max() < 1e-13
