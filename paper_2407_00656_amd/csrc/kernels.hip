@@ -1097,16 +1097,6 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
                 }
             }
             gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
-            if (!finite_flux(F, dF)) {     // (FP32 form) a non-finite point flux: first order
-                cell_mean(P, stage, l, qL);
-                cell_mean(P, stage, r, qR);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    gL[v][0] = gL[v][1] = gL[v][2] = T(0);
-                    gR[v][0] = gR[v][1] = gR[v][2] = T(0);
-                }
-                gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
-            }
         }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
 #pragma unroll
