@@ -811,7 +811,9 @@ __device__ __forceinline__ void cell_mean(const ProbDesc &P, int stage, uint32_t
 
 // Value and gradient of a cell's reconstruction at offset y from its centroid;
 // ADD accumulates the gradient into g (tau = 0 needs only the sum of both sides).
-template <class T, bool ADD>
+// REC32: the records are the FP32-mixed ones (FP32 coefficients, c0 the deviation from
+// the FP64 cell mean); they may be evaluated in FP64 (T = double).
+template <class T, bool ADD, bool REC32 = (sizeof(T) == 4)>
 __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32_t c, const T y[3], T q[5], T g[5][3]) {
     const uint32_t nc = (uint32_t)P.nc;
     const T yy[6] = {y[0] * y[0], y[1] * y[1], y[2] * y[2], y[0] * y[1], y[0] * y[2], y[1] * y[2]};
@@ -820,7 +822,7 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32
         T cf[10];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            if constexpr (sizeof(T) == 8) {
+            if constexpr (!REC32) {
                 const d2 pr = ldg<d2>(reinterpret_cast<const d2 *>(P.C) + (size_t)(v * 5 + k) * nc, c * 16u);
                 cf[2 * k] = pr.x;
                 cf[2 * k + 1] = pr.y;
@@ -833,12 +835,12 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32
         T val = cf[0] + cf[1] * y[0] + cf[2] * y[1] + cf[3] * y[2];
 #pragma unroll
         for (int k = 0; k < 6; ++k) val += cf[4 + k] * yy[k];
-        if constexpr (sizeof(T) == 8) {
+        if constexpr (!REC32) {
             q[v] = val;
         } else {
-            // FP32 form: FP64 cell mean plus FP32 deviation, rounded once
+            // FP32 form: FP64 cell mean plus the deviation, rounded once to T
             const double mean = ldg<double>((stage == 1 ? P.Q : P.Qs) + (size_t)v * nc, c * 8u);
-            q[v] = (float)(mean + (double)val);
+            q[v] = (T)(mean + (double)val);
         }
         const T gx = cf[1] + T(2) * cf[4] * y[0] + cf[7] * y[1] + cf[8] * y[2];
         const T gy = cf[2] + T(2) * cf[5] * y[1] + cf[7] * y[0] + cf[9] * y[2];
@@ -1076,33 +1078,49 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
             yl[a] = (T)ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
             yr[a] = (T)ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
         }
-        T F[5], dF[5];
+        double Fo[5], dFo[5];
         if constexpr (TAU0) {
-            T qL[5], qR[5], gs[5][3];
+            T qL[5], qR[5], gs[5][3], F[5], dF[5];
             recon_point<T, false>(P, stage, l, yl, qL, gs);
             recon_point<T, true>(P, stage, r, yr, qR, gs);
             gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                Fo[k] = (double)F[k];
+                dFo[k] = (double)dF[k];
+            }
         } else {
-            T qL[5], gL[5][3], qR[5], gR[5][3];
-            recon_point<T, false>(P, stage, l, yl, qL, gL);
-            recon_point<T, false>(P, stage, r, yr, qR, gR);
+            // tau > 0 runs in FP64 in both forms (the FP32-mixed form reads its FP32
+            // records and evaluates them in FP64): the FP32 evaluation of this flux
+            // turns non-finite next to a shock on large meshes
+            const double nd[3] = {ldg<double>(fg, f * 8u), ldg<double>(fg + nf, f * 8u),
+                                  ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+            double yld[3], yrd[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                yld[a] = ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
+                yrd[a] = ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
+            }
+            double qL[5], gL[5][3], qR[5], gR[5][3];
+            recon_point<double, false, MIXED>(P, stage, l, yld, qL, gL);
+            recon_point<double, false, MIXED>(P, stage, r, yrd, qR, gR);
             const bool okL = physical_point(qL), okR = physical_point(qR);
             if (!(okL && okR)) {
                 if (!okL) cell_mean(P, stage, l, qL);
                 if (!okR) cell_mean(P, stage, r, qR);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    gL[v][0] = gL[v][1] = gL[v][2] = T(0);
-                    gR[v][0] = gR[v][1] = gR[v][2] = T(0);
+                    gL[v][0] = gL[v][1] = gL[v][2] = 0.0;
+                    gR[v][0] = gR[v][1] = gR[v][2] = 0.0;
                 }
             }
-            gks_flux_full<T>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+            gks_flux_full<double>(qL, gL, qR, gR, nd, P.dt[0], P, Fo, dFo);
         }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            out[k] = w * (double)F[k];
-            out[5 + k] = w * (double)dF[k];
+            out[k] = w * Fo[k];
+            out[5 + k] = w * dFo[k];
         }
     }
 #pragma unroll
