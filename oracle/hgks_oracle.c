@@ -25,8 +25,9 @@
  *   - the slopes of the equilibrium state use dQ0 = (dQ_l + dQ_r)/2;
  *   - tau = 0 (smooth flow, Sec. 5.1) or tau = eps*dt + C*|pl-pr|/(pl+pr)*dt;
  *   - dt = CFL * min_i h_i / (|U_i| + c_i), h_i = 6|Omega_i| / sum_p S_ip;
- *   - positivity fallback at Gauss points (a non-physical reconstructed side takes
- *     its cell average with zero gradient), which acts only at discontinuities.
+ *   - positivity fallback at Gauss points (where a reconstructed side is
+ *     non-physical the point is first order: zero gradients, cell averages for
+ *     the non-physical sides), which acts only at discontinuities.
  *
  * Conventions: cells are 0-based; face p of a tetrahedron is the one opposite
  * its node p (Sec. 3.1 item 1); the neighbour across face p is "i_{p+1}" of
@@ -873,20 +874,28 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
  * the thread count.
  */
 /*
- * Positivity fallback (not in the paper, which has no limiter): a side whose
- * reconstructed state at the Gauss point has rho <= 0 or p <= 0 takes its cell
- * average with zero gradient there.  It never acts in smooth flow; at a strong
- * discontinuity (the shock tube) the quadratic reconstruction would otherwise
- * hand the flux a state with negative pressure on the first step.
+ * Positivity fallback (not in the paper, which has no limiter): at a Gauss point
+ * where the reconstructed state of either side has rho <= 0 or p <= 0, the point
+ * is evaluated at first order: both sides' gradients are zero and each
+ * non-physical side takes its cell average.  It never acts in smooth flow; at a
+ * strong discontinuity (the shock tube) the quadratic reconstruction would
+ * otherwise hand the flux a state with negative pressure on the first step.
  */
-static void gauss_point_fallback(const orc_params *p, const double *qcell, double *v, double g[5][3]) {
+static int physical_point(const orc_params *p, const double *v) {
     const double rho = v[0];
     const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
-    const double pr = (p->gamma - 1.0) * (v[4] - ke);
-    if (rho > 0.0 && pr > 0.0) return;
+    return rho > 0.0 && (p->gamma - 1.0) * (v[4] - ke) > 0.0;
+}
+
+static void gauss_point_fallback(const orc_params *p, const double *ql_cell, const double *qr_cell, double *vl,
+                                 double gl[5][3], double *vr, double gr[5][3]) {
+    const int okl = physical_point(p, vl), okr = physical_point(p, vr);
+    if (okl && okr) return;
     for (int q = 0; q < 5; ++q) {
-        v[q] = qcell[q];
-        g[q][0] = g[q][1] = g[q][2] = 0.0;
+        if (!okl) vl[q] = ql_cell[q];
+        if (!okr) vr[q] = qr_cell[q];
+        gl[q][0] = gl[q][1] = gl[q][2] = 0.0;
+        gr[q][0] = gr[q][1] = gr[q][2] = 0.0;
     }
 }
 
@@ -909,8 +918,7 @@ int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, 
                 for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
                 weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
                 weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
-                gauss_point_fallback(p, Q + 5 * l, vl, gl);
-                gauss_point_fallback(p, Q + 5 * r, vr, gr);
+                gauss_point_fallback(p, Q + 5 * l, Q + 5 * r, vl, gl, vr, gr);
                 int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
                 if (r_ > rc) rc = r_;
                 for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
@@ -1093,8 +1101,7 @@ static int rhs_subset(const orc_mesh *m, const orc_params *p, const double *Q, d
                 for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
                 weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
                 weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
-                gauss_point_fallback(p, Q + 5 * l, vl, gl);
-                gauss_point_fallback(p, Q + 5 * r, vr, gr);
+                gauss_point_fallback(p, Q + 5 * l, Q + 5 * r, vl, gl, vr, gr);
                 int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
                 if (r_ > rc) rc = r_;
                 for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
