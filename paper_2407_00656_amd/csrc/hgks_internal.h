@@ -30,7 +30,9 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hgks.h"
@@ -49,17 +51,41 @@ constexpr int FACE_TILE = 64;      // faces per workgroup (flux: 3 waves, one pe
 // S_4 = {i3,i1,i4} + N(i4)   (Sec. 2.3, tetrahedral sub-stencils)
 constexpr int SUBFIRST[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
 
+// Allocator whose value-less construct leaves trivially constructible elements
+// uninitialised: resize() of the packed arrays then skips a serial zero fill of
+// memory the precompute writes in full, in parallel, right after.
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <class U>
+    UninitAlloc(const UninitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using hvec = std::vector<T, UninitAlloc<T>>;
+
 struct HostMesh {
     int64_t nc = 0, nf = 0;
     std::vector<int64_t> perm;      // internal cell c holds caller cell perm[c]
-    std::vector<int32_t> sten;      // [16][nc]
-    std::vector<double> pinv0;      // [72][nc][2]
-    std::vector<double> cen;        // [3][nc]
-    std::vector<uint32_t> sshift;   // [4][nc]
-    std::vector<double> cgeo;       // [9][nc]
-    std::vector<int32_t> cface;     // [4][nc]
-    std::vector<int32_t> fcell;     // [2][nf]
-    std::vector<double> fgeo;       // [22][nf]
+    hvec<int32_t> sten;             // [16][nc]
+    hvec<double> pinv0;             // [72][nc][2]
+    hvec<double> cen;               // [3][nc]
+    hvec<uint32_t> sshift;          // [4][nc]
+    hvec<double> cgeo;              // [9][nc]
+    hvec<int32_t> cface;            // [4][nc]
+    hvec<int32_t> fcell;            // [2][nf]
+    hvec<double> fgeo;              // [22][nf]
     // faces grouped by colour (coloured accumulation); colour_offsets[c]..[c+1]
     std::vector<int32_t> colour_offsets;
     // diagnostics

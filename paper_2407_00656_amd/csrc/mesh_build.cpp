@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <memory>
 #include <thread>
 
 #include "hgks_internal.h"
@@ -74,46 +75,46 @@ struct Member {            // a stencil member: cell id and integer periodic ima
 constexpr int QA[6] = {0, 1, 2, 0, 0, 1};
 constexpr int QB[6] = {0, 1, 2, 1, 2, 2};
 
-// Pseudo-inverse of a full-column-rank m x n matrix (row-major) by Householder QR:
-// P (n x m, row-major) = R^{-1} Q^T.  Returns false when a diagonal of R is
-// negligible against the largest (rank deficiency).
-bool pinv_qr(int m, int n, const double *A, double *P) {
-    double R[16 * 9], V[9][16], beta[9];
-    std::memcpy(R, A, sizeof(double) * m * n);
-    double rmax = 0.0;
+// Pseudo-inverse of a full-column-rank m x n matrix (row-major, m <= 16, n <= 9) by
+// the normal equations: P (n x m, row-major) = (A^T A)^{-1} A^T with a Cholesky
+// factor of A^T A (the least-squares fit the oracle solves the same way).  Returns
+// false when a pivot of the factor is negligible against the largest (rank
+// deficiency; the squared form of the test |R_jj| > 1e-9 max |R| on a QR factor).
+// With P == nullptr only the rank test runs.
+bool pinv_normal(int m, int n, const double *A, double *P) {
+    double L[9][9];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < m; ++k) s += A[k * n + i] * A[k * n + j];
+            L[i][j] = s;
+        }
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = std::max(dmax, L[i][i]);
     for (int j = 0; j < n; ++j) {
-        double nrm = 0.0;
-        for (int i = j; i < m; ++i) nrm += R[i * n + j] * R[i * n + j];
-        nrm = std::sqrt(nrm);
-        double alpha = R[j * n + j] >= 0 ? -nrm : nrm;
-        for (int i = 0; i < m; ++i) V[j][i] = i < j ? 0.0 : R[i * n + j];
-        V[j][j] -= alpha;
-        double vv = 0.0;
-        for (int i = j; i < m; ++i) vv += V[j][i] * V[j][i];
-        beta[j] = vv > 0.0 ? 2.0 / vv : 0.0;
-        for (int c = j; c < n; ++c) {
-            double s = 0.0;
-            for (int i = j; i < m; ++i) s += V[j][i] * R[i * n + c];
-            s *= beta[j];
-            for (int i = j; i < m; ++i) R[i * n + c] -= s * V[j][i];
+        double d = L[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 1e-18 * dmax)) return false;
+        const double ljj = std::sqrt(d);
+        L[j][j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double s = L[i][j];
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = s / ljj;
         }
-        rmax = std::max(rmax, std::fabs(R[j * n + j]));
     }
-    for (int j = 0; j < n; ++j)
-        if (!(std::fabs(R[j * n + j]) > 1e-9 * rmax)) return false;
-    for (int k = 0; k < m; ++k) {
-        double y[16];
-        for (int i = 0; i < m; ++i) y[i] = i == k ? 1.0 : 0.0;
-        for (int j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int i = j; i < m; ++i) s += V[j][i] * y[i];
-            s *= beta[j];
-            for (int i = j; i < m; ++i) y[i] -= s * V[j][i];
+    if (!P) return true;
+    for (int c = 0; c < m; ++c) {          // column c of P solves (L L^T) x = row c of A
+        double y[9];
+        for (int i = 0; i < n; ++i) {
+            double s = A[c * n + i];
+            for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+            y[i] = s / L[i][i];
         }
-        for (int r = n - 1; r >= 0; --r) {
-            double s = y[r];
-            for (int c = r + 1; c < n; ++c) s -= R[r * n + c] * P[c * m + k];
-            P[r * m + k] = s / R[r * n + r];
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < n; ++k) s -= L[k][i] * P[k * m + c];
+            P[i * m + c] = s / L[i][i];
         }
     }
     return true;
@@ -281,18 +282,57 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         }
     });
 
-    // ---- 4. stencils and pseudo-inverses ----------------------------------------
-    // 16 slots per cell (caller numbering for now)
-    std::vector<std::array<Member, SLOTS>> slot(nc);
-    std::vector<double> P0(nc * 9 * SLOTS), PS(nc * 72);
+    // ---- 4. renumbering ---------------------------------------------------------
+    std::vector<int64_t> perm(nc);
+    for (int64_t c = 0; c < nc; ++c) perm[c] = c;
+    if (prm.reorder) {
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = 1e300;
+            hi[a] = -1e300;
+        }
+        for (int64_t c = 0; c < nc; ++c)
+            for (int a = 0; a < 3; ++a) {
+                double x = comp(cen[c], a);
+                if (per[a] > 0) x -= per[a] * std::floor(x / per[a]);
+                lo[a] = std::min(lo[a], x);
+                hi[a] = std::max(hi[a], x);
+            }
+        std::vector<std::pair<uint64_t, int64_t>> key(nc);
+        parallel_for(nc, [&](int64_t b, int64_t e) {
+            for (int64_t c = b; c < e; ++c) {
+                uint64_t code = 0;
+                for (int a = 0; a < 3; ++a) {
+                    double x = comp(cen[c], a);
+                    if (per[a] > 0) x -= per[a] * std::floor(x / per[a]);
+                    double t = hi[a] > lo[a] ? (x - lo[a]) / (hi[a] - lo[a]) : 0.0;
+                    uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+                    code |= spread3(q) << a;
+                }
+                key[c] = {code, c};
+            }
+        });
+        std::sort(key.begin(), key.end());
+        for (int64_t c = 0; c < nc; ++c) perm[c] = key[c].second;
+    }
+    std::vector<int32_t> inv(nc);
+    for (int64_t c = 0; c < nc; ++c) inv[perm[c]] = (int32_t)c;
+
+    // ---- 5. stencils and pseudo-inverses, written in internal numbering --------
+    const int64_t nf = 2 * nc;
+    // every entry of these arrays is written below (no fill on resize)
+    out.sten.resize((size_t)SLOTS * nc);
+    out.pinv0.resize((size_t)144 * nc);
+    out.sshift.resize((size_t)4 * nc);
     std::atomic<int> members_max{0}, members_min{1 << 30}, dups{0};
     std::mutex mu;
     double resid_max = 0.0;
     parallel_for(nc, [&](int64_t b, int64_t e) {
         double local_resid = 0.0;
         int lmax = 0, lmin = 1 << 30, ldup = 0;
-        for (int64_t i = b; i < e; ++i) {
-            auto &S = slot[i];
+        for (int64_t c = b; c < e; ++c) {
+            const int64_t i = perm[c];          // caller id
+            Member S[SLOTS];
             for (int p = 0; p < 4; ++p) S[p] = {nb[i][p], {nsh[i][p][0], nsh[i][p][1], nsh[i][p][2]}};
             for (int m = 0; m < 4; ++m) {
                 int32_t j = nb[i][m];
@@ -336,7 +376,7 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             lmax = std::max(lmax, nm);
             lmin = std::min(lmin, nm);
             double Pk[9 * SLOTS];
-            if (!pinv_qr(nm, 9, A, Pk)) {
+            if (!pinv_normal(nm, 9, A, Pk)) {
                 bad = 4;
                 continue;
             }
@@ -347,34 +387,43 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                     for (int k = 0; k < nm; ++k) s += Pk[r * nm + k] * A[k * 9 + c];
                     local_resid = std::max(local_resid, std::fabs(s - (r == c ? 1.0 : 0.0)));
                 }
+            // slot s of a cell reached twice keeps its member but gets zero weight
             for (int r = 0; r < 9; ++r)
-                for (int s = 0; s < SLOTS; ++s) P0[(i * 9 + r) * SLOTS + s] = first[s] >= 0 ? Pk[r * nm + first[s]] : 0.0;
-            // the four linear sub-stencil fits (first-layer minus one, plus N(i_m))
+                for (int s = 0; s < SLOTS; ++s)
+                    out.pinv0[(((size_t)(r * 8 + s / 2)) * nc + c) * 2 + (s & 1)] = first[s] >= 0 ? Pk[r * nm + first[s]] : 0.0;
+            for (int s = 0; s < SLOTS; ++s) out.sten[(size_t)s * nc + c] = inv[S[s].cell];
+            for (int w = 0; w < 4; ++w) {
+                uint32_t word = 0;
+                for (int s = 4 * w; s < 4 * w + 4; ++s) {
+                    const uint32_t code = (uint32_t)((S[s].s[0] + 2) + 5 * (S[s].s[1] + 2) + 25 * (S[s].s[2] + 2));
+                    word |= code << (8 * (s % 4));
+                }
+                out.sshift[(size_t)w * nc + c] = word;
+            }
+            // the four linear sub-stencil fits (first-layer minus one, plus N(i_m)) are
+            // formed on the device; here only their rank is checked
             for (int m = 0; m < 4; ++m) {
                 int sl[6] = {SUBFIRST[m][0], SUBFIRST[m][1], SUBFIRST[m][2], 4 + 3 * m, 5 + 3 * m, 6 + 3 * m};
-                double As[6 * 3], Ps[3 * 6];
-                int fs[6], ns = 0;
+                double As[6 * 3];
+                int ns = 0;
                 Member us[6];
                 for (int t = 0; t < 6; ++t) {
-                    fs[t] = -1;
+                    bool dup = false;
                     for (int u = 0; u < ns; ++u)
-                        if (us[u] == S[sl[t]]) fs[t] = -2;
-                    if (fs[t] == -1) {
-                        us[ns] = S[sl[t]];
-                        double r[9];
-                        row(S[sl[t]], r);
-                        As[ns * 3 + 0] = r[0];
-                        As[ns * 3 + 1] = r[1];
-                        As[ns * 3 + 2] = r[2];
-                        fs[t] = ns++;
-                    }
+                        if (us[u] == S[sl[t]]) dup = true;
+                    if (dup) continue;
+                    us[ns] = S[sl[t]];
+                    double r[9];
+                    row(S[sl[t]], r);
+                    As[ns * 3 + 0] = r[0];
+                    As[ns * 3 + 1] = r[1];
+                    As[ns * 3 + 2] = r[2];
+                    ++ns;
                 }
-                if (ns < 3 || !pinv_qr(ns, 3, As, Ps)) {
+                if (ns < 3 || !pinv_normal(ns, 3, As, nullptr)) {
                     bad = 4;
                     continue;
                 }
-                for (int k = 0; k < 3; ++k)
-                    for (int t = 0; t < 6; ++t) PS[i * 72 + (m * 3 + k) * 6 + t] = fs[t] >= 0 ? Ps[k * ns + fs[t]] : 0.0;
             }
         }
         std::lock_guard<std::mutex> g(mu);
@@ -392,45 +441,8 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         return HGKS_E_BAD_MESH;
     }
 
-    // ---- 5. renumbering ---------------------------------------------------------
-    std::vector<int64_t> perm(nc);
-    for (int64_t c = 0; c < nc; ++c) perm[c] = c;
-    if (prm.reorder) {
-        double lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = 1e300;
-            hi[a] = -1e300;
-        }
-        for (int64_t c = 0; c < nc; ++c)
-            for (int a = 0; a < 3; ++a) {
-                double x = comp(cen[c], a);
-                if (per[a] > 0) x -= per[a] * std::floor(x / per[a]);
-                lo[a] = std::min(lo[a], x);
-                hi[a] = std::max(hi[a], x);
-            }
-        std::vector<std::pair<uint64_t, int64_t>> key(nc);
-        parallel_for(nc, [&](int64_t b, int64_t e) {
-            for (int64_t c = b; c < e; ++c) {
-                uint64_t code = 0;
-                for (int a = 0; a < 3; ++a) {
-                    double x = comp(cen[c], a);
-                    if (per[a] > 0) x -= per[a] * std::floor(x / per[a]);
-                    double t = hi[a] > lo[a] ? (x - lo[a]) / (hi[a] - lo[a]) : 0.0;
-                    uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
-                    code |= spread3(q) << a;
-                }
-                key[c] = {code, c};
-            }
-        });
-        std::sort(key.begin(), key.end());
-        for (int64_t c = 0; c < nc; ++c) perm[c] = key[c].second;
-    }
-    std::vector<int32_t> inv(nc);
-    for (int64_t c = 0; c < nc; ++c) inv[perm[c]] = (int32_t)c;
-
     // ---- 6. faces in internal numbering: left = smaller internal id -------------
     // counting sort by left cell, then by right cell
-    const int64_t nf = 2 * nc;
     std::vector<int64_t> fstart(nc + 1, 0);
     for (int64_t c = 0; c < nc; ++c)
         for (int p = 0; p < 4; ++p) {
@@ -489,31 +501,16 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
     out.nc = nc;
     out.nf = nf;
     out.perm = perm;
-    out.sten.assign((size_t)SLOTS * nc, 0);
-    out.pinv0.assign((size_t)144 * nc, 0.0);
-    out.cen.assign((size_t)3 * nc, 0.0);
-    out.sshift.assign((size_t)4 * nc, 0u);
-    out.cgeo.assign((size_t)CGEO * nc, 0.0);
-    out.cface.assign((size_t)4 * nc, 0);
-    out.fcell.assign((size_t)2 * nf, 0);
-    out.fgeo.assign((size_t)FGEO * nf, 0.0);
-    std::vector<int32_t> fpos(nf);
-    for (int64_t k = 0; k < nf; ++k) fpos[forder[k]] = (int32_t)k;
-    double closure = 0.0;
-    std::vector<double> cl_acc(3 * (size_t)nc, 0.0);
+    // every entry of these arrays is written below (no fill on resize)
+    out.cen.resize((size_t)3 * nc);
+    out.cgeo.resize((size_t)CGEO * nc);
+    out.cface.resize((size_t)4 * nc);
+    out.fcell.resize((size_t)2 * nf);
+    out.fgeo.resize((size_t)FGEO * nf);
     parallel_for(nc, [&](int64_t b, int64_t e) {
         for (int64_t c = b; c < e; ++c) {
             int64_t o = perm[c];
-            for (int s = 0; s < SLOTS; ++s) out.sten[(size_t)s * nc + c] = inv[slot[o][s].cell];
-            for (int r = 0; r < 9; ++r)
-                for (int s = 0; s < SLOTS; ++s)
-                    out.pinv0[(((size_t)(r * 8 + s / 2)) * nc + c) * 2 + (s & 1)] = P0[(o * 9 + r) * SLOTS + s];
             for (int a = 0; a < 3; ++a) out.cen[(size_t)a * nc + c] = comp(cen[o], a);
-            for (int s = 0; s < SLOTS; ++s) {
-                const Member &x = slot[o][s];
-                const uint32_t code = (uint32_t)((x.s[0] + 2) + 5 * (x.s[1] + 2) + 25 * (x.s[2] + 2));
-                out.sshift[(size_t)(s / 4) * nc + c] |= code << (8 * (s % 4));
-            }
             double h = std::cbrt(vol[o]);
             out.cgeo[0 * (size_t)nc + c] = 1.0 / h;
             for (int q = 0; q < 6; ++q) out.cgeo[(size_t)(1 + q) * nc + c] = smom[o][q] / (h * h);
@@ -568,20 +565,28 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         err = "overlapping or folded cells (a face does not separate its two cells)";
         return HGKS_E_BAD_MESH;
     }
-    for (int64_t k = 0; k < nf; ++k) {
-        double S = out.fgeo[3 * (size_t)nf + k];
-        for (int a = 0; a < 3; ++a) {
-            double v = out.fgeo[(size_t)a * nf + k] * S;
-            cl_acc[3 * (size_t)out.fcell[k] + a] += v;
-            cl_acc[3 * (size_t)out.fcell[nf + k] + a] -= v;
-        }
-    }
-    for (double v : cl_acc) closure = std::max(closure, std::fabs(v));
     for (int64_t c = 0; c < nc; ++c)
         if (cfill[c] != 4) {
             err = "cell without four faces";
             return HGKS_E_BAD_MESH;
         }
+    // closure: the outward n S of each cell's four faces sum to zero
+    double closure = 0.0;
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        double lmax = 0.0;
+        for (int64_t c = b; c < e; ++c) {
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (int p = 0; p < 4; ++p) {
+                const int32_t code = out.cface[(size_t)p * nc + c];
+                const int64_t k = code >> 1;
+                const double sS = (code & 1 ? -1.0 : 1.0) * out.fgeo[3 * (size_t)nf + k];
+                for (int a = 0; a < 3; ++a) acc[a] += out.fgeo[(size_t)a * nf + k] * sS;
+            }
+            for (int a = 0; a < 3; ++a) lmax = std::max(lmax, std::fabs(acc[a]));
+        }
+        std::lock_guard<std::mutex> g(mu);
+        closure = std::max(closure, lmax);
+    });
     out.max_members = members_max;
     out.min_members = members_min;
     out.dup_slots = dups;
