@@ -130,9 +130,10 @@ hgks_status hgks_init_state(hgks_ctx *ctx, const double *q, double t0);
  * requested and a step produced a non-physical state. */
 hgks_status hgks_step_s2o4(hgks_ctx *ctx, int32_t nsteps, double dt_fixed, double *dt_last);
 
-/* Copies the state to q_out [n_cells][5] (caller order) and the time to t_out
- * (nullable).  Synchronises.  Errors: STATE, NONPHYSICAL (a step went non-physical;
- * the state returned is the last one computed), DEVICE. */
+/* Copies the state to q_out [n_cells][5] (caller order) and the time to t_out.
+ * Both are nullable; with q_out NULL only the time and the non-physical flag are
+ * read back (a few bytes).  Synchronises.  Errors: STATE, NONPHYSICAL (a step went
+ * non-physical; the state returned is the last one computed), DEVICE. */
 hgks_status hgks_get_state(hgks_ctx *ctx, double *q_out, double *t_out);
 
 /* Waits for the context's queued work.  Errors: DEVICE, NONPHYSICAL. */

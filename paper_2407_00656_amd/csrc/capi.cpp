@@ -435,15 +435,16 @@ hgks_status hgks_get_state(hgks_ctx *c, double *q_out, double *t_out) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->pool_refs) HIPCHK(c, hipStreamSynchronize(c->pool_stream));
     const int64_t nc = c->nc;
-    std::vector<double> soa((size_t)5 * nc);
-    HIPCHK(c, hipMemcpy(soa.data(), c->desc.Q, soa.size() * 8, hipMemcpyDeviceToHost));
+    if (q_out) {
+        std::vector<double> soa((size_t)5 * nc);
+        HIPCHK(c, hipMemcpy(soa.data(), c->desc.Q, soa.size() * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < nc; ++i)
+            for (int v = 0; v < 5; ++v) q_out[5 * c->perm[i] + v] = soa[(size_t)v * nc + i];
+    }
     double tt = 0.0;
     int32_t flag = 0;
     HIPCHK(c, hipMemcpy(&tt, c->desc.time, 8, hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(&flag, c->desc.flag, 4, hipMemcpyDeviceToHost));
-    if (q_out)
-        for (int64_t i = 0; i < nc; ++i)
-            for (int v = 0; v < 5; ++v) q_out[5 * c->perm[i] + v] = soa[(size_t)v * nc + i];
     if (t_out) *t_out = tt;
     if (flag) return fail(c, HGKS_E_NONPHYSICAL, "a step produced rho <= 0, p <= 0 or a non-finite value");
     return HGKS_OK;

@@ -157,6 +157,12 @@ class Solver:
         self._check(lib().hgks_get_state(self._h, q.ctypes.data_as(_dp), C.byref(t)))
         return q, t.value
 
+    def get_time(self) -> float:
+        """The simulated time (and the non-physical check) without reading the state back."""
+        t = C.c_double(0.0)
+        self._check(lib().hgks_get_state(self._h, None, C.byref(t)))
+        return t.value
+
     def sync(self):
         self._check(lib().hgks_sync(self._h))
 

@@ -109,6 +109,7 @@ def test_bitwise_determinism_and_restart():
         qa, ta = a.get_state()
         b = make_solver(mesh, q0, precision=prec)
         b.step(6)
+        assert b.get_time() == ta          # time-only read back (no state copy)
         qb, tb = b.get_state()
         assert np.array_equal(qa, qb) and ta == tb
         c = make_solver(mesh, q0, precision=prec)
