@@ -442,15 +442,6 @@ __device__ __forceinline__ void mom_half(T U, T lam, T i2l, T sgn, T *m) {
     for (int n = 2; n < NM; ++n) m[n] = U * m[n - 1] + T(n - 1) * i2l * m[n - 2];
 }
 
-template <class T>
-__device__ __forceinline__ void mom_state(const State<T> &s, T K, Mom<T> &M) {
-    mom_full(s.U, s.i2l, M.u);
-    mom_full(s.V, s.i2l, M.v);
-    mom_full(s.W, s.i2l, M.w);
-    M.xi2 = K * s.i2l;
-    M.xi4 = K * (K + T(2)) * s.i2l * s.i2l;
-}
-
 // <u^P v^Q w^R (a.psi) psi>, psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2)
 template <class T, int P, int Q, int R>
 __device__ __forceinline__ void apsi(const Mom<T> &M, const T a[5], T out[5]) {
@@ -490,18 +481,6 @@ __device__ __forceinline__ void slope(const T b[5], const State<T> &s, T a[5]) {
     a[2] = s.tl * R2 - s.V * a[4];
     a[3] = s.tl * R3 - s.W * a[4];
     a[0] = b[0] - s.U * a[1] - s.V * a[2] - s.W * a[3] - T(0.5) * a[4] * s.e2;
-}
-
-// <a_1 u + a_2 v + a_3 w + A> = 0  =>  <(A.psi) psi> = -sum_j <u_j (a_j.psi) psi>
-template <class T>
-__device__ __forceinline__ void time_slope(const Mom<T> &M, const T a[3][5], const State<T> &s, T A[5]) {
-    T t0[5], t1[5], t2[5], b[5];
-    apsi<T, 1, 0, 0>(M, a[0], t0);
-    apsi<T, 0, 1, 0>(M, a[1], t1);
-    apsi<T, 0, 0, 1>(M, a[2], t2);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = -(t0[k] + t1[k] + t2[k]);
-    slope(b, s, A);
 }
 
 // Time-integral weights q0..q5 of Eq. (flux) over [0, d].
@@ -564,20 +543,6 @@ __device__ __forceinline__ void dir_deriv(const T g[5][3], const T e[3], const T
 #pragma unroll
     for (int q = 0; q < 5; ++q) d[q] = (g[q][0] * e[0] + g[q][1] * e[1] + g[q][2] * e[2]) * scale;
     rot_in(d, n, t1, t2, o);
-}
-
-// The interface equilibrium: compatibility condition Q0 = int_{u>0} psi g_l + int_{u<0} psi g_r.
-template <class T>
-__device__ __forceinline__ State<T> collide(const State<T> &l, const State<T> &r, const T ml[7], const T mr[7], T K,
-                                            T gam, T Kp3, T c4k) {
-    const T rho0 = l.rho * ml[0] + r.rho * mr[0];
-    const T mu0 = l.rho * ml[1] + r.rho * mr[1];
-    const T mv0 = l.rho * ml[0] * l.V + r.rho * mr[0] * r.V;
-    const T mw0 = l.rho * ml[0] * l.W + r.rho * mr[0] * r.W;
-    const T E0 = T(0.5) * (l.rho * (ml[2] + ml[0] * (l.V * l.V + l.W * l.W + (K + T(2)) * l.i2l)) +
-                           r.rho * (mr[2] + mr[0] * (r.V * r.V + r.W * r.W + (K + T(2)) * r.i2l)));
-    const T q0[5] = {rho0, mu0, mv0, mw0, E0};
-    return make_state(q0, gam, Kp3, c4k);
 }
 
 // tau = 0 (smooth flow, Sec. 5.1): f = g0 (1 + A t) with g0 the Maxwellian of the
@@ -681,86 +646,113 @@ __device__ __forceinline__ void gks_flux_tau0(const T ql[5], const T qr[5], cons
     euler_jvp_dir(n, gm1, u0, u20, H0, Qt, dF);
 }
 
+// Derivative of the second-moment flux rho <u_n u_a psi> of a Maxwellian along
+// the conservative perturbation D_a = dQ0/dx_a, summed over the three axes a:
+//   S = sum_a rho <u_n u_a (abar_a.psi) psi>_0
+// because abar_a.psi g0 is the derivative of g0 along x_a.  With theta = p/rho the
+// Gaussian moments are
+//   rho <u_n u_a>       = rho (U_n U_a + theta n_a)
+//   rho <u_n u_a u_c>   = rho (U_n U_a U_c + theta (U_n d_ac + U_a n_c + U_c n_a))
+//   rho <u_n u_a psi_4> = rho/2 (U_n U_a (|U|^2 + (K+7) theta) + n_a (theta |U|^2 + (K+5) theta^2)),
+// and the product rule with rho dU = D_m - U D_0, rho dtheta = dp - theta D_0 gives the
+// derivative without a division.  gsum holds dQ_l/dx_a + dQ_r/dx_a (D_a is half of it).
+template <class T>
+__device__ __forceinline__ void second_moment_jvp(const T n[3], const T U[3], T U2, T th, T K, T gm1,
+                                                  const T gsum[5][3], T S[5]) {
+    const T Un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
+    const T W = U2 + (K + T(7)) * th, Z = th * U2 + (K + T(5)) * th * th;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) S[q] = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T D0 = T(0.5) * gsum[0][a], D4 = T(0.5) * gsum[4][a];
+        T m[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m[c] = T(0.5) * gsum[1 + c][a] - U[c] * D0;        // rho dU
+        const T Um = U[0] * m[0] + U[1] * m[1] + U[2] * m[2];
+        // rho dtheta = dp - theta D0, dp = (gamma-1)(D4 - U.D_m + |U|^2 D0 / 2) = (gamma-1)(D4 - U.m - |U|^2 D0 / 2)
+        const T tp = gm1 * (D4 - Um - T(0.5) * U2 * D0) - th * D0;
+        const T mn = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+        const T Ua = U[a], ma = m[a], na = n[a];
+        S[0] += D0 * (Un * Ua + th * na) + (mn * Ua + Un * ma + tp * na);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T lin = (c == a ? Un : T(0)) + Ua * n[c] + U[c] * na;
+            const T dlin = (c == a ? mn : T(0)) + ma * n[c] + m[c] * na;
+            S[1 + c] += D0 * (Un * Ua * U[c] + th * lin) +
+                        ((mn * Ua + Un * ma) * U[c] + Un * Ua * m[c] + tp * lin + th * dlin);
+        }
+        const T dW = T(2) * Um + (K + T(7)) * tp;
+        const T dZ = tp * U2 + T(2) * th * Um + T(2) * (K + T(5)) * th * tp;
+        S[4] += T(0.5) * (D0 * (Un * Ua * W + na * Z) + (mn * Ua + Un * ma) * W + Un * Ua * dW + na * dZ);
+    }
+}
+
+// One initial (left or right) part of Eq. (flux) in the local frame: the half-space
+// integrals of u psi g_k (1 + spatial and temporal micro-slopes), returned as
+//   e0 = <u psi>,  e1 = sum_j <u u_j (a_j.psi) psi>,  e2 = <u (A.psi) psi>
+// over u > 0 (sgn = +1, the left state) or u < 0 (sgn = -1).  The time slope A
+// follows from <a_1 u + a_2 v + a_3 w + A> = 0, i.e. rho <(A.psi) psi> = -sum_j
+// dF_j/dQ dQ/dx_j (Euler Jacobians along the frame axes).
+template <class T>
+__device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], const T n[3], const T t1[3],
+                                             const T t2[3], T sgn, T K, T gam, T Kp3, T c4k, T e0[5], T e1[5],
+                                             T e2[5]) {
+    const State<T> s = make_state(Qf, gam, Kp3, c4k);
+    const T *e[3] = {n, t1, t2};
+    const T u[3] = {s.U, s.V, s.W};
+    const T u2 = s.U * s.U + s.V * s.V + s.W * s.W;
+    const T H = (Qf[4] + s.p) * s.ir;
+    T a[3][5], bt[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T d[5], b[5], jv[5];
+        dir_deriv(g, e[j], n, t1, t2, T(1), d);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) b[q] = d[q] * s.ir;
+        slope(b, s, a[j]);
+        euler_jvp_axis(j, gam - T(1), u, u2, H, b, jv);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bt[q] -= jv[q];
+    }
+    T A[5];
+    slope(bt, s, A);
+    Mom<T> M;
+    mom_half<T, 7>(s.U, s.lam, s.i2l, sgn, M.u);
+    mom_full(s.V, s.i2l, M.v);
+    mom_full(s.W, s.i2l, M.w);
+    M.xi2 = K * s.i2l;
+    M.xi4 = K * (K + T(2)) * s.i2l * s.i2l;
+    T t[5];
+    u_psi(M, e0);
+    apsi<T, 2, 0, 0>(M, a[0], e1);
+    apsi<T, 1, 1, 0>(M, a[1], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) e1[k] += t[k];
+    apsi<T, 1, 0, 1>(M, a[2], t);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) e1[k] += t[k];
+    apsi<T, 1, 0, 0>(M, A, e2);
+}
+
 // General collision time (Eq. flux with tau > 0): the equilibrium part and both
 // initial (left / right) parts, fitted linearly in time over [0, dt].
+//   * Equilibrium part, in the global frame: rho0 <u psi>_0 is the Euler flux of Q0,
+//     rho0 <u (Abar.psi) psi>_0 its time derivative through the Euler Jacobians
+//     (as at tau = 0), and rho0 sum_j <u u_j (abar_j.psi) psi>_0 the derivative of
+//     the second-moment flux (second_moment_jvp); the micro-slopes of g0 are never
+//     formed.  The sum over the frame directions j equals the sum over the axes.
+//   * Initial parts, in the local frame (n, t1, t2), where the half-space moments
+//     factorise (initial_part).
 template <class T>
 __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], const T qr[5], const T gr[5][3],
                                               const T n[3], T dt, const ProbDesc &P, T F[5], T dF[5]) {
-    const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma, c4k = T(4) / Kp3;
-    T t1[3], t2[3];
-    frame(n, t1, t2);
-    T Ql[5], Qr[5];
-    rot_in(ql, n, t1, t2, Ql);
-    rot_in(qr, n, t1, t2, Qr);
-    const State<T> sl = make_state(Ql, gam, Kp3, c4k), sr = make_state(Qr, gam, Kp3, c4k);
-    T ml[7], mr[7];
-    mom_half<T, 7>(sl.U, sl.lam, sl.i2l, T(1), ml);
-    mom_half<T, 7>(sr.U, sr.lam, sr.i2l, T(-1), mr);
-    const State<T> s0 = collide(sl, sr, ml, mr, K, gam, Kp3, c4k);
-    Mom<T> M0, Ml, Mr;
-    mom_state(s0, K, M0);
-    mom_state(sl, K, Ml);
-    mom_state(sr, K, Mr);
-    const T *e[3] = {n, t1, t2};
-    const T irl = sl.ir, irr = sr.ir, half_ir0 = T(0.5) * s0.ir;
-    T a0[3][5], al[3][5], ar[3][5];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        T dl[5], dr[5], b[5];
-        dir_deriv(gl, e[j], n, t1, t2, T(1), dl);
-        dir_deriv(gr, e[j], n, t1, t2, T(1), dr);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) b[q] = (dl[q] + dr[q]) * half_ir0;
-        slope(b, s0, a0[j]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) b[q] = dl[q] * irl;
-        slope(b, sl, al[j]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) b[q] = dr[q] * irr;
-        slope(b, sr, ar[j]);
-    }
-    T A0[5], Al[5], Ar[5];
-    time_slope(M0, a0, s0, A0);
-    time_slope(Ml, al, sl, Al);
-    time_slope(Mr, ar, sr, Ar);
-    // the initial parts act on their half spaces
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        Ml.u[k] = ml[k];
-        Mr.u[k] = mr[k];
-    }
-    T up0[5], e01[5], uA0[5], el0[5], el1[5], el2[5], er0[5], er1[5], er2[5], t[5];
-    u_psi(M0, up0);
-    apsi<T, 1, 0, 0>(M0, A0, uA0);
-    apsi<T, 2, 0, 0>(M0, a0[0], e01);
-    apsi<T, 1, 1, 0>(M0, a0[1], t);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) e01[k] += t[k];
-    apsi<T, 1, 0, 1>(M0, a0[2], t);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) e01[k] += t[k];
-    u_psi(Ml, el0);
-    apsi<T, 2, 0, 0>(Ml, al[0], el1);
-    apsi<T, 1, 1, 0>(Ml, al[1], t);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) el1[k] += t[k];
-    apsi<T, 1, 0, 1>(Ml, al[2], t);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) el1[k] += t[k];
-    apsi<T, 1, 0, 0>(Ml, Al, el2);
-    u_psi(Mr, er0);
-    apsi<T, 2, 0, 0>(Mr, ar[0], er1);
-    apsi<T, 1, 1, 0>(Mr, ar[1], t);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) er1[k] += t[k];
-    apsi<T, 1, 0, 1>(Mr, ar[2], t);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) er1[k] += t[k];
-    apsi<T, 1, 0, 0>(Mr, Ar, er2);
+    const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma, gm1 = gam - T(1), c4k = T(4) / Kp3;
+    const SideG<T> sl = side_state(ql, n, gm1), sr = side_state(qr, n, gm1);
+    // time-integral weights: F = (4 I(dt/2) - I(dt)) / dt, dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
+    const T pl = sl.rho * sl.i2l, pr = sr.rho * sr.i2l;
     T tau = T(0);
-    if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(sl.p - sr.p) / (sl.p + sr.p) * dt;
-    // F^n, dF^n from int_0^dt and int_0^(dt/2) (Eq. expansion-1):
-    //   F = (4 I(dt/2) - I(dt)) / dt,  dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
+    if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
     T q1[6], qh[6], cF[6], cD[6];
     q_coef(dt, tau, q1);
     q_coef(T(0.5) * dt, tau, qh);
@@ -770,18 +762,84 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
         cF[k] = (T(4) * qh[k] - q1[k]) * idt;
         cD[k] = T(4) * (q1[k] - T(2) * qh[k]) * idt * idt;
     }
-    T Fl[5], dFl[5];
+    // collision: Q0 = int_{u_n>0} psi g_l + int_{u_n<0} psi g_r (normal moments only)
+    T ml[3], mr[3];
+    mom_half<T, 3>(sl.un, sl.lam, sl.i2l, T(1), ml);
+    mom_half<T, 3>(sr.un, sr.lam, sr.i2l, T(-1), mr);
+    const T wl = sl.rho * ml[0], wr = sr.rho * mr[0];
+    const T rho0 = wl + wr;
+    const T sn = sl.rho * (ml[1] - sl.un * ml[0]) + sr.rho * (mr[1] - sr.un * mr[0]);
+    T mom0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mom0[a] = wl * sl.u[a] + wr * sr.u[a] + sn * n[a];
+    const T E0 = T(0.5) * (sl.rho * ml[2] + wl * (sl.q2 - sl.un * sl.un + (K + T(2)) * sl.i2l) +
+                           sr.rho * mr[2] + wr * (sr.q2 - sr.un * sr.un + (K + T(2)) * sr.i2l));
+    const T ir0 = hg_rcp(rho0);
+    const T u0[3] = {mom0[0] * ir0, mom0[1] * ir0, mom0[2] * ir0};
+    const T u20 = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+    const T p0 = gm1 * (E0 - T(0.5) * rho0 * u20);
+    const T H0 = (E0 + p0) * ir0;
+    T gsum[5][3];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gsum[q][a] = gl[q][a] + gr[q][a];
+    // equilibrium part
+    T Qt[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T d0[5], jv[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) d0[q] = T(0.5) * gsum[q][j];
+        euler_jvp_axis(j, gm1, u0, u20, H0, d0, jv);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Qt[q] -= jv[q];
+    }
+    T Fe[5], Ft[5], Se[5];
+    const T un0 = u0[0] * n[0] + u0[1] * n[1] + u0[2] * n[2];
+    Fe[0] = rho0 * un0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Fe[1 + a] = Fe[0] * u0[a] + p0 * n[a];
+    Fe[4] = (E0 + p0) * un0;
+    euler_jvp_dir(n, gm1, u0, u20, H0, Qt, Ft);
+    second_moment_jvp(n, u0, u20, p0 * ir0, K, gm1, gsum, Se);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        Fl[k] = s0.rho * (cF[0] * up0[k] + cF[1] * e01[k] + cF[2] * uA0[k]) +
-                sl.rho * (cF[3] * el0[k] + cF[4] * el1[k] + cF[5] * el2[k]) +
-                sr.rho * (cF[3] * er0[k] + cF[4] * er1[k] + cF[5] * er2[k]);
-        dFl[k] = s0.rho * (cD[0] * up0[k] + cD[1] * e01[k] + cD[2] * uA0[k]) +
-                 sl.rho * (cD[3] * el0[k] + cD[4] * el1[k] + cD[5] * el2[k]) +
-                 sr.rho * (cD[3] * er0[k] + cD[4] * er1[k] + cD[5] * er2[k]);
+        F[k] = cF[0] * Fe[k] + cF[1] * Se[k] + cF[2] * Ft[k];
+        dF[k] = cD[0] * Fe[k] + cD[1] * Se[k] + cD[2] * Ft[k];
     }
-    rot_out(Fl, n, t1, t2, F);
-    rot_out(dFl, n, t1, t2, dF);
+    // initial parts, local frame
+    T t1[3], t2[3];
+    frame(n, t1, t2);
+    T Fl[5], dFl[5];
+    {
+        T Qf[5], e0[5], e1[5], e2[5];
+        rot_in(ql, n, t1, t2, Qf);
+        initial_part(Qf, gl, n, t1, t2, T(1), K, gam, Kp3, c4k, e0, e1, e2);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            Fl[k] = sl.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
+            dFl[k] = sl.rho * (cD[3] * e0[k] + cD[4] * e1[k] + cD[5] * e2[k]);
+        }
+    }
+    {
+        T Qf[5], e0[5], e1[5], e2[5];
+        rot_in(qr, n, t1, t2, Qf);
+        initial_part(Qf, gr, n, t1, t2, T(-1), K, gam, Kp3, c4k, e0, e1, e2);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            Fl[k] += sr.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
+            dFl[k] += sr.rho * (cD[3] * e0[k] + cD[4] * e1[k] + cD[5] * e2[k]);
+        }
+    }
+    T Fg[5], dFg[5];
+    rot_out(Fl, n, t1, t2, Fg);
+    rot_out(dFl, n, t1, t2, dFg);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        F[k] += Fg[k];
+        dF[k] += dFg[k];
+    }
 }
 
 // Positivity fallback (not in the paper, which has no limiter): at a Gauss point
