@@ -33,6 +33,19 @@
  * its node p (Sec. 3.1 item 1); the neighbour across face p is "i_{p+1}" of
  * Sec. 2.3.  Meshes may be periodic: period[a] > 0 identifies x_a with
  * x_a + period[a]; each cell is unwrapped around its first node.
+ *
+ * Boundaries (Algorithm 1 gives a boundary face a ghost neighbour "according to
+ * the boundary condition"; the reading here is the transmissive wall): an axis
+ * with period 0 ends in two planar walls at the extreme node coordinates.  The
+ * ghost across a wall face is the mirror image of the wall cell in the wall
+ * plane and holds the wall cell's state.  A ghost's face neighbours are the
+ * mirror images of the wall cell's neighbours (so a two-layer stencil near a
+ * wall contains mirror images of interior cells, and near an edge images under
+ * two mirrors), all holding the state of the cell they image.  Stencil members
+ * are therefore (cell, x -> s*x + o per axis) pairs: s = 1 for periodic images,
+ * s = -1 for mirrors.  Because a ghost's stencil and data are the mirror image of
+ * the wall cell's, so is its reconstruction: at a wall Gauss point its value is
+ * the wall cell's and its gradient the wall cell's reflected in the wall.
  */
 #include <math.h>
 #include <stdint.h>
@@ -61,31 +74,36 @@ typedef struct {
     double gamma_lin;      /* linear weight of each sub-stencil; gamma_0 = 1 - 4*gamma_lin */
 } orc_params;
 
+/* placement of a stencil member: x -> s*x + o on each axis */
+typedef struct { double s[3], o[3]; } xform;
+static const xform XID = {{1.0, 1.0, 1.0}, {0.0, 0.0, 0.0}};
+
 typedef struct {
     int64_t nc, nn, nf;
     double period[3];
+    double lo[3], hi[3];            /* node extent per axis (the walls of non-periodic axes) */
     double (*vert)[4][3];          /* unwrapped vertices of each cell */
     double *vol;
     double (*cen)[3];
     double *h;                      /* |Omega|^(1/3): length scale of the local coordinates */
     double *hdt;                    /* 6|Omega| / sum of face areas */
     /* faces */
-    int64_t (*fcell)[2];            /* left, right */
+    int64_t (*fcell)[2];            /* left, right (-1: a wall face, the right side is the ghost) */
     double (*fshift)[3];            /* right cell's image in the left cell's frame = right + fshift */
     double (*fnrm)[3];
     double *farea;
     double (*fgp)[3][3];            /* Gauss points, left cell's frame */
     int64_t (*cface)[4];            /* face opposite local node p */
     /* neighbours i_1..i_4 */
-    int64_t (*nb)[4];
-    double (*nbshift)[4][3];
+    int64_t (*nb)[4];               /* the cell itself across a wall face */
+    xform (*nbx)[4];                /* placement of that neighbour (a mirror across a wall face) */
     /* big stencil and the four sub-stencils (members other than the cell itself) */
     int *nsten;
     int64_t (*sten)[MAXSTEN];
-    double (*stsh)[MAXSTEN][3];
+    xform (*stx)[MAXSTEN];
     int (*nsub)[4];
     int64_t (*sub)[4][MAXSUB];
-    double (*subsh)[4][MAXSUB][3];
+    xform (*subx)[4][MAXSUB];
 } orc_mesh;
 
 /* ------------------------------------------------------------------------- */
@@ -247,8 +265,18 @@ static void sort3(int64_t *k) {
 
 void orc_mesh_free(orc_mesh *m);
 
-static int same_member(int64_t c1, const double *s1, int64_t c2, const double *s2) {
-    return c1 == c2 && fabs(s1[0] - s2[0]) < 1e-9 && fabs(s1[1] - s2[1]) < 1e-9 && fabs(s1[2] - s2[2]) < 1e-9;
+static int same_member(int64_t c1, const xform *x1, int64_t c2, const xform *x2) {
+    if (c1 != c2) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (x1->s[a] != x2->s[a] || fabs(x1->o[a] - x2->o[a]) > 1e-9 * (1.0 + fabs(x1->o[a]))) return 0;
+    return 1;
+}
+
+/* x -> A(B(x)) */
+static xform compose(const xform *A, const xform *B) {
+    xform r;
+    for (int a = 0; a < 3; ++a) { r.s[a] = A->s[a] * B->s[a]; r.o[a] = A->s[a] * B->o[a] + A->o[a]; }
+    return r;
 }
 
 orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t *cell_nodes,
@@ -264,7 +292,10 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
     m->hdt = malloc(sizeof(double) * nc);
     m->cface = malloc(sizeof(*m->cface) * nc);
     m->nb = malloc(sizeof(*m->nb) * nc);
-    m->nbshift = malloc(sizeof(*m->nbshift) * nc);
+    m->nbx = malloc(sizeof(*m->nbx) * nc);
+    for (int a = 0; a < 3; ++a) { m->lo[a] = INFINITY; m->hi[a] = -INFINITY; }
+    for (int64_t k = 0; k < nn; ++k)
+        for (int a = 0; a < 3; ++a) { m->lo[a] = fmin(m->lo[a], xyz[3 * k + a]); m->hi[a] = fmax(m->hi[a], xyz[3 * k + a]); }
 
     /* unwrap every cell around its first node; volume, centroid */
     for (int64_t c = 0; c < nc; ++c) {
@@ -311,10 +342,7 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
     for (int64_t k = 0; k < nc * 4;) {
         int64_t j = k + 1;
         while (j < nc * 4 && memcmp(fr[j].key, fr[k].key, sizeof(fr[k].key)) == 0) ++j;
-        if (j - k != 2) {
-            set_err(err, errlen, j - k == 1 ? "boundary face (only periodic meshes are supported)" : "non-conforming face");
-            free(fr); orc_mesh_free(m); return NULL;
-        }
+        if (j - k > 2) { set_err(err, errlen, "non-conforming face"); free(fr); orc_mesh_free(m); return NULL; }
         ++nf; k = j;
     }
     m->nf = nf;
@@ -325,20 +353,18 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
     m->fgp = malloc(sizeof(*m->fgp) * nf);
     double *asum = calloc((size_t)nc, sizeof(double));
     int64_t f = 0;
-    for (int64_t k = 0; k < nc * 4; k += 2, ++f) {
-        const face_rec *A = &fr[k], *B = &fr[k + 1];          /* A->cell <= B->cell */
-        int64_t l = A->cell, r = B->cell;
-        int pl = A->p, pr = B->p;
-        m->fcell[f][0] = l; m->fcell[f][1] = r;
-        m->cface[l][pl] = f; m->cface[r][pr] = f;
-        /* face vertices in the left frame, and the right cell's image shift */
+    for (int64_t k = 0; k < nc * 4; ++f) {
+        const int wall = k + 1 >= nc * 4 || memcmp(fr[k + 1].key, fr[k].key, sizeof(fr[k].key)) != 0;
+        const face_rec *A = &fr[k], *B = wall ? NULL : &fr[k + 1];     /* A->cell <= B->cell */
+        k += wall ? 1 : 2;
+        int64_t l = A->cell;
+        int pl = A->p;
+        m->fcell[f][0] = l;
+        m->cface[l][pl] = f;
+        /* face vertices in the left frame */
         double tri[3][3];
         int t = 0;
         for (int q = 0; q < 4; ++q) if (q != pl) { memcpy(tri[t], m->vert[l][q], sizeof(tri[t])); ++t; }
-        int64_t n0 = cell_nodes[l * 4 + (pl == 0 ? 1 : 0)];
-        int ql = -1, qr = -1;
-        for (int q = 0; q < 4; ++q) { if (cell_nodes[l * 4 + q] == n0) ql = q; if (cell_nodes[r * 4 + q] == n0) qr = q; }
-        sub3(m->vert[l][ql], m->vert[r][qr], m->fshift[f]);
         double e1[3], e2[3], nrm[3];
         sub3(tri[1], tri[0], e1);
         sub3(tri[2], tri[0], e2);
@@ -354,15 +380,48 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
         /* 3-point degree-2 rule: barycentric permutations of (2/3, 1/6, 1/6) */
         for (int g = 0; g < 3; ++g)
             for (int a = 0; a < 3; ++a) {
-                double s = 0.0;
-                for (int v = 0; v < 3; ++v) s += (v == g ? 2.0 / 3.0 : 1.0 / 6.0) * tri[v][a];
-                m->fgp[f][g][a] = s;
+                double s_ = 0.0;
+                for (int v = 0; v < 3; ++v) s_ += (v == g ? 2.0 / 3.0 : 1.0 / 6.0) * tri[v][a];
+                m->fgp[f][g][a] = s_;
             }
         asum[l] += m->farea[f];
+        if (wall) {
+            /* a wall of a non-periodic axis: all three nodes on the lowest or highest coordinate */
+            int axis = -1;
+            double w = 0.0;
+            for (int a = 0; a < 3 && axis < 0; ++a) {
+                if (m->period[a] > 0.0) continue;
+                const double x0 = xyz[3 * A->key[0] + a], x1 = xyz[3 * A->key[1] + a], x2 = xyz[3 * A->key[2] + a];
+                if (x0 == x1 && x1 == x2 && (x0 == m->lo[a] || x0 == m->hi[a])) { axis = a; w = x0; }
+            }
+            if (axis < 0) {
+                set_err(err, errlen, "boundary face off the walls (an unmatched face must lie on the lowest or highest "
+                                     "coordinate of a non-periodic axis)");
+                free(fr); free(asum); orc_mesh_free(m); return NULL;
+            }
+            m->fcell[f][1] = -1;
+            for (int a = 0; a < 3; ++a) m->fshift[f][a] = 0.0;
+            m->nb[l][pl] = l;
+            m->nbx[l][pl] = XID;
+            m->nbx[l][pl].s[axis] = -1.0;
+            m->nbx[l][pl].o[axis] = 2.0 * w;
+            continue;
+        }
+        int64_t r = B->cell;
+        int pr = B->p;
+        m->fcell[f][1] = r;
+        m->cface[r][pr] = f;
+        /* the right cell's image shift in the left frame */
+        int64_t n0 = cell_nodes[l * 4 + (pl == 0 ? 1 : 0)];
+        int ql = -1, qr = -1;
+        for (int q = 0; q < 4; ++q) { if (cell_nodes[l * 4 + q] == n0) ql = q; if (cell_nodes[r * 4 + q] == n0) qr = q; }
+        sub3(m->vert[l][ql], m->vert[r][qr], m->fshift[f]);
         asum[r] += m->farea[f];
         m->nb[l][pl] = r;
         m->nb[r][pr] = l;
-        for (int a = 0; a < 3; ++a) { m->nbshift[l][pl][a] = m->fshift[f][a]; m->nbshift[r][pr][a] = -m->fshift[f][a]; }
+        m->nbx[l][pl] = XID;
+        m->nbx[r][pr] = XID;
+        for (int a = 0; a < 3; ++a) { m->nbx[l][pl].o[a] = m->fshift[f][a]; m->nbx[r][pr].o[a] = -m->fshift[f][a]; }
     }
     free(fr);
     for (int64_t c = 0; c < nc; ++c) m->hdt[c] = 6.0 * m->vol[c] / asum[c];
@@ -371,31 +430,30 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
     /* two-layer stencil (Algorithm 1, self excluded) and the tet sub-stencils (Sec. 2.3) */
     m->nsten = malloc(sizeof(int) * nc);
     m->sten = malloc(sizeof(*m->sten) * nc);
-    m->stsh = malloc(sizeof(*m->stsh) * nc);
+    m->stx = malloc(sizeof(*m->stx) * nc);
     m->nsub = malloc(sizeof(*m->nsub) * nc);
     m->sub = malloc(sizeof(*m->sub) * nc);
-    m->subsh = malloc(sizeof(*m->subsh) * nc);
-    static const double zero[3] = {0, 0, 0};
+    m->subx = malloc(sizeof(*m->subx) * nc);
     /* S_1 = {i1,i2,i3} + N(i1), S_2 = {i1,i2,i4} + N(i2), S_3 = {i2,i3,i4} + N(i3), S_4 = {i3,i1,i4} + N(i4) */
     static const int SUBFIRST[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
     for (int64_t i = 0; i < nc; ++i) {
+        /* a neighbour's neighbours are placed by composing the two placements */
         int n = 0;
         for (int p = 0; p < 4; ++p) {
-            int dup = same_member(m->nb[i][p], m->nbshift[i][p], i, zero);
-            for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], m->stsh[i][k], m->nb[i][p], m->nbshift[i][p]);
-            if (!dup) { m->sten[i][n] = m->nb[i][p]; memcpy(m->stsh[i][n], m->nbshift[i][p], sizeof(double) * 3); ++n; }
+            int dup = same_member(m->nb[i][p], &m->nbx[i][p], i, &XID);
+            for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], &m->stx[i][k], m->nb[i][p], &m->nbx[i][p]);
+            if (!dup) { m->sten[i][n] = m->nb[i][p]; m->stx[i][n] = m->nbx[i][p]; ++n; }
         }
         for (int p = 0; p < 4; ++p) {
             int64_t j = m->nb[i][p];
             for (int q = 0; q < 4; ++q) {
                 int64_t c = m->nb[j][q];
-                double s[3];
-                for (int a = 0; a < 3; ++a) s[a] = m->nbshift[i][p][a] + m->nbshift[j][q][a];
-                int dup = same_member(c, s, i, zero);
-                for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], m->stsh[i][k], c, s);
+                xform x = compose(&m->nbx[i][p], &m->nbx[j][q]);
+                int dup = same_member(c, &x, i, &XID);
+                for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], &m->stx[i][k], c, &x);
                 if (!dup) {
                     if (n >= MAXSTEN) { set_err(err, errlen, "stencil too large"); orc_mesh_free(m); return NULL; }
-                    m->sten[i][n] = c; memcpy(m->stsh[i][n], s, sizeof(s)); ++n;
+                    m->sten[i][n] = c; m->stx[i][n] = x; ++n;
                 }
             }
         }
@@ -405,17 +463,16 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
             for (int t = 0; t < 3; ++t) {
                 int p = SUBFIRST[s_][t];
                 int dup = 0;
-                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], m->subsh[i][s_][u], m->nb[i][p], m->nbshift[i][p]);
-                if (!dup) { m->sub[i][s_][k] = m->nb[i][p]; memcpy(m->subsh[i][s_][k], m->nbshift[i][p], sizeof(double) * 3); ++k; }
+                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], &m->subx[i][s_][u], m->nb[i][p], &m->nbx[i][p]);
+                if (!dup) { m->sub[i][s_][k] = m->nb[i][p]; m->subx[i][s_][k] = m->nbx[i][p]; ++k; }
             }
             int64_t j = m->nb[i][s_];
             for (int q = 0; q < 4; ++q) {
                 int64_t c = m->nb[j][q];
-                double s[3];
-                for (int a = 0; a < 3; ++a) s[a] = m->nbshift[i][s_][a] + m->nbshift[j][q][a];
-                int dup = same_member(c, s, i, zero);
-                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], m->subsh[i][s_][u], c, s);
-                if (!dup) { m->sub[i][s_][k] = c; memcpy(m->subsh[i][s_][k], s, sizeof(s)); ++k; }
+                xform x = compose(&m->nbx[i][s_], &m->nbx[j][q]);
+                int dup = same_member(c, &x, i, &XID);
+                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], &m->subx[i][s_][u], c, &x);
+                if (!dup) { m->sub[i][s_][k] = c; m->subx[i][s_][k] = x; ++k; }
             }
             m->nsub[i][s_] = k;
         }
@@ -427,8 +484,8 @@ void orc_mesh_free(orc_mesh *m) {
     if (!m) return;
     free(m->vert); free(m->vol); free(m->cen); free(m->h); free(m->hdt);
     free(m->fcell); free(m->fshift); free(m->fnrm); free(m->farea); free(m->fgp);
-    free(m->cface); free(m->nb); free(m->nbshift);
-    free(m->nsten); free(m->sten); free(m->stsh); free(m->nsub); free(m->sub); free(m->subsh);
+    free(m->cface); free(m->nb); free(m->nbx);
+    free(m->nsten); free(m->sten); free(m->stx); free(m->nsub); free(m->sub); free(m->subx);
     free(m);
 }
 
@@ -455,7 +512,7 @@ int orc_mesh_stencil(const orc_mesh *m, int64_t i, int64_t *members, double *shi
     int n = m->nsten[i];
     for (int k = 0; k < n; ++k) {
         if (members) members[k] = m->sten[i][k];
-        if (shifts) memcpy(shifts + 3 * k, m->stsh[i][k], sizeof(double) * 3);
+        if (shifts) memcpy(shifts + 3 * k, m->stx[i][k].o, sizeof(double) * 3);   /* offsets (s = 1 unless mirrored) */
     }
     for (int s = 0; s < 4; ++s) {
         if (nsub) nsub[s] = m->nsub[i][s];
@@ -479,9 +536,9 @@ typedef struct {
     double mean_i[9];      /* mean over the cell of xi^d */
 } orc_weno;
 
-/* Shifted copy of a member's vertices in the target cell's frame. */
-static void member_vertices(const orc_mesh *m, int64_t k, const double *shift, double v[4][3]) {
-    for (int q = 0; q < 4; ++q) for (int a = 0; a < 3; ++a) v[q][a] = m->vert[k][q][a] + shift[a];
+/* A member's vertices placed in the target cell's frame (periodic image or mirror). */
+static void member_vertices(const orc_mesh *m, int64_t k, const xform *x, double v[4][3]) {
+    for (int q = 0; q < 4; ++q) for (int a = 0; a < 3; ++a) v[q][a] = x->s[a] * m->vert[k][q][a] + x->o[a];
 }
 
 static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i, orc_weno *w) {
@@ -493,7 +550,7 @@ static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, in
     double A[MAXSTEN * 9], B[MAXSTEN * 5];
     for (int k = 0; k < K; ++k) {
         double v[4][3], mk[9];
-        member_vertices(m, m->sten[i][k], m->stsh[i][k], v);
+        member_vertices(m, m->sten[i][k], &m->stx[i][k], v);
         tet_monomial_means(v, ci, hi, mk);
         for (int d = 0; d < 9; ++d) A[k * 9 + d] = mk[d] - w->mean_i[d];
         for (int q = 0; q < 5; ++q) B[k * 5 + q] = Q[5 * m->sten[i][k] + q] - Q[5 * i + q];
@@ -507,7 +564,7 @@ static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, in
         double As[MAXSUB * 3], Bs[MAXSUB * 5], Xs[3 * 5];
         for (int k = 0; k < n; ++k) {
             double v[4][3], mk[9];
-            member_vertices(m, m->sub[i][s][k], m->subsh[i][s][k], v);
+            member_vertices(m, m->sub[i][s][k], &m->subx[i][s][k], v);
             tet_monomial_means(v, ci, hi, mk);
             for (int d = 0; d < 3; ++d) As[k * 3 + d] = mk[d] - w->mean_i[d];
             for (int q = 0; q < 5; ++q) Bs[k * 5 + q] = Q[5 * m->sub[i][s][k] + q] - Q[5 * i + q];
@@ -899,6 +956,37 @@ static void gauss_point_fallback(const orc_params *p, const double *ql_cell, con
     }
 }
 
+/* S * sum_G w_G (F, dF) of face f.  At a wall face the right side is the ghost:
+ * the wall cell's reconstruction mirrored, i.e. the same value at the (in-wall)
+ * Gauss point and the gradient reflected in the wall. */
+static int face_flux(const orc_mesh *m, const orc_params *p, const double *Q, const orc_weno *W, int64_t f,
+                     double dt, double out[10]) {
+    const int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+    const double *n = m->fnrm[f];
+    double Ff[5] = {0}, dFf[5] = {0};
+    int rc = ORC_OK;
+    for (int g = 0; g < 3; ++g) {
+        double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5];
+        for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
+        weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
+        if (r >= 0) {
+            weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+        } else {
+            for (int q = 0; q < 5; ++q) {
+                const double gn = gl[q][0] * n[0] + gl[q][1] * n[1] + gl[q][2] * n[2];
+                vr[q] = vl[q];
+                for (int a = 0; a < 3; ++a) gr[q][a] = gl[q][a] - 2.0 * gn * n[a];
+            }
+        }
+        gauss_point_fallback(p, Q + 5 * l, Q + 5 * (r >= 0 ? r : l), vl, gl, vr, gr);
+        int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], n, dt, F, dF);
+        if (r_ > rc) rc = r_;
+        for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
+    }
+    for (int q = 0; q < 5; ++q) { out[q] = Ff[q] * m->farea[f]; out[5 + q] = dFf[q] * m->farea[f]; }
+    return rc;
+}
+
 int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, double *L, double *dL) {
     orc_weno *W = malloc(sizeof(orc_weno) * m->nc);
     double (*FF)[10] = malloc(sizeof(double[10]) * m->nf);   /* S * sum_G w_G (F, dF) per face */
@@ -911,19 +999,8 @@ int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, 
     if (rc == ORC_OK) {
 #pragma omp parallel for schedule(static) reduction(max: rc)
         for (int64_t f = 0; f < m->nf; ++f) {
-            int64_t l = m->fcell[f][0], r = m->fcell[f][1];
-            double Ff[5] = {0}, dFf[5] = {0};
-            for (int g = 0; g < 3; ++g) {
-                double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5];
-                for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
-                weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
-                weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
-                gauss_point_fallback(p, Q + 5 * l, Q + 5 * r, vl, gl, vr, gr);
-                int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
-                if (r_ > rc) rc = r_;
-                for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
-            }
-            for (int q = 0; q < 5; ++q) { FF[f][q] = Ff[q] * m->farea[f]; FF[f][5 + q] = dFf[q] * m->farea[f]; }
+            int r_ = face_flux(m, p, Q, W, f, dt, FF[f]);
+            if (r_ > rc) rc = r_;
         }
     }
     if (rc == ORC_OK) {
@@ -1072,6 +1149,7 @@ static void mark_stencils(const orc_mesh *m, const unsigned char *in, unsigned c
 static void mark_faces(const orc_mesh *m, const unsigned char *cells, unsigned char *faces, unsigned char *both) {
     for (int64_t f = 0; f < m->nf; ++f) {
         int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+        if (r < 0) r = l;                              /* wall face: the ghost images l */
         if (cells[l] || cells[r]) { faces[f] = 1; both[l] = both[r] = 1; }
     }
 }
@@ -1094,19 +1172,8 @@ static int rhs_subset(const orc_mesh *m, const orc_params *p, const double *Q, d
 #pragma omp parallel for schedule(dynamic, 64) reduction(max: rc)
         for (int64_t f = 0; f < m->nf; ++f) {
             if (!faces[f]) continue;
-            int64_t l = m->fcell[f][0], r = m->fcell[f][1];
-            double Ff[5] = {0}, dFf[5] = {0};
-            for (int g = 0; g < 3; ++g) {
-                double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5];
-                for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
-                weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
-                weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
-                gauss_point_fallback(p, Q + 5 * l, Q + 5 * r, vl, gl, vr, gr);
-                int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->fnrm[f], dt, F, dF);
-                if (r_ > rc) rc = r_;
-                for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
-            }
-            for (int q = 0; q < 5; ++q) { FF[f][q] = Ff[q] * m->farea[f]; FF[f][5 + q] = dFf[q] * m->farea[f]; }
+            int r_ = face_flux(m, p, Q, W, f, dt, FF[f]);
+            if (r_ > rc) rc = r_;
         }
     }
     if (rc == ORC_OK)

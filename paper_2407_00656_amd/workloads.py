@@ -317,9 +317,17 @@ class SodCase:
         return q
 
 
-def sod_box(nx: int, ny: int, nz: int, jitter: float = 0.1, seed: int = SEED_ADVECTION + 7):
-    """The periodic doubled Sod tube: [0, 2] x [0, ny/nx * 2] x [0, nz/nx * 2] with cubes
-    of edge 2/nx, every axis periodic."""
+def sod_box(nx: int, ny: int, nz: int, jitter: float = 0.1, seed: int = SEED_ADVECTION + 7, walls: bool = False):
+    """Sod's tube on jittered Kuhn tetrahedra.
+
+    walls=False: the periodic doubled tube, [0, 2] x [0, ny h] x [0, nz h] with cubes of
+    edge h = 2/nx, every axis periodic (each half is one tube until t = 0.286).
+    walls=True: the tube itself, [0, 1] x [0, ny h] x [0, nz h] with h = 1/nx, the
+    diaphragm at x = 0.5, transmissive walls at x = 0 and x = 1, y and z periodic."""
+    if walls:
+        h = 1.0 / nx
+        mesh = kuhn_box((nx, ny, nz), (1.0, ny * h, nz * h), jitter, seed, periodic=(False, True, True))
+        return mesh, SodCase(x0=-0.5)
     h = 2.0 / nx
     mesh = kuhn_box((nx, ny, nz), (2.0, ny * h, nz * h), jitter, seed)
     return mesh, SodCase()

@@ -28,3 +28,28 @@ def advection_case(n, seed=None, **kw):
     mesh = W.kuhn_box(n, seed=W.SEED_ADVECTION if seed is None else seed)
     case = W.AdvectionCase(**kw)
     return mesh, case, case.conservative(mesh)
+
+
+def mirror_double(mesh, axis):
+    """The mesh and its mirror image across its highest wall on `axis`, as one mesh
+    periodic on that axis with twice the length.  Cells [0, nc) are the original
+    ones, cells [nc, 2 nc) their mirror images in the same order.  On this mesh the
+    state (q, q) is mirror-symmetric about both walls of the original box, so the
+    original cells see real cells where the wall mesh has ghosts."""
+    x = mesh.nodes[:, axis]
+    lo, hi = x.min(), x.max()
+    assert lo == 0.0 and mesh.period[axis] == 0.0
+    inner = (x > lo) & (x < hi)
+    n0 = mesh.nodes.shape[0]
+    copy_id = np.arange(n0)
+    copy_id[inner] = n0 + np.arange(int(inner.sum()))
+    extra = mesh.nodes[inner].copy()
+    extra[:, axis] = 2.0 * hi - extra[:, axis]
+    nodes = np.concatenate([mesh.nodes, extra])
+    cells = np.concatenate([mesh.cell_nodes, copy_id[mesh.cell_nodes]])
+    verts_m = mesh.cell_vertices.copy()
+    verts_m[:, :, axis] = 2.0 * hi - verts_m[:, :, axis]
+    period = mesh.period.copy()
+    period[axis] = 2.0 * hi
+    return W.TetMesh(nodes=nodes, cell_nodes=cells, period=period,
+                     cell_vertices=np.concatenate([mesh.cell_vertices, verts_m]))
