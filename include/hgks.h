@@ -108,11 +108,18 @@ hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream,
  *   xyz         [n_nodes][3] node coordinates
  *   cell_nodes  [n_cells][nodes_per_cell] node ids; nodes_per_cell must be 4
  *   period      [3]: period[a] > 0 identifies x_a with x_a + period[a] (NULL = none)
- *   n_bfaces, bface_nodes, bface_kind: boundary faces; must be 0 / NULL
- *               (every face must be shared by two cells, e.g. a periodic box)
+ *               An axis with period 0 ends in two transmissive walls, the planes
+ *               through its lowest and highest node coordinate: every face that
+ *               belongs to one cell only must lie in one of them (all three nodes
+ *               there).  Algorithm 1 gives such a face a ghost neighbour "according
+ *               to the boundary condition"; here the ghost is the mirror image of
+ *               the wall cell in the wall, holding the wall cell's state, and a
+ *               ghost's neighbours are the mirror images of the wall cell's.
+ *   n_bfaces, bface_nodes, bface_kind: other boundary kinds; must be 0 / NULL
  * Replaces any previous mesh and state.
  * Errors: INVALID_ARG, BAD_MESH (degenerate cell, a face shared by more than two
- * cells, a boundary face, a rank-deficient least-squares stencil), OOM, DEVICE.
+ * cells, an unshared face off the walls, a stencil reaching both walls of an axis,
+ * a rank-deficient least-squares stencil), OOM, DEVICE.
  */
 hgks_status hgks_mesh_upload(hgks_ctx *ctx, int64_t n_nodes, const double *xyz,
                              int64_t n_cells, int nodes_per_cell, const int64_t *cell_nodes,
@@ -183,7 +190,8 @@ typedef struct hgks_pool hgks_pool;
 
 /* hbm_budget: admission limit on the summed footprints of the slots (0 = none). */
 hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hgks_pool **out);
-/* Bytes a context with this mesh size will hold (used for admission). */
+/* Bytes a context with this mesh size will hold (used for admission; exact for a
+ * periodic mesh, wall faces add 8 + 176 + 80 bytes each). */
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int nodes_per_cell, size_t *bytes);
 /* Adds a context (mesh uploaded, state initialised); returns its slot id.
  * Errors: STATE, INVALID_ARG (other device), OOM (budget exceeded). */

@@ -80,6 +80,7 @@ struct hgks_ctx {
     bool user_alloc = false;
     std::string err;
     bool has_mesh = false, has_state = false;
+    bool walls = false;           // the mesh has wall faces (a non-periodic axis)
     int64_t nc = 0, nf = 0;
     std::vector<int64_t> perm;
     std::vector<int32_t> colour_offsets;   // face offsets of each colour class
@@ -193,14 +194,14 @@ void enqueue_step(hgks_ctx *c, double dt_fixed) {
     hipStream_t s = c->stream;
     timed(c, 0, [&] { launch_dt_final(c->d_desc, 1, dt_fixed, s); });
     for (int stage = 1; stage <= 2; ++stage) {
-        timed(c, 1, [&] { launch_weno(c->d_desc, c->d_ctiles, c->n_ctiles, stage, mixed, s); });
+        timed(c, 1, [&] { launch_weno(c->d_desc, c->d_ctiles, c->n_ctiles, stage, mixed, c->walls, s); });
         if (col) {
             for (size_t k = 0; k + 1 < c->colour_tiles.size(); ++k) {
                 int t0 = c->colour_tiles[k], t1 = c->colour_tiles[k + 1];
-                timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles + t0, t1 - t0, stage, mixed, tau0, true, s); });
+                timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles + t0, t1 - t0, stage, mixed, tau0, true, c->walls, s); });
             }
         } else {
-            timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles, c->n_ftiles, stage, mixed, tau0, false, s); });
+            timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles, c->n_ftiles, stage, mixed, tau0, false, c->walls, s); });
         }
         timed(c, 3, [&] { launch_update(c->d_desc, c->d_ctiles, c->n_ctiles, stage, col, s); });
     }
@@ -308,7 +309,11 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     D.pinv0 = (const double *)(B + L.pinv0);
     D.cen = (const double *)(B + L.cen);
     D.sshift = (const uint32_t *)(B + L.sshift);
-    for (int a = 0; a < 3; ++a) D.per[a] = (period && period[a] > 0.0) ? period[a] : 0.0;
+    for (int a = 0; a < 3; ++a) {
+        D.per[a] = (period && period[a] > 0.0) ? period[a] : 0.0;
+        D.mir[a][0] = hm.mir[a][0];
+        D.mir[a][1] = hm.mir[a][1];
+    }
     D.cgeo = (const double *)(B + L.cgeo);
     D.cface = (const int32_t *)(B + L.cface);
     D.fcell = (const int32_t *)(B + L.fcell);
@@ -361,6 +366,7 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     c->nf = hm.nf;
     c->perm = std::move(hm.perm);
     c->colour_offsets = hm.colour_offsets;
+    c->walls = hm.n_wall_faces > 0;
     c->has_mesh = true;
     c->has_state = false;
     return HGKS_OK;
@@ -545,7 +551,7 @@ struct hgks_pool {
     ProbDesc *d_probs = nullptr;
     int nprobs = 0;
     Tile *d_ct = nullptr, *d_ft = nullptr;
-    struct Group { bool mixed, tau0; int c0, c1, f0, f1; };
+    struct Group { bool mixed, tau0; int c0, c1, f0, f1; bool walls; };
     std::vector<Group> groups;
     int n_ct = 0;
 };
@@ -579,7 +585,8 @@ hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
         hgks_ctx *c = P->slot[order[k]];
         bool mixed = c->prm.precision == HGKS_FP32_MIXED, tau0 = c->prm.tau_mode == 0;
         if (P->groups.empty() || P->groups.back().mixed != mixed || P->groups.back().tau0 != tau0)
-            P->groups.push_back({mixed, tau0, (int)ct.size(), (int)ct.size(), (int)ft.size(), (int)ft.size()});
+            P->groups.push_back({mixed, tau0, (int)ct.size(), (int)ct.size(), (int)ft.size(), (int)ft.size(), false});
+        P->groups.back().walls = P->groups.back().walls || c->walls;
         const int pid = (int)probs.size();
         probs.push_back(c->desc);
         for (Tile t : c->h_ctiles) { t.prob = pid; ct.push_back(t); }
@@ -676,8 +683,8 @@ hgks_status hgks_pool_step(hgks_pool *p, const int *slots, int n, int32_t nsteps
     for (int32_t it = 0; it < nsteps; ++it) {
         launch_dt_final(p->d_probs, p->nprobs, 0.0, s);
         for (int stage = 1; stage <= 2; ++stage) {
-            for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.mixed, s);
-            for (auto &g : p->groups) launch_flux(p->d_probs, p->nprobs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.mixed, g.tau0, false, s);
+            for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.mixed, g.walls, s);
+            for (auto &g : p->groups) launch_flux(p->d_probs, p->nprobs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.mixed, g.tau0, false, g.walls, s);
             launch_update(p->d_probs, p->d_ct, p->n_ct, stage, false, s);
         }
     }

@@ -12,13 +12,17 @@
 //                                element (r, s) in pair r*8 + s/2, lane s%2
 //   cen    double [3][nc]        cell centroids (the sub-stencil fits are formed on
 //                                the device from them)
-//   sshift uint32 [4][nc]        periodic image of each stencil slot: byte s%4 of word
-//                                s/4 holds (sx+2) + 5 (sy+2) + 25 (sz+2), the member
-//                                sits at its centroid + (sx, sy, sz) * period
+//   sshift uint32 [4][nc]        placement of each stencil slot: byte s%4 of word s/4
+//                                holds (sx+2) + 5 (sy+2) + 25 (sz+2); on a periodic axis
+//                                the member sits at its centroid + s * period, on a
+//                                non-periodic axis s = -1 / +1 is its mirror image in the
+//                                low / high wall (2 wall - x) and s = 0 the cell itself
 //   cgeo   double [9][nc]        1/h, scaled second moments (xx,yy,zz,xy,xz,yz),
 //                                1/|Omega|, h_dt = 6|Omega|/sum S
 //   cface  int32  [4][nc]        (face << 1) | (cell is the face's right cell)
-//   fcell  int32  [2][nf]        left, right cell of each face (normal points left->right)
+//   fcell  int32  [2][nf]        left, right cell of each face (normal points left->right);
+//                                right = -1 at a wall face (the ghost: the left cell's
+//                                mirror image, evaluated from the left cell's record)
 //   fgeo   double [22][nf]       n(3), S, Gauss-point offsets from the left centroid
 //                                [3][3], offsets from the right centroid [3][3]
 //   C      double [25][nc][2]    reconstruction: per variable (c0, g(3), H(6)) of
@@ -91,6 +95,9 @@ struct HostMesh {
     // diagnostics
     int max_members = 0, min_members = 0, dup_slots = 0;
     double pinv_residual = 0.0, closure = 0.0;
+    // walls of the non-periodic axes: twice the lowest / highest node coordinate
+    double mir[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    int64_t n_wall_faces = 0;
 };
 
 // Builds the device-ready arrays on the host.  Returns HGKS_OK or an error with `err` set.

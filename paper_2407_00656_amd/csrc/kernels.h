@@ -31,7 +31,9 @@ struct ProbDesc {
     double *dt;         // [0] dt of the current step
     double *time;       // [0] simulated time
     int32_t *flag;      // [0] non-physical state seen, [1] the tau = 0 flux fix-up pass has work
-    double per[3];                // period per axis (0: not periodic)
+    double per[3];                // period per axis (0: not periodic, walls at both ends)
+    double mir[3][2];             // twice the low / high wall coordinate of a non-periodic axis
+                                  // (a member mirrored in a wall sits at mir - x)
     double gamma, K, weno_eps, gamma_lin, cfl, tau_eps, tau_C;
     int32_t tau_mode, mixed;
 };
@@ -46,9 +48,10 @@ struct Tile {
 constexpr int WENO_TILE = 64;    // cells per WENO workgroup (5 waves: one per variable)
 constexpr int UPD_TILE = 64;     // cells per update / dt workgroup
 
-void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s);
+void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool walls,
+                 hipStream_t s);
 void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0,
-                 bool coloured, hipStream_t s);
+                 bool coloured, bool walls, hipStream_t s);
 void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, hipStream_t s);
 void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, hipStream_t s);
 void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s);

@@ -212,6 +212,7 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
 // the cell itself), and the pseudo-inverse is (A^T A)^-1 A^T over the distinct
 // members; a member met twice gets a zero column.  The 3x3 normal matrix is
 // inverted through its adjugate.  out[k][t]: row k (d/dxi_k), member t.
+template <bool WALLS>
 __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, uint32_t m, double out[3][6]) {
     const size_t nc = (size_t)P.nc;
     // first-layer slots of sub-stencil m, four bits each: SUBFIRST[m][t]
@@ -236,7 +237,16 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
         id[t] = P.sten[sl * nc + i];
         const int sh[3] = {(int)(code[t] % 5u) - 2, (int)((code[t] / 5u) % 5u) - 2, (int)(code[t] / 25u) - 2};
 #pragma unroll
-        for (int a = 0; a < 3; ++a) A[t][a] = (P.cen[a * nc + (size_t)id[t]] + (double)sh[a] * P.per[a] - ci[a]) * ih;
+        for (int a = 0; a < 3; ++a) {
+            // periodic image, or on a non-periodic axis the cell (s = 0) or its mirror in a wall
+            const double c = P.cen[a * nc + (size_t)id[t]];
+            double x = c + (double)sh[a] * P.per[a];
+            if constexpr (WALLS) {      // meshes without walls keep the plain periodic form
+                const double mlo = P.mir[a][0], mhi = P.mir[a][1];
+                if (!(P.per[a] > 0.0)) x = sh[a] == 0 ? c : (sh[a] > 0 ? mhi : mlo) - c;
+            }
+            A[t][a] = (x - ci[a]) * ih;
+        }
     }
     bool dup[6];
 #pragma unroll
@@ -277,7 +287,7 @@ constexpr int WPAIRS0 = 72, WPAIRS = 108;
 template <int WC>
 constexpr int weno_threads() { return (5 * WC + 63) / 64 * 64; }
 
-template <bool MIXED, int WC>
+template <bool MIXED, int WC, bool WALLS>
 __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__restrict__ probs,
                                                               const Tile *__restrict__ tiles, int stage) {
     constexpr int NT = weno_threads<WC>();
@@ -320,7 +330,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     if (threadIdx.x < 4u * WC) {
         const uint32_t m = threadIdx.x / WC, cs = threadIdx.x % WC;
         double ps[3][6];
-        sub_stencil_pinv(P, min(c0 + cs, last), m, ps);
+        sub_stencil_pinv<WALLS>(P, min(c0 + cs, last), m, ps);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -842,6 +852,20 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     }
 }
 
+// At a wall face the ghost side is the wall cell's reconstruction mirrored in the
+// wall: at the (in-wall) Gauss point the same value and the gradient reflected,
+// g - 2 (g.n) n.  Where only the sum of both sides' gradients is kept (2 g after
+// adding the wall cell's gradient twice), the reflection removes its normal part.
+template <class T>
+__device__ __forceinline__ void reflect_grad(T g[5][3], const T n[3], T times) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const T gn = times * (g[v][0] * n[0] + g[v][1] * n[1] + g[v][2] * n[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[v][a] -= gn * n[a];
+    }
+}
+
 // Positivity fallback (not in the paper, which has no limiter): at a Gauss point
 // where the reconstructed state of either side has rho <= 0 or p <= 0, the point
 // is first order: both gradients are zero and each non-physical side takes its
@@ -914,9 +938,11 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32
 // Values at the three Gauss points y[p] and gradients of the five variables of one
 // cell's reconstruction, evaluated while its coefficients stream in, so that each
 // coefficient is loaded once per face.  ADD accumulates the gradients.
-template <class T, bool ADD>
+// REFL: the gradient is reflected before it is added, g - refl (g.n) n (refl = 2 at a
+// wall face, 0 elsewhere; the ghost side of a wall face)
+template <class T, bool ADD, bool REFL = false>
 __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t c, const T y[3][3], T q[3][5],
-                                          T g[3][5][3]) {
+                                          T g[3][5][3], const T *nrm = nullptr, T refl = T(0)) {
     const uint32_t nc = (uint32_t)P.nc;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -949,9 +975,15 @@ __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t
                 q[p][v] = val;
             else  // FP32 form: FP64 cell mean plus FP32 deviation, rounded once
                 q[p][v] = (float)(mean + (double)val);
-            const T gx = cf[1] + T(2) * cf[4] * yp[0] + cf[7] * yp[1] + cf[8] * yp[2];
-            const T gy = cf[2] + T(2) * cf[5] * yp[1] + cf[7] * yp[0] + cf[9] * yp[2];
-            const T gz = cf[3] + T(2) * cf[6] * yp[2] + cf[8] * yp[0] + cf[9] * yp[1];
+            T gx = cf[1] + T(2) * cf[4] * yp[0] + cf[7] * yp[1] + cf[8] * yp[2];
+            T gy = cf[2] + T(2) * cf[5] * yp[1] + cf[7] * yp[0] + cf[9] * yp[2];
+            T gz = cf[3] + T(2) * cf[6] * yp[2] + cf[8] * yp[0] + cf[9] * yp[1];
+            if constexpr (REFL) {
+                const T gn = refl * (gx * nrm[0] + gy * nrm[1] + gz * nrm[2]);
+                gx -= gn * nrm[0];
+                gy -= gn * nrm[1];
+                gz -= gn * nrm[2];
+            }
             if constexpr (ADD) {
                 g[p][v][0] += gx; g[p][v][1] += gy; g[p][v][2] += gz;
             } else {
@@ -965,7 +997,7 @@ __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t
 // time from reloaded inputs (only faces that need it come here).
 template <class T>
 __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage, uint32_t f, uint32_t l,
-                                                             uint32_t r, double out[10]) {
+                                                             uint32_t r, bool wall, double out[10]) {
     const uint32_t nf = (uint32_t)P.nf;
     const double *fg = P.fgeo;
     const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
@@ -982,6 +1014,7 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
         T qL[5], qR[5], gs[5][3];
         recon_point<T, false>(P, stage, l, yl, qL, gs);
         recon_point<T, true>(P, stage, r, yr, qR, gs);
+        if (wall) reflect_grad(gs, n, T(1));
         const bool okL = physical_point(qL), okR = physical_point(qR);
         if (!(okL && okR)) {
             if (!okL) cell_mean(P, stage, l, qL);
@@ -1012,7 +1045,7 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
 // not the arithmetic, bound this kernel: loading every record byte once per face
 // rather than once per Gauss point is what counts), then evaluates the three
 // Gauss-point fluxes and writes S * sum_G w_G (F, dF).  No LDS and no barriers.
-template <bool MIXED, bool COLOURED>
+template <bool MIXED, bool COLOURED, bool WALLS>
 __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restrict__ probs,
                                                        const Tile *__restrict__ tiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -1024,7 +1057,9 @@ __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restric
     if (f >= (uint32_t)tl.end) return;
     const uint32_t nf = (uint32_t)P.nf;
     const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
-    const uint32_t r = (uint32_t)ldg<int32_t>(P.fcell + nf, f * 4u);
+    const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
+    const bool wall = WALLS && rr < 0;           // the ghost side is l's record mirrored
+    const uint32_t r = rr < 0 ? l : (uint32_t)rr;
     const double *fg = P.fgeo;
     const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
                     (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
@@ -1039,7 +1074,9 @@ __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restric
         }
     T qL[3][5], qR[3][5], gs[3][5][3];
     recon_gp3<T, false>(P, stage, l, yl, qL, gs);
-    recon_gp3<T, true>(P, stage, r, yr, qR, gs);
+    // at a wall face the ghost side adds l's gradient reflected in the wall (branch-free:
+    // a branch on the wall flag here costs the kernel half its occupancy)
+    recon_gp3<T, true, WALLS>(P, stage, r, yr, qR, gs, n, wall ? T(2) : T(0));
     const double w = S * (1.0 / 3.0);          // three Gauss points of equal weight
     double out[10];
 #pragma unroll
@@ -1053,14 +1090,14 @@ __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restric
         }
     }
     if constexpr (COLOURED) {      // this mode accumulates at once: take the fallback inline
-        if (!(out[0] == out[0])) flux_face_fallback<T>(P, stage, f, l, r, out);
+        if (!(out[0] == out[0])) flux_face_fallback<T>(P, stage, f, l, r, wall, out);
     }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         if constexpr (COLOURED) {
             double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
             stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - out[k]);
-            stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + out[k]);
+            if (!wall) stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + out[k]);
         } else {
             stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
         }
@@ -1099,15 +1136,15 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) 
         const double f0 = ldg<double>(P.FF, f * 8u);
         if (f0 - f0 == 0.0) continue;            // finite
         const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
-        const uint32_t r = (uint32_t)ldg<int32_t>(P.fcell + nf, f * 4u);
+        const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
         double out[10];
-        flux_face_fallback<T>(P, stage, f, l, r, out);
+        flux_face_fallback<T>(P, stage, f, l, rr < 0 ? l : (uint32_t)rr, rr < 0, out);
 #pragma unroll
         for (int k = 0; k < 10; ++k) stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
     }
 }
 
-template <bool MIXED, bool TAU0, bool COLOURED>
+template <bool MIXED, bool TAU0, bool COLOURED, bool WALLS>
 __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restrict__ probs,
                                                          const Tile *__restrict__ tiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
@@ -1123,9 +1160,12 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
 #pragma unroll
     for (int k = 0; k < 10; ++k) out[k] = 0.0;
     uint32_t l = 0, r = 0;
+    bool wall = false;
     if (ok) {
         l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
-        r = (uint32_t)ldg<int32_t>(P.fcell + nf, f * 4u);
+        const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
+        wall = WALLS && rr < 0;                  // the ghost side is l's record mirrored
+        r = rr < 0 ? l : (uint32_t)rr;
         const double *fg = P.fgeo;
         const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
                         (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
@@ -1141,6 +1181,7 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
             T qL[5], qR[5], gs[5][3], F[5], dF[5];
             recon_point<T, false>(P, stage, l, yl, qL, gs);
             recon_point<T, true>(P, stage, r, yr, qR, gs);
+            if constexpr (WALLS) reflect_grad(gs, n, wall ? T(1) : T(0));
             gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
@@ -1162,6 +1203,7 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
             double qL[5], gL[5][3], qR[5], gR[5][3];
             recon_point<double, false, MIXED>(P, stage, l, yld, qL, gL);
             recon_point<double, false, MIXED>(P, stage, r, yrd, qR, gR);
+            if constexpr (WALLS) reflect_grad(gR, nd, wall ? 2.0 : 0.0);
             const bool okL = physical_point(qL), okR = physical_point(qR);
             if (!(okL && okR)) {
                 if (!okL) cell_mean(P, stage, l, qL);
@@ -1191,7 +1233,7 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
             if constexpr (COLOURED) {
                 double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
                 stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - s);
-                stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + s);
+                if (!wall) stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + s);
             } else {
                 stg<double>(P.FF + (size_t)k * nf, f * 8u, s);
             }
@@ -1338,13 +1380,14 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 // ----------------------------------------------------------------------------
 constexpr int WENO_CELLS = HGKS_WENO_CELLS;     // cells per WENO workgroup (16, 32 or 64)
 
-void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
+void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool walls,
+                 hipStream_t s) {
     if (ntiles <= 0) return;
     dim3 g(ntiles * (WENO_TILE / WENO_CELLS)), b(weno_threads<WENO_CELLS>());
-    if (mixed)
-        hipLaunchKernelGGL((k_weno<true, WENO_CELLS>), g, b, 0, s, probs, tiles, stage);
-    else
-        hipLaunchKernelGGL((k_weno<false, WENO_CELLS>), g, b, 0, s, probs, tiles, stage);
+#define HGKS_WENO(M, WA) hipLaunchKernelGGL((k_weno<M, WENO_CELLS, WA>), g, b, 0, s, probs, tiles, stage)
+    if (mixed) { if (walls) HGKS_WENO(true, true); else HGKS_WENO(true, false); }
+    else { if (walls) HGKS_WENO(false, true); else HGKS_WENO(false, false); }
+#undef HGKS_WENO
 }
 
 // Compute units of the current device (queried once per device).
@@ -1361,11 +1404,15 @@ static int device_cus() {
 }
 
 void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0,
-                 bool coloured, hipStream_t s) {
+                 bool coloured, bool walls, hipStream_t s) {
     if (ntiles <= 0) return;
     if (tau0) {
         dim3 g(ntiles), b(FACE_TILE);
-#define HGKS_FLUX0(M, CO) hipLaunchKernelGGL((k_flux_t0<M, CO>), g, b, 0, s, probs, tiles, stage)
+#define HGKS_FLUX0(M, CO)                                                                                   \
+    do {                                                                                                    \
+        if (walls) hipLaunchKernelGGL((k_flux_t0<M, CO, true>), g, b, 0, s, probs, tiles, stage);           \
+        else hipLaunchKernelGGL((k_flux_t0<M, CO, false>), g, b, 0, s, probs, tiles, stage);                \
+    } while (0)
         if (coloured) { if (mixed) HGKS_FLUX0(true, true); else HGKS_FLUX0(false, true); }
         else { if (mixed) HGKS_FLUX0(true, false); else HGKS_FLUX0(false, false); }
 #undef HGKS_FLUX0
@@ -1377,7 +1424,11 @@ void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntile
         return;
     }
     dim3 g(ntiles), b(3 * FACE_TILE);
-#define HGKS_FLUX(M, CO) hipLaunchKernelGGL((k_flux<M, false, CO>), g, b, 0, s, probs, tiles, stage)
+#define HGKS_FLUX(M, CO)                                                                                    \
+    do {                                                                                                    \
+        if (walls) hipLaunchKernelGGL((k_flux<M, false, CO, true>), g, b, 0, s, probs, tiles, stage);       \
+        else hipLaunchKernelGGL((k_flux<M, false, CO, false>), g, b, 0, s, probs, tiles, stage);            \
+    } while (0)
     if (coloured) { if (mixed) HGKS_FLUX(true, true); else HGKS_FLUX(false, true); }
     else { if (mixed) HGKS_FLUX(true, false); else HGKS_FLUX(false, false); }
 #undef HGKS_FLUX

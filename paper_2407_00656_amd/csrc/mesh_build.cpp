@@ -63,7 +63,10 @@ inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 
-struct Member {            // a stencil member: cell id and integer periodic image shift
+// A stencil member: cell id and, per axis, its placement: on a periodic axis the
+// image shift k (x + k * period), on a non-periodic axis 0 (the cell itself), -1 or
+// +1 (its mirror image in the low or high wall: 2 lo - x or 2 hi - x).
+struct Member {
     int32_t cell;
     int8_t s[3];
     bool operator==(const Member &o) const {
@@ -160,6 +163,14 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             return HGKS_E_INVALID_ARG;
         }
 
+    // extent of the nodes per axis: the walls of the non-periodic axes
+    double wlo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, whi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int64_t k = 0; k < nn; ++k)
+        for (int a = 0; a < 3; ++a) {
+            wlo[a] = std::min(wlo[a], xyz[3 * k + a]);
+            whi[a] = std::max(whi[a], xyz[3 * k + a]);
+        }
+
     // ---- 1. unwrapped vertices, volume, centroid, central second moments --------
     std::vector<std::array<V3, 4>> vert(nc);
     std::vector<V3> cen(nc);
@@ -238,18 +249,33 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             for (size_t s = 0; s < buf.size();) {
                 size_t t = s + 1;
                 while (t < buf.size() && buf[t].first == buf[s].first) ++t;
-                if (t - s != 2) {
-                    bad = t - s == 1 ? 1 : 2;
-                } else {
+                if (t - s == 2) {
                     partner[buf[s].second] = buf[s + 1].second;
                     partner[buf[s + 1].second] = buf[s].second;
+                } else if (t - s == 1) {
+                    // a wall face: all three nodes on the lowest or highest coordinate of a
+                    // non-periodic axis; partner = -2 - (2 axis + side)
+                    int64_t cp = buf[s].second, k[3];
+                    face_nodes(cp / 4, (int)(cp % 4), k);
+                    int code = -1;
+                    for (int a = 0; a < 3 && code < 0; ++a) {
+                        if (per[a] > 0) continue;
+                        const double x0 = xyz[3 * k[0] + a], x1 = xyz[3 * k[1] + a], x2 = xyz[3 * k[2] + a];
+                        if (x0 == x1 && x1 == x2 && (x0 == wlo[a] || x0 == whi[a])) code = 2 * a + (x0 == whi[a] ? 1 : 0);
+                    }
+                    if (code < 0) bad = 1;
+                    partner[cp] = -2 - code;
+                } else {
+                    bad = 2;
                 }
                 s = t;
             }
         }
     });
     if (bad) {
-        err = bad == 1 ? "boundary face (every face must be shared by two cells)" : "non-conforming face";
+        err = bad == 1 ? "boundary face off the walls (an unshared face must lie on the lowest or highest "
+                         "coordinate of a non-periodic axis)"
+                       : "non-conforming face";
         return HGKS_E_BAD_MESH;
     }
 
@@ -264,6 +290,15 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             double as = 0.0;
             for (int p = 0; p < 4; ++p) {
                 int64_t o = partner[c * 4 + p];
+                if (o < 0) {                    // wall face: the neighbour is the cell's mirror image
+                    const int code = (int)(-2 - o), a = code / 2;
+                    nb[c][p] = (int32_t)c;
+                    for (int d = 0; d < 3; ++d) nsh[c][p][d] = 0;
+                    nsh[c][p][a] = (int8_t)(code % 2 ? 1 : -1);
+                    V3 t0 = vert[c][(p + 1) % 4], t1 = vert[c][(p + 2) % 4], t2 = vert[c][(p + 3) % 4];
+                    as += 0.5 * std::sqrt(dot(cross(t1 - t0, t2 - t0), cross(t1 - t0, t2 - t0)));
+                    continue;
+                }
                 int64_t c2 = o / 4;
                 nb[c][p] = (int32_t)c2;
                 int q0 = p == 0 ? 1 : 0;
@@ -319,7 +354,19 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
     for (int64_t c = 0; c < nc; ++c) inv[perm[c]] = (int32_t)c;
 
     // ---- 5. stencils and pseudo-inverses, written in internal numbering --------
-    const int64_t nf = 2 * nc;
+    // centroid of a member in the frame of the cell whose stencil holds it
+    auto place = [&](const Member &x) {
+        V3 c = cen[x.cell];
+        double v[3] = {c.x, c.y, c.z};
+        for (int a = 0; a < 3; ++a) {
+            if (per[a] > 0)
+                v[a] += x.s[a] * per[a];
+            else if (x.s[a] != 0)
+                v[a] = 2.0 * (x.s[a] < 0 ? wlo[a] : whi[a]) - v[a];
+        }
+        return V3{v[0], v[1], v[2]};
+    };
+    auto mirror_sign = [&](const Member &x, int a) { return per[a] <= 0 && x.s[a] != 0 ? -1.0 : 1.0; };
     // every entry of these arrays is written below (no fill on resize)
     out.sten.resize((size_t)SLOTS * nc);
     out.pinv0.resize((size_t)144 * nc);
@@ -338,8 +385,16 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                 int32_t j = nb[i][m];
                 int t = 0;
                 for (int q = 0; q < 4; ++q) {
-                    Member x{nb[j][q], {(int8_t)(nsh[i][m][0] + nsh[j][q][0]), (int8_t)(nsh[i][m][1] + nsh[j][q][1]),
-                                        (int8_t)(nsh[i][m][2] + nsh[j][q][2])}};
+                    Member x{nb[j][q], {0, 0, 0}};
+                    for (int a = 0; a < 3; ++a) {
+                        const int s1 = nsh[i][m][a], s2 = nsh[j][q][a];
+                        if (per[a] > 0) {
+                            x.s[a] = (int8_t)(s1 + s2);
+                        } else {        // mirror images compose: the same wall twice is the identity
+                            if (s1 != 0 && s2 != 0 && s1 != s2) bad = 6;   // both walls: a translation
+                            x.s[a] = (int8_t)(s2 == 0 ? s1 : (s1 == 0 ? s2 : 0));
+                        }
+                    }
                     if (x.cell == i && x.s[0] == 0 && x.s[1] == 0 && x.s[2] == 0) continue;
                     if (t < 3) S[4 + 3 * m + t] = x;
                     ++t;
@@ -349,13 +404,15 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             // least-squares rows in the scaled coordinates xi = (x - c_i)/h_i
             const double h = std::cbrt(vol[i]);
             auto row = [&](const Member &x, double r[9]) {
-                V3 sh = {x.s[0] * per[0], x.s[1] * per[1], x.s[2] * per[2]};
-                V3 d = cen[x.cell] + sh - cen[i];
+                V3 d = place(x) - cen[i];
                 r[0] = d.x / h;
                 r[1] = d.y / h;
                 r[2] = d.z / h;
-                for (int q = 0; q < 6; ++q)
-                    r[3 + q] = (smom[x.cell][q] + comp(d, QA[q]) * comp(d, QB[q]) - smom[i][q]) / (h * h);
+                for (int q = 0; q < 6; ++q) {
+                    // a mirror flips the sign of the mixed moments that involve its axis
+                    const double sg = mirror_sign(x, QA[q]) * mirror_sign(x, QB[q]);
+                    r[3 + q] = (sg * smom[x.cell][q] + comp(d, QA[q]) * comp(d, QB[q]) - smom[i][q]) / (h * h);
+                }
             };
             // distinct members of the big stencil (self excluded by construction)
             int first[SLOTS], nm = 0;
@@ -436,21 +493,34 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         err = "a neighbour does not have three other neighbours";
         return HGKS_E_BAD_MESH;
     }
+    if (bad == 6) {
+        err = "a stencil reaches both walls of a non-periodic axis (too few cells across it)";
+        return HGKS_E_BAD_MESH;
+    }
     if (bad == 4) {
         err = "rank-deficient least-squares stencil";
         return HGKS_E_BAD_MESH;
     }
 
     // ---- 6. faces in internal numbering: left = smaller internal id -------------
-    // counting sort by left cell, then by right cell
+    // counting sort by left cell, then by right cell; a wall face has the wall cell
+    // on the left and right = -1 (the ghost), and sorts first among its cell's faces
+    auto is_wall = [&](int64_t c, int p) { return partner[c * 4 + p] < 0; };
     std::vector<int64_t> fstart(nc + 1, 0);
+    int64_t nwall = 0;
     for (int64_t c = 0; c < nc; ++c)
         for (int p = 0; p < 4; ++p) {
             int64_t c2 = nb[c][p];
-            if (inv[c] < inv[c2]) fstart[inv[c] + 1]++;
+            if (is_wall(c, p)) {
+                fstart[inv[c] + 1]++;
+                ++nwall;
+            } else if (inv[c] < inv[c2]) {
+                fstart[inv[c] + 1]++;
+            }
         }
     for (int64_t c = 0; c < nc; ++c) fstart[c + 1] += fstart[c];
-    if (fstart[nc] != nf) {
+    const int64_t nf = fstart[nc];
+    if (2 * nf != 4 * nc + nwall) {
         err = "face count mismatch";
         return HGKS_E_BAD_MESH;
     }
@@ -465,7 +535,10 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         for (int64_t c = 0; c < nc; ++c)
             for (int p = 0; p < 4; ++p) {
                 int64_t c2 = nb[c][p];
-                if (inv[c] < inv[c2]) faces[fill[inv[c]]++] = {inv[c], inv[c2], (int32_t)c, (int8_t)p};
+                if (is_wall(c, p))
+                    faces[fill[inv[c]]++] = {inv[c], -1, (int32_t)c, (int8_t)p};
+                else if (inv[c] < inv[c2])
+                    faces[fill[inv[c]]++] = {inv[c], inv[c2], (int32_t)c, (int8_t)p};
             }
         parallel_for(nc, [&](int64_t b, int64_t e) {
             for (int64_t c = b; c < e; ++c)
@@ -479,12 +552,13 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
     {
         std::vector<uint32_t> used(nc, 0);
         for (int64_t f = 0; f < nf; ++f) {
-            uint32_t m = used[faces[f].l] | used[faces[f].r];
+            const int32_t l = faces[f].l, r = faces[f].r;
+            uint32_t m = used[l] | (r >= 0 ? used[r] : 0u);
             int k = 0;
             while (m & (1u << k)) ++k;
             colour[f] = (int8_t)k;
-            used[faces[f].l] |= 1u << k;
-            used[faces[f].r] |= 1u << k;
+            used[l] |= 1u << k;
+            if (r >= 0) used[r] |= 1u << k;
             ncol = std::max(ncol, k + 1);
         }
     }
@@ -525,7 +599,7 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         out.fcell[k] = F.l;
         out.fcell[nf + k] = F.r;
         out.cface[(size_t)cfill[F.l]++ * nc + F.l] = (int32_t)(k << 1);
-        out.cface[(size_t)cfill[F.r]++ * nc + F.r] = (int32_t)((k << 1) | 1);
+        if (F.r >= 0) out.cface[(size_t)cfill[F.r]++ * nc + F.r] = (int32_t)((k << 1) | 1);
     }
     parallel_for(nf, [&](int64_t b, int64_t e) {
         for (int64_t k = b; k < e; ++k) {
@@ -542,9 +616,14 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             nrm = (1.0 / len) * nrm;
             V3 fc = (1.0 / 3.0) * (tri[0] + tri[1] + tri[2]);
             if (dot(nrm, fc - cen[lo]) < 0) nrm = -1.0 * nrm;
-            V3 shift = {nsh[lo][p][0] * per[0], nsh[lo][p][1] * per[1], nsh[lo][p][2] * per[2]};
-            V3 cr = cen[ro] + shift;   // right centroid in the left frame
-            if (!(dot(nrm, cr - fc) > 0.0)) bad = 5;   // both cells on one side: overlapping / folded
+            // right centroid in the left frame; at a wall the ghost side is evaluated from
+            // the wall cell's own record at the same point (its mirror image), so yr = yl
+            V3 cr = cen[lo];
+            if (F.r >= 0) {
+                V3 shift = {nsh[lo][p][0] * per[0], nsh[lo][p][1] * per[1], nsh[lo][p][2] * per[2]};
+                cr = cen[ro] + shift;
+                if (!(dot(nrm, cr - fc) > 0.0)) bad = 5;   // both cells on one side: overlapping / folded
+            }
             double *g = &out.fgeo[0];
             g[0 * (size_t)nf + k] = nrm.x;
             g[1 * (size_t)nf + k] = nrm.y;
@@ -591,6 +670,11 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
     out.min_members = members_min;
     out.dup_slots = dups;
     out.pinv_residual = resid_max;
+    out.n_wall_faces = nwall;
+    for (int a = 0; a < 3; ++a) {
+        out.mir[a][0] = per[a] > 0 ? 0.0 : 2.0 * wlo[a];
+        out.mir[a][1] = per[a] > 0 ? 0.0 : 2.0 * whi[a];
+    }
     out.closure = closure;
     return HGKS_OK;
 }

@@ -1,18 +1,19 @@
 """Sod's shock tube on jittered Kuhn tetrahedra, FP64 and FP32-mixed, on one GPU.
 
-The tube is laid out periodically (workloads.sod_box): on [0, 2) x [0, Ly) x
-[0, Lz) the high state fills [0.5, 1.5), so each half of the period holds one
-tube that equals the tube with transmissive ends until t = 0.286.  The
-configured case is 256 x 128 x 64 cubes (12.6 M cells, h = 1/128 along the
-tube, the same cell count and spacing as 6*128^3 cells on [0, 1]^3), collision
-time tau_mode 1, CFL 0.3, to t = 0.2.
+The configured case is the tube on [0, 1]^3 with 128^3 cubes (12.6 M cells): the
+diaphragm at x = 0.5, transmissive walls at x = 0 and x = 1 (mirror-image
+ghosts), y and z periodic, collision time tau_mode 1, CFL 0.3, to t = 0.2.
+With --doubled the tube is instead laid out periodically (workloads.sod_box
+without walls): on [0, 2) x [0, Ly) x [0, Lz) the high state fills [0.5, 1.5), so
+each half of the period holds one tube, equal to the tube with transmissive ends
+until t = 0.286 (use --nx 256 --ny 128 --nz 64 for the same spacing).
 
 For each precision it reports the step rate (cell-updates/s over the whole run,
 state resident on the GPU), the kernel split, and the volume-weighted L1 error
 of density and pressure against the exact solution; FP32-mixed also reports its
 relative L1 difference from FP64.
 
-    python -m paper_2407_00656_amd.shock_tube [--nx 256 --ny 128 --nz 64] [--t-end 0.2]
+    python -m paper_2407_00656_amd.shock_tube [--nx 128 --ny 128 --nz 128] [--t-end 0.2] [--doubled]
 """
 from __future__ import annotations
 
@@ -68,9 +69,10 @@ def run(mesh, q0, precision, t_end, chunk=20, log=print, profile=True):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--nx", type=int, default=128)
     ap.add_argument("--ny", type=int, default=128)
-    ap.add_argument("--nz", type=int, default=64)
+    ap.add_argument("--nz", type=int, default=128)
+    ap.add_argument("--doubled", action="store_true", help="periodic doubled tube instead of walls")
     ap.add_argument("--t-end", type=float, default=0.2)
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events")
     ap.add_argument("--fp64-only", action="store_true")
@@ -80,11 +82,12 @@ def main(argv=None):
         print(msg, file=sys.stderr, flush=True)
 
     log(f"shock_tube: building {args.nx}x{args.ny}x{args.nz} cubes")
-    mesh, case = W.sod_box(args.nx, args.ny, args.nz)
+    mesh, case = W.sod_box(args.nx, args.ny, args.nz, walls=not args.doubled)
     q0 = case.conservative(mesh)
     vol = W.tet_volumes(mesh.cell_vertices)
     x = mesh.cell_vertices[:, :, 0].mean(axis=1)
-    out = {"workload": f"shock tube, periodic doubled, {args.nx}x{args.ny}x{args.nz} cubes, tau_mode 1, CFL 0.3",
+    layout = "periodic doubled" if args.doubled else "transmissive walls in x, periodic y/z"
+    out = {"workload": f"shock tube, {layout}, {args.nx}x{args.ny}x{args.nz} cubes, tau_mode 1, CFL 0.3",
            "cells": mesh.n_cells, "t_end": args.t_end}
     res = {}
     precs = ((hgks.FP64, "fp64"),) if args.fp64_only else ((hgks.FP64, "fp64"), (hgks.FP32_MIXED, "fp32_mixed"))

@@ -53,3 +53,20 @@ def mirror_double(mesh, axis):
     period[axis] = 2.0 * hi
     return W.TetMesh(nodes=nodes, cell_nodes=cells, period=period,
                      cell_vertices=np.concatenate([mesh.cell_vertices, verts_m]))
+
+
+def smooth_state(mesh, seed, gamma=1.4):
+    """A smooth state with every component nonzero (moving in all directions)."""
+    rng = np.random.default_rng(seed)
+    c = mesh.cell_vertices.mean(axis=1)
+    k = rng.uniform(1.0, 3.0, size=(5, 3))
+    ph = rng.uniform(0.0, 2 * np.pi, size=5)
+    s = np.sin(c @ k.T + ph)
+    rho = 1.0 + 0.2 * s[:, 0]
+    u = np.stack([0.4 + 0.3 * s[:, 1], -0.3 + 0.2 * s[:, 2], 0.2 + 0.25 * s[:, 3]], axis=1)
+    p = 1.0 + 0.15 * s[:, 4]
+    q = np.empty((c.shape[0], 5))
+    q[:, 0] = rho
+    q[:, 1:4] = rho[:, None] * u
+    q[:, 4] = p / (gamma - 1.0) + 0.5 * rho * (u * u).sum(axis=1)
+    return q

@@ -12,7 +12,7 @@ import pytest
 from oracle import oracle as O
 from paper_2407_00656_amd import hgks
 from paper_2407_00656_amd import workloads as W
-from tests.helpers import advection_case, rel_l1, scaled_err
+from tests.helpers import advection_case, rel_l1, scaled_err, smooth_state
 
 pytestmark = pytest.mark.gpu
 
@@ -292,6 +292,50 @@ def test_fp32_mixed_shock_tube_against_fp64():
         while t < 0.1 - 1e-14:
             dt = s.step(1, want_dt=True)
             _, t = s.get_state()
+        out[prec] = s.get_state()[0]
+        s.close()
+    e = rel_l1(out[hgks.FP32_MIXED], out[hgks.FP64], vol)
+    say("fp32-mixed vs fp64 relative L1", e)
+    assert np.all(np.isfinite(out[hgks.FP32_MIXED]))
+    assert e[0] < 1e-4 and e[4] < 1e-4, e
+
+
+# ---------------------------------------------------------------------------
+# Transmissive walls (non-periodic axes): mirror-image ghosts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau_mode", [0, 1])
+def test_fp64_walls_smooth_every_step(tau_mode):
+    """Walls on x and y (edges, where members are images under two mirrors), a
+    smooth state moving in every direction: each step matches the oracle."""
+    say(f"case: fp64 walls on x and y, smooth state, tau_mode={tau_mode}, 4 steps")
+    mesh = W.kuhn_box((6, 5, 4), (1.0, 0.9, 0.8), jitter=0.15, seed=4243, periodic=(False, False, True))
+    per_step_parity(mesh, smooth_state(mesh, 11), 4, tau_mode=tau_mode)
+
+
+def test_fp64_walls_shock_tube_every_step():
+    say("case: fp64 shock tube with walls nx=16 tau_mode=1 6 steps")
+    mesh, case = W.sod_box(16, 4, 4, walls=True)
+    per_step_parity(mesh, case.conservative(mesh), 6, tau_mode=1)
+
+
+def test_fp64_walls_coloured_accumulation():
+    say("case: fp64 walls coloured accumulation 3 steps")
+    mesh = W.kuhn_box((6, 5, 4), (1.0, 0.9, 0.8), jitter=0.15, seed=4244, periodic=(False, True, True))
+    per_step_parity(mesh, smooth_state(mesh, 12), 3, accumulation=hgks.ACC_COLOURED)
+
+
+def test_fp32_mixed_walls_shock_tube_against_fp64():
+    say("case: fp32-mixed vs fp64 shock tube with walls nx=32 to t=0.1")
+    mesh, case = W.sod_box(32, 4, 4, walls=True)
+    q0 = case.conservative(mesh)
+    vol = W.tet_volumes(mesh.cell_vertices)
+    out = {}
+    for prec in (hgks.FP64, hgks.FP32_MIXED):
+        s = make_solver(mesh, q0, precision=prec, tau_mode=1)
+        t = 0.0
+        while t < 0.1 - 1e-14:
+            s.step(1, want_dt=True)
+            t = s.get_time()
         out[prec] = s.get_state()[0]
         s.close()
     e = rel_l1(out[hgks.FP32_MIXED], out[hgks.FP64], vol)

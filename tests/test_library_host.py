@@ -22,12 +22,18 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-def test_stencils_match_oracle_and_pinv_is_a_left_inverse():
-    m = W.kuhn_box(8)
+@pytest.mark.parametrize("periodic", [(True, True, True), (False, True, True), (False, False, True)])
+def test_stencils_match_oracle_and_pinv_is_a_left_inverse(periodic):
+    """Also with walls (non-periodic axes), where stencils hold mirror images."""
+    m = W.kuhn_box(6 if periodic[0] else (5, 6, 4), jitter=0.15, periodic=periodic)
     r = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period)
     st = r["stats"]
-    assert st["n_faces"] == 2 * m.n_cells
-    assert st["max_members"] == 14 and st["min_members"] == 14
+    om = O.Mesh.from_workload(m)
+    lr = om.faces()["lr"]
+    assert st["n_faces"] == lr.shape[0]
+    walls = int(np.sum(lr[:, 1] < 0))
+    assert 2 * st["n_faces"] == 4 * m.n_cells + walls and (walls > 0) == (not all(periodic))
+    assert st["max_members"] == 14 and st["min_members"] >= 13
     assert st["pinv_residual"] < 1e-12
     assert st["closure"] < 1e-14
     perm = r["perm"]
@@ -37,7 +43,7 @@ def test_stencils_match_oracle_and_pinv_is_a_left_inverse():
     sten = r["sten"]
     inv = np.empty_like(perm)
     inv[perm] = np.arange(m.n_cells)
-    for c in range(0, m.n_cells, 5):
+    for c in range(0, m.n_cells, 3):
         o = perm[c]
         mem, _, subs = om.stencil(o)
         slots = perm[sten[:, c]]
@@ -70,9 +76,11 @@ def test_bad_meshes_are_rejected():
     with pytest.raises(hgks.HGKSError) as e:
         hgks.inspect_mesh(m.nodes, cells, m.period)
     assert e.value.status in (hgks.E_BAD_MESH,)
-    box = W.kuhn_box(4, periodic=(False, True, True))    # boundary faces on x = 0 and x = 2
+    box = W.kuhn_box(4, periodic=(False, True, True))    # walls on x = 0 and x = 2 are fine,
+    hgks.inspect_mesh(box.nodes, box.cell_nodes, box.period)
+    hole = np.delete(box.cell_nodes, 200, axis=0)         # but not unshared faces inside the box
     with pytest.raises(hgks.HGKSError) as e:
-        hgks.inspect_mesh(box.nodes, box.cell_nodes, box.period)
+        hgks.inspect_mesh(box.nodes, hole, box.period)
     assert e.value.status == hgks.E_BAD_MESH
     with pytest.raises(hgks.HGKSError) as e:             # wrapped cells without their period
         hgks.inspect_mesh(m.nodes, m.cell_nodes, (0.0, 0.0, 0.0))

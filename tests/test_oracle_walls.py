@@ -20,33 +20,16 @@ import pytest
 from oracle import oracle as O
 from paper_2407_00656_amd import workloads as W
 
-from helpers import mirror_double
+from helpers import mirror_double, smooth_state
 
 GAMMA = 1.4
-
-
-def _smooth_state(mesh, seed):
-    """A smooth state with every component nonzero (moving in all directions)."""
-    rng = np.random.default_rng(seed)
-    c = mesh.cell_vertices.mean(axis=1)
-    k = rng.uniform(1.0, 3.0, size=(5, 3))
-    ph = rng.uniform(0.0, 2 * np.pi, size=5)
-    s = np.sin(c @ k.T + ph)
-    rho = 1.0 + 0.2 * s[:, 0]
-    u = np.stack([0.4 + 0.3 * s[:, 1], -0.3 + 0.2 * s[:, 2], 0.2 + 0.25 * s[:, 3]], axis=1)
-    p = 1.0 + 0.15 * s[:, 4]
-    q = np.empty((c.shape[0], 5))
-    q[:, 0] = rho
-    q[:, 1:4] = rho[:, None] * u
-    q[:, 4] = p / (GAMMA - 1.0) + 0.5 * rho * (u * u).sum(axis=1)
-    return q
 
 
 @pytest.mark.parametrize("tau_mode,axes", [(0, (0,)), (1, (0,)), (0, (0, 1))])
 def test_walls_equal_the_mirror_doubled_box(tau_mode, axes):
     periodic = tuple(a not in axes for a in range(3))
     mesh = W.kuhn_box((5, 4, 4), (1.0, 0.8, 0.8), jitter=0.15, seed=4242, periodic=periodic)
-    q = _smooth_state(mesh, 7)
+    q = smooth_state(mesh, 7)
     doubled, qd = mesh, q
     for a in axes:
         doubled = mirror_double(doubled, a)
