@@ -120,11 +120,12 @@ def serve_bench(count: int, steps: int, budget_gb: float):
     for r in reqs:
         r.arrival = 0.0
     budget = int(budget_gb * 1e9)
-    burst = serve.run(reqs, budget, workers=4)
+    payloads = serve.make_payloads(reqs)          # the clients' meshes and initial states
+    burst = serve.run(reqs, budget, workers=4, payloads=payloads)
     capacity = burst["requests"] / burst["makespan_s"]
     rate = 0.8 * capacity
     reqs = W.serve_requests(count, seed=2407, n_range=(8, 48), steps=steps, rate=rate)
-    res = serve.run(reqs, budget, workers=4)
+    res = serve.run(reqs, budget, workers=4, payloads=payloads)
     errs = serve.exact_errors(res["jobs"])
     cells = [j.mesh.n_cells for j in res["jobs"]]
     return {"requests": res["requests"], "steps_each": steps, "n_range": [8, 48],

