@@ -498,12 +498,13 @@ __device__ __forceinline__ void slope(const T b[5], const State<T> &s, T a[5]) {
 
 // Time-integral weights q0..q5 of Eq. (flux) over [0, d].
 template <class T>
-__device__ __forceinline__ void q_coef(T d, T tau, T q[6]) {
+__device__ __forceinline__ void q_coef(T d, T tau, T E, T q[6]) {
+    // E = exp(-d / tau), passed in: the weights over [0, dt] and [0, dt/2] share one
+    // exponential (exp(-dt/tau) = exp(-dt/(2 tau))^2)
     if (tau == T(0)) {
         q[0] = d; q[1] = T(0); q[2] = T(0.5) * d * d; q[3] = T(0); q[4] = T(0); q[5] = T(0);
         return;
     }
-    const T E = hg_exp(-d / tau);
     q[0] = d - tau * (T(1) - E);
     q[1] = T(2) * tau * tau - tau * d - tau * (d + T(2) * tau) * E;
     q[2] = T(0.5) * d * d - tau * d + tau * tau * (T(1) - E);
@@ -709,7 +710,7 @@ __device__ __forceinline__ void second_moment_jvp(const T n[3], const T U[3], T 
 // dF_j/dQ dQ/dx_j (Euler Jacobians along the frame axes).
 template <class T>
 __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], const T n[3], const T t1[3],
-                                             const T t2[3], T sgn, T K, T gam, T Kp3, T c4k, T e0[5], T e1[5],
+                                             const T t2[3], T h0, T h1, T K, T gam, T Kp3, T c4k, T e0[5], T e1[5],
                                              T e2[5]) {
     const State<T> s = make_state(Qf, gam, Kp3, c4k);
     const T *e[3] = {n, t1, t2};
@@ -730,8 +731,13 @@ __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], con
     }
     T A[5];
     slope(bt, s, A);
+    // half-space moments of u: the first two come from the collision (same side, same
+    // normal velocity), the rest from the recursion
     Mom<T> M;
-    mom_half<T, 7>(s.U, s.lam, s.i2l, sgn, M.u);
+    M.u[0] = h0;
+    M.u[1] = h1;
+#pragma unroll
+    for (int k = 2; k < 7; ++k) M.u[k] = s.U * M.u[k - 1] + T(k - 1) * s.i2l * M.u[k - 2];
     mom_full(s.V, s.i2l, M.v);
     mom_full(s.W, s.i2l, M.w);
     M.xi2 = K * s.i2l;
@@ -767,8 +773,9 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     T tau = T(0);
     if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
     T q1[6], qh[6], cF[6], cD[6];
-    q_coef(dt, tau, q1);
-    q_coef(T(0.5) * dt, tau, qh);
+    const T Eh = tau > T(0) ? hg_exp(T(-0.5) * dt / tau) : T(0);
+    q_coef(dt, tau, Eh * Eh, q1);
+    q_coef(T(0.5) * dt, tau, Eh, qh);
     const T idt = T(1) / dt;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -828,7 +835,7 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     {
         T Qf[5], e0[5], e1[5], e2[5];
         rot_in(ql, n, t1, t2, Qf);
-        initial_part(Qf, gl, n, t1, t2, T(1), K, gam, Kp3, c4k, e0, e1, e2);
+        initial_part(Qf, gl, n, t1, t2, ml[0], ml[1], K, gam, Kp3, c4k, e0, e1, e2);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             Fl[k] = sl.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
@@ -838,7 +845,7 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     {
         T Qf[5], e0[5], e1[5], e2[5];
         rot_in(qr, n, t1, t2, Qf);
-        initial_part(Qf, gr, n, t1, t2, T(-1), K, gam, Kp3, c4k, e0, e1, e2);
+        initial_part(Qf, gr, n, t1, t2, mr[0], mr[1], K, gam, Kp3, c4k, e0, e1, e2);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             Fl[k] += sr.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
