@@ -284,8 +284,9 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
         }
         c->colour_tiles.push_back((int)ft.size());
     } else {
-        for (int64_t b = 0; b < hm.nf; b += FACE_TILE)
-            ft.push_back({0, (int32_t)b, (int)ft.size(), (int32_t)std::min<int64_t>(hm.nf, b + FACE_TILE)});
+        const int fw = tau0_of(c->prm) ? FACE_TILE : 3 * GP_FACES;   // faces per tile of the flux kernel
+        for (int64_t b = 0; b < hm.nf; b += fw)
+            ft.push_back({0, (int32_t)b, (int)ft.size(), (int32_t)std::min<int64_t>(hm.nf, b + fw)});
         xcd_order(ft, 0, ft.size());
     }
     Layout L = layout_for(hm.nc, hm.nf, (int)ct.size(), (int)ft.size(), mixed, col);
@@ -563,7 +564,8 @@ size_t footprint_of(const hgks_params &p, int64_t nc) {
     const int nct = n_cell_tiles(nc);
     // coloured accumulation rounds every colour class up to whole tiles (at most 8 classes)
     const bool col = p.accumulation == HGKS_ACC_COLOURED;
-    const int nft = (int)((nf + FACE_TILE - 1) / FACE_TILE) + (col ? 8 : 0);
+    const int fw = (col || p.tau_mode == 0) ? FACE_TILE : 3 * GP_FACES;
+    const int nft = (int)((nf + fw - 1) / fw) + (col ? 8 : 0);
     Layout L = layout_for(nc, nf, nct, nft, p.precision == HGKS_FP32_MIXED, p.accumulation == HGKS_ACC_COLOURED);
     return L.total;
 }

@@ -45,6 +45,8 @@ struct Tile {
     int32_t end;    // one past the last cell / face of the tile
 };
 
+constexpr int GP_FACES = 21;     // tau > 0 flux without colouring: faces per single-wave workgroup;
+                                 // its face tiles hold 3 * GP_FACES = 63 faces
 constexpr int WENO_TILE = 64;    // cells per WENO workgroup (5 waves: one per variable)
 constexpr int UPD_TILE = 64;     // cells per update / dt workgroup
 

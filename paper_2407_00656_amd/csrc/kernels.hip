@@ -1154,6 +1154,40 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) 
     }
 }
 
+// The tau > 0 flux at Gauss point g of face f (between cells l and r; wall: r = l and
+// the ghost side mirrored).  It runs in FP64 in both forms (the FP32-mixed form reads
+// its FP32 records and evaluates them in FP64): the FP32 evaluation of this flux turns
+// non-finite next to a shock on large meshes.
+template <bool MIXED, bool WALLS>
+__device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
+                                                uint32_t r, bool wall, double Fo[5], double dFo[5]) {
+    const uint32_t nf = (uint32_t)P.nf;
+    const double *fg = P.fgeo;
+    const double nd[3] = {ldg<double>(fg, f * 8u), ldg<double>(fg + nf, f * 8u),
+                          ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+    double yld[3], yrd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        yld[a] = ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
+        yrd[a] = ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
+    }
+    double qL[5], gL[5][3], qR[5], gR[5][3];
+    recon_point<double, false, MIXED>(P, stage, l, yld, qL, gL);
+    recon_point<double, false, MIXED>(P, stage, r, yrd, qR, gR);
+    if constexpr (WALLS) reflect_grad(gR, nd, wall ? 2.0 : 0.0);
+    const bool okL = physical_point(qL), okR = physical_point(qR);
+    if (!(okL && okR)) {
+        if (!okL) cell_mean(P, stage, l, qL);
+        if (!okR) cell_mean(P, stage, r, qR);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            gL[v][0] = gL[v][1] = gL[v][2] = 0.0;
+            gR[v][0] = gR[v][1] = gR[v][2] = 0.0;
+        }
+    }
+    gks_flux_full<double>(qL, gL, qR, gR, nd, P.dt[0], P, Fo, dFo);
+}
+
 template <bool MIXED, bool TAU0, bool COLOURED, bool WALLS>
 __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restrict__ probs,
                                                          const Tile *__restrict__ tiles, int stage) {
@@ -1199,32 +1233,7 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
                 dFo[k] = (double)dF[k];
             }
         } else {
-            // tau > 0 runs in FP64 in both forms (the FP32-mixed form reads its FP32
-            // records and evaluates them in FP64): the FP32 evaluation of this flux
-            // turns non-finite next to a shock on large meshes
-            const double nd[3] = {ldg<double>(fg, f * 8u), ldg<double>(fg + nf, f * 8u),
-                                  ldg<double>(fg + (size_t)2 * nf, f * 8u)};
-            double yld[3], yrd[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                yld[a] = ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
-                yrd[a] = ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
-            }
-            double qL[5], gL[5][3], qR[5], gR[5][3];
-            recon_point<double, false, MIXED>(P, stage, l, yld, qL, gL);
-            recon_point<double, false, MIXED>(P, stage, r, yrd, qR, gR);
-            if constexpr (WALLS) reflect_grad(gR, nd, wall ? 2.0 : 0.0);
-            const bool okL = physical_point(qL), okR = physical_point(qR);
-            if (!(okL && okR)) {
-                if (!okL) cell_mean(P, stage, l, qL);
-                if (!okR) cell_mean(P, stage, r, qR);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    gL[v][0] = gL[v][1] = gL[v][2] = 0.0;
-                    gR[v][0] = gR[v][1] = gR[v][2] = 0.0;
-                }
-            }
-            gks_flux_full<double>(qL, gL, qR, gR, nd, P.dt[0], P, Fo, dFo);
+            point_flux_full<MIXED, WALLS>(P, stage, f, (uint32_t)g, l, r, wall, Fo, dFo);
         }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
 #pragma unroll
@@ -1248,6 +1257,59 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
                 stg<double>(P.FF + (size_t)k * nf, f * 8u, s);
             }
         }
+    }
+}
+
+// tau > 0 with the per-face buffer: single-wave workgroups, lane 3j + g evaluating
+// Gauss point g of face j of the workgroup's 21 faces (tiles of 63 faces, three
+// workgroups each).  The three points of a face are summed across neighbouring lanes
+// in the order (g0 + g1) + g2, as the three-wave kernel sums them.  At two waves per
+// SIMD a three-wave workgroup leaves a quarter of a CU's wave slots idle; single-wave
+// workgroups fill them all.
+template <bool MIXED, bool WALLS>
+__global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ probs, const Tile *__restrict__ tiles,
+                                                int stage) {
+    constexpr uint32_t SPLIT = 3;                        // workgroups per tile
+    // XCD x takes a contiguous run of (tile, part) units (the tile table is laid out
+    // for one workgroup per tile: invert that layout, as the WENO kernel does)
+    const uint32_t nb = gridDim.x, xcd = blockIdx.x & 7u;
+    const uint32_t bx = xcd * (nb >> 3) + min(xcd, nb & 7u) + (blockIdx.x >> 3);
+    const uint32_t jt = bx / SPLIT, nt = nb / SPLIT;
+    uint32_t kt = jt;
+    if (nt >= 16u) {
+        const uint32_t q8 = nt >> 3, r8 = nt & 7u, big = r8 * (q8 + 1u);
+        const uint32_t xx = jt < big ? jt / (q8 + 1u) : r8 + (jt - big) / q8;
+        const uint32_t qq = jt < big ? jt % (q8 + 1u) : (jt - big) % q8;
+        kt = 8u * qq + xx;
+    }
+    const Tile tl = tiles[kt];
+    const ProbDesc &P = probs[tl.prob];
+    const uint32_t j = threadIdx.x / 3u, g = threadIdx.x % 3u;
+    const uint32_t f = tl.begin + (bx % SPLIT) * (uint32_t)GP_FACES + j;
+    const bool ok = threadIdx.x < 3u * GP_FACES && f < (uint32_t)tl.end;
+    const uint32_t nf = (uint32_t)P.nf;
+    double out[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[k] = 0.0;
+    if (ok) {
+        const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
+        const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
+        const bool wall = WALLS && rr < 0;               // the ghost side is l's record mirrored
+        const uint32_t r = rr < 0 ? l : (uint32_t)rr;
+        double Fo[5], dFo[5];
+        point_flux_full<MIXED, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
+        const double w = ldg<double>(P.fgeo + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            out[k] = w * Fo[k];
+            out[5 + k] = w * dFo[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        const double o1 = __shfl_down(out[k], 1u), o2 = __shfl_down(out[k], 2u);
+        const double sum = (out[k] + o1) + o2;
+        if (ok && g == 0u) stg<double>(P.FF + (size_t)k * nf, f * 8u, sum);
     }
 }
 
@@ -1431,6 +1493,14 @@ void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntile
             if (mixed) hipLaunchKernelGGL((k_flux_fix<true>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
             else hipLaunchKernelGGL((k_flux_fix<false>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
         }
+        return;
+    }
+    if (!coloured) {          // tiles of 3 * GP_FACES faces, three single-wave workgroups each
+        dim3 g(ntiles * 3), b(64);
+        if (mixed) { if (walls) hipLaunchKernelGGL((k_flux_gp<true, true>), g, b, 0, s, probs, tiles, stage);
+                     else hipLaunchKernelGGL((k_flux_gp<true, false>), g, b, 0, s, probs, tiles, stage); }
+        else { if (walls) hipLaunchKernelGGL((k_flux_gp<false, true>), g, b, 0, s, probs, tiles, stage);
+               else hipLaunchKernelGGL((k_flux_gp<false, false>), g, b, 0, s, probs, tiles, stage); }
         return;
     }
     dim3 g(ntiles), b(3 * FACE_TILE);
