@@ -1155,9 +1155,8 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) 
 }
 
 // The tau > 0 flux at Gauss point g of face f (between cells l and r; wall: r = l and
-// the ghost side mirrored).  It runs in FP64 in both forms (the FP32-mixed form reads
-// its FP32 records and evaluates them in FP64): the FP32 evaluation of this flux turns
-// non-finite next to a shock on large meshes.
+// the ghost side mirrored), in FP64.  MIXED: from the FP32-mixed records (the points
+// the FP32 pass leaves, and the coloured mode of the FP32-mixed form).
 template <bool MIXED, bool WALLS>
 __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
                                                 uint32_t r, bool wall, double Fo[5], double dFo[5]) {
@@ -1186,6 +1185,45 @@ __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, ui
         }
     }
     gks_flux_full<double>(qL, gL, qR, gR, nd, P.dt[0], P, Fo, dFo);
+}
+
+// The FP32-mixed form evaluates the tau > 0 flux in FP32 away from discontinuities.
+// A Gauss point where the two reconstructed sides differ by more than 30% in density
+// or pressure (a shock), where the positivity fallback acts, or whose flux is not
+// finite, is left to the FP64 evaluation of the fix-up pass (returns false).  (An
+// FP32 evaluation at every point went non-physical next to a diaphragm on large
+// meshes; with the FP64 path taking the shock points both shock-tube layouts run.)
+template <bool WALLS>
+__device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
+                                                  uint32_t r, bool wall, double Fo[5], double dFo[5]) {
+    const uint32_t nf = (uint32_t)P.nf;
+    const double *fg = P.fgeo;
+    const float n[3] = {(float)ldg<double>(fg, f * 8u), (float)ldg<double>(fg + nf, f * 8u),
+                        (float)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+    float yl[3], yr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        yl[a] = (float)ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
+        yr[a] = (float)ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
+    }
+    float qL[5], gL[5][3], qR[5], gR[5][3];
+    recon_point<float, false>(P, stage, l, yl, qL, gL);
+    recon_point<float, false>(P, stage, r, yr, qR, gR);
+    if constexpr (WALLS) reflect_grad(gR, n, wall ? 2.0f : 0.0f);
+    if (!(physical_point(qL) && physical_point(qR))) return false;
+    const float gm1 = (float)P.gamma - 1.0f;
+    const float pL = gm1 * (qL[4] - 0.5f * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) / qL[0]);
+    const float pR = gm1 * (qR[4] - 0.5f * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) / qR[0]);
+    if (!(hg_abs(pL - pR) <= 0.3f * (pL + pR) && hg_abs(qL[0] - qR[0]) <= 0.3f * (qL[0] + qR[0]))) return false;
+    float F[5], dF[5];
+    gks_flux_full<float>(qL, gL, qR, gR, n, (float)P.dt[0], P, F, dF);
+    if (!finite_flux(F, dF)) return false;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        Fo[k] = (double)F[k];
+        dFo[k] = (double)dF[k];
+    }
+    return true;
 }
 
 template <bool MIXED, bool TAU0, bool COLOURED, bool WALLS>
@@ -1297,19 +1335,69 @@ __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ pro
         const bool wall = WALLS && rr < 0;               // the ghost side is l's record mirrored
         const uint32_t r = rr < 0 ? l : (uint32_t)rr;
         double Fo[5], dFo[5];
-        point_flux_full<MIXED, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
+        bool done = true;
+        if constexpr (MIXED)
+            done = point_flux_full32<WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
+        else
+            point_flux_full<false, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
         const double w = ldg<double>(P.fgeo + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            out[k] = w * Fo[k];
-            out[5 + k] = w * dFo[k];
+            out[k] = done ? w * Fo[k] : __builtin_nan("");   // NaN: the face goes to the fix-up pass
+            out[5 + k] = done ? w * dFo[k] : __builtin_nan("");
         }
     }
+    double s0 = 0.0;
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         const double o1 = __shfl_down(out[k], 1u), o2 = __shfl_down(out[k], 2u);
         const double sum = (out[k] + o1) + o2;
+        if (k == 0) s0 = sum;
         if (ok && g == 0u) stg<double>(P.FF + (size_t)k * nf, f * 8u, sum);
+    }
+    if constexpr (MIXED) {
+        // the fix-up pass has work: a face left to FP64 (flag cleared by the stage update)
+        const uint64_t bad = __ballot(ok && g == 0u && !(s0 - s0 == 0.0));
+        if (bad != 0 && threadIdx.x == 0) P.flag[1] = 1;
+    }
+}
+
+// Faces the FP32 tau > 0 pass left (their flux is NaN): the three Gauss points again,
+// in FP64 from the FP32 records, summed in the same order.  Grid-stride over the face
+// tiles, after one look at every problem's flag (nothing to do is the common case).
+template <bool WALLS>
+__global__ __launch_bounds__(64) void k_flux_fix_full(const ProbDesc *__restrict__ probs, int nprobs,
+                                                      const Tile *__restrict__ tiles, int ntiles, int stage) {
+    bool any = false;
+    for (int k = threadIdx.x; k < nprobs; k += 64) any = any || ldg<int32_t>(probs[k].flag, 4u) != 0;
+    if (__ballot(any) == 0) return;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const ProbDesc &P = probs[tl.prob];
+        if (ldg<int32_t>(P.flag, 4u) == 0) continue;
+        const uint32_t f = tl.begin + threadIdx.x;
+        if (f >= (uint32_t)tl.end) continue;
+        const uint32_t nf = (uint32_t)P.nf;
+        const double f0 = ldg<double>(P.FF, f * 8u);
+        if (f0 - f0 == 0.0) continue;                     // finite: done in FP32
+        const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
+        const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
+        const bool wall = WALLS && rr < 0;
+        const uint32_t r = rr < 0 ? l : (uint32_t)rr;
+        const double w = ldg<double>(P.fgeo + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
+        double out[10];
+#pragma unroll 1
+        for (uint32_t g = 0; g < 3u; ++g) {
+            double Fo[5], dFo[5];
+            point_flux_full<true, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                out[k] = g == 0u ? w * Fo[k] : out[k] + w * Fo[k];
+                out[5 + k] = g == 0u ? w * dFo[k] : out[5 + k] + w * dFo[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
     }
 }
 
@@ -1501,6 +1589,11 @@ void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntile
                      else hipLaunchKernelGGL((k_flux_gp<true, false>), g, b, 0, s, probs, tiles, stage); }
         else { if (walls) hipLaunchKernelGGL((k_flux_gp<false, true>), g, b, 0, s, probs, tiles, stage);
                else hipLaunchKernelGGL((k_flux_gp<false, false>), g, b, 0, s, probs, tiles, stage); }
+        if (mixed) {            // faces left to FP64 by the FP32 pass
+            const dim3 gf(std::min(ntiles, 8 * device_cus())), bf(64);
+            if (walls) hipLaunchKernelGGL((k_flux_fix_full<true>), gf, bf, 0, s, probs, nprobs, tiles, ntiles, stage);
+            else hipLaunchKernelGGL((k_flux_fix_full<false>), gf, bf, 0, s, probs, nprobs, tiles, ntiles, stage);
+        }
         return;
     }
     dim3 g(ntiles), b(3 * FACE_TILE);
