@@ -54,7 +54,10 @@ typedef enum {
     HGKS_FP64 = 0,            /* every step in double precision */
     HGKS_FP32_MIXED = 1       /* FP64 geometry, pseudo-inverse contraction, state and
                                  accumulation; FP32 smoothness indicators, weights,
-                                 Gauss-point reconstruction and gas-kinetic flux */
+                                 Gauss-point reconstruction and gas-kinetic flux
+                                 (with tau > 0, Gauss points across a shock, where the
+                                 two sides differ by more than 30%, are evaluated in
+                                 FP64) */
 } hgks_precision;
 
 typedef enum {
