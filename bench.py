@@ -42,14 +42,24 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
 #          = 264, plus per cell the reconstruction read once (400)
 #   update per cell: face ids (16) + its faces' fluxes (2 faces' worth, 160) + 1/|V|
 #          and h (16) + state traffic (stage 1: 3 x 40, stage 2: 2 x 40)       ~ 292
-def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool) -> float:
+def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool = False) -> float:
     if kernel == "weno":
-        return nc * (64 + 40 + 1152 + 56 + 24 + 16 + (200 if mixed else 400))
+        return nc * (64 + 40 + (576 if pinv32 else 1152) + 56 + 24 + 16 + (200 if mixed else 400))
     if kernel == "flux":
         return nf * 264 + nc * ((200 + 40) if mixed else 400)
     if kernel == "update":
         return nc * (16 + 160 + 16 + 100)
     return 0.0
+
+
+def reduced_weno(r, nc: int, nf: int, pinv32: bool):
+    """Average WENO launch time of a reduced-precision run, and its algorithmic rate."""
+    ms, cnt = r["prof"]["weno"]
+    if not cnt:
+        return None
+    avg_s = ms / 1e3 / cnt
+    return {"us": round(1e6 * avg_s, 2),
+            "alg_GBps": round(algorithmic_bytes("weno", nc, nf, True, pinv32) / avg_s / 1e9, 1)}
 
 
 def kernel_source_hash() -> str:
@@ -181,10 +191,12 @@ def main():
     r64 = run_gpu(mesh, q0, hgks.FP64, args.steps, args.warmup)
     nf = r64["info"]["n_faces"]
     value = nc * args.steps / r64["seconds"]
-    r32 = None
+    r32 = r32f = None
     if not args.no_fp32:
         print("bench: FP32-mixed", file=sys.stderr, flush=True)
         r32 = run_gpu(mesh, q0, hgks.FP32_MIXED, args.steps, args.warmup)
+        print("bench: FP32", file=sys.stderr, flush=True)
+        r32f = run_gpu(mesh, q0, hgks.FP32, args.steps, args.warmup)
 
     # dominant kernel of the FP64 step and its roofline position
     prof = r64["prof"]
@@ -235,7 +247,13 @@ def main():
         "fp32_mixed": None if r32 is None else {
             "value": round(nc * args.steps / r32["seconds"], 1),
             "ms_per_step": round(1e3 * r32["seconds"] / args.steps, 4),
-            "speedup_vs_fp64": round(r64["seconds"] / r32["seconds"], 3)},
+            "speedup_vs_fp64": round(r64["seconds"] / r32["seconds"], 3),
+            "weno": reduced_weno(r32, nc, nf, False)},
+        "fp32": None if r32f is None else {
+            "value": round(nc * args.steps / r32f["seconds"], 1),
+            "ms_per_step": round(1e3 * r32f["seconds"] / args.steps, 4),
+            "speedup_vs_fp64": round(r64["seconds"] / r32f["seconds"], 3),
+            "weno": reduced_weno(r32f, nc, nf, True)},
         "serve": srv,
         "kernels": kernels,
         "setup_s": round(r64["setup_s"], 2),

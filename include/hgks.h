@@ -57,7 +57,15 @@ typedef enum {
                                  Gauss-point reconstruction and gas-kinetic flux
                                  (with tau > 0, Gauss points across a shock, where the
                                  two sides differ by more than 30%, are evaluated in
-                                 FP64) */
+                                 FP64) */,
+    HGKS_FP32 = 2             /* the FP32-mixed form with the big-stencil pseudo-inverse
+                                 stored in FP32 (each coefficient rounded once at
+                                 mesh upload, half its bytes) and its contraction, the
+                                 sub-stencil fits' contraction and the stencil
+                                 differences in FP32: the storage and arithmetic side of
+                                 the single-precision build of Sec. 5.1 (memory and
+                                 speed against FP64) where it carries the bytes; the
+                                 state, geometry, accumulation and update stay FP64 */
 } hgks_precision;
 
 typedef enum {
@@ -187,14 +195,15 @@ hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const 
  * steps any subset of them together, one launch per phase covering every
  * slot's tiles, with each slot's own dt.  Per-cell arithmetic never depends on
  * the batch, so a slot's results are bitwise the same alone or in a mix.
- * Contexts of both precisions may share a pool (their phases launch separately).
+ * Contexts of every precision may share a pool (their phases launch separately).
  */
 typedef struct hgks_pool hgks_pool;
 
 /* hbm_budget: admission limit on the summed footprints of the slots (0 = none). */
 hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hgks_pool **out);
 /* Bytes a context with this mesh size will hold (used for admission; exact for a
- * periodic mesh, wall faces add 8 + 176 + 80 bytes each). */
+ * periodic mesh, wall faces add 8 + 176 + 80 bytes each).  HGKS_E_INVALID_ARG for
+ * parameters hgks_create would reject, n_cells <= 0 or nodes_per_cell != 4. */
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int nodes_per_cell, size_t *bytes);
 /* Adds a context (mesh uploaded, state initialised); returns its slot id.
  * Errors: STATE, INVALID_ARG (other device), OOM (budget exceeded). */

@@ -41,12 +41,13 @@ struct Layout {
     size_t sten, pinv0, cen, sshift, cgeo, cface, fcell, fgeo, Q, Qs, R, C, C32, FF, acc, dtpart, scal, desc, tiles, total;
 };
 
-Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, bool mixed, bool coloured) {
+Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, int prec, bool coloured) {
+    const bool mixed = prec != HGKS_FP64;
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t p = o; o += up(bytes); return p; };
     L.sten = take((size_t)SLOTS * nc * 4);
-    L.pinv0 = take((size_t)144 * nc * 8);
+    L.pinv0 = take((size_t)144 * nc * (prec == HGKS_FP32 ? 4 : 8));
     L.cen = take((size_t)3 * nc * 8);
     L.sshift = take((size_t)4 * nc * 4);
     L.cgeo = take((size_t)CGEO * nc * 8);
@@ -181,20 +182,22 @@ hgks_status check_params(const hgks_params *p) {
     if (!(p->gamma > 1.0 && p->gamma < 5.0 / 3.0 + 1e-12)) return HGKS_E_INVALID_ARG;
     if (!(p->cfl > 0.0) || !(p->weno_eps > 0.0) || !(p->gamma_lin > 0.0 && p->gamma_lin < 0.25)) return HGKS_E_INVALID_ARG;
     if (p->tau_mode < 0 || p->tau_mode > 1) return HGKS_E_INVALID_ARG;
-    if (p->precision != HGKS_FP64 && p->precision != HGKS_FP32_MIXED) return HGKS_E_INVALID_ARG;
+    if (p->precision != HGKS_FP64 && p->precision != HGKS_FP32_MIXED && p->precision != HGKS_FP32)
+        return HGKS_E_INVALID_ARG;
     if (p->accumulation != HGKS_ACC_GATHER && p->accumulation != HGKS_ACC_COLOURED) return HGKS_E_INVALID_ARG;
     return HGKS_OK;
 }
 
 // Queue one S2O4 step of a single context.
 void enqueue_step(hgks_ctx *c, double dt_fixed) {
-    const bool mixed = c->prm.precision == HGKS_FP32_MIXED;
+    const int prec = c->prm.precision;
+    const bool mixed = prec != HGKS_FP64;
     const bool tau0 = tau0_of(c->prm);
     const bool col = c->prm.accumulation == HGKS_ACC_COLOURED;
     hipStream_t s = c->stream;
     timed(c, 0, [&] { launch_dt_final(c->d_desc, 1, dt_fixed, s); });
     for (int stage = 1; stage <= 2; ++stage) {
-        timed(c, 1, [&] { launch_weno(c->d_desc, c->d_ctiles, c->n_ctiles, stage, mixed, c->walls, s); });
+        timed(c, 1, [&] { launch_weno(c->d_desc, c->d_ctiles, c->n_ctiles, stage, prec, c->walls, s); });
         if (col) {
             for (size_t k = 0; k + 1 < c->colour_tiles.size(); ++k) {
                 int t0 = c->colour_tiles[k], t1 = c->colour_tiles[k + 1];
@@ -263,7 +266,8 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     if (st != HGKS_OK) return fail(c, st, err);
     HIPCHK(c, hipSetDevice(c->device));
     release(c);
-    const bool mixed = c->prm.precision == HGKS_FP32_MIXED;
+    const int prec = c->prm.precision;
+    const bool mixed = prec != HGKS_FP64;
     const bool col = c->prm.accumulation == HGKS_ACC_COLOURED;
     // tile tables
     std::vector<Tile> ct, ft;
@@ -289,7 +293,7 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
             ft.push_back({0, (int32_t)b, (int)ft.size(), (int32_t)std::min<int64_t>(hm.nf, b + fw)});
         xcd_order(ft, 0, ft.size());
     }
-    Layout L = layout_for(hm.nc, hm.nf, (int)ct.size(), (int)ft.size(), mixed, col);
+    Layout L = layout_for(hm.nc, hm.nf, (int)ct.size(), (int)ft.size(), prec, col);
     void *mem = nullptr;
     if (c->user_alloc) {
         mem = c->alloc.alloc(L.total, c->stream, c->alloc.user);
@@ -307,7 +311,8 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     D.nf = (int32_t)hm.nf;
     D.n_cell_tiles = (int32_t)ct.size();
     D.sten = (const int32_t *)(B + L.sten);
-    D.pinv0 = (const double *)(B + L.pinv0);
+    D.pinv0 = prec == HGKS_FP32 ? nullptr : (const double *)(B + L.pinv0);
+    D.pinv32 = prec == HGKS_FP32 ? (const float *)(B + L.pinv0) : nullptr;
     D.cen = (const double *)(B + L.cen);
     D.sshift = (const uint32_t *)(B + L.sshift);
     for (int a = 0; a < 3; ++a) {
@@ -351,7 +356,19 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
         return hipMemcpyAsync((void *)dst, src, n, hipMemcpyHostToDevice, s);
     };
     HIPCHK(c, h2d(D.sten, hm.sten.data(), hm.sten.size() * 4));
-    HIPCHK(c, h2d(D.pinv0, hm.pinv0.data(), hm.pinv0.size() * 8));
+    if (prec == HGKS_FP32) {
+        // pair rows 2k and 2k+1 of a cell become its quad row k, each value rounded once
+        const size_t n = (size_t)hm.nc;
+        hvec<float> p32(hm.pinv0.size());
+        for (size_t k = 0; k < 36; ++k)
+            for (size_t i = 0; i < n; ++i)
+                for (size_t e = 0; e < 4; ++e)
+                    p32[(k * n + i) * 4 + e] = (float)hm.pinv0[((2 * k + e / 2) * n + i) * 2 + e % 2];
+        HIPCHK(c, h2d(D.pinv32, p32.data(), p32.size() * 4));
+        HIPCHK(c, hipStreamSynchronize(s));   // p32 is released on return
+    } else {
+        HIPCHK(c, h2d(D.pinv0, hm.pinv0.data(), hm.pinv0.size() * 8));
+    }
     HIPCHK(c, h2d(D.cen, hm.cen.data(), hm.cen.size() * 8));
     HIPCHK(c, h2d(D.sshift, hm.sshift.data(), hm.sshift.size() * 4));
     HIPCHK(c, h2d(D.cgeo, hm.cgeo.data(), hm.cgeo.size() * 8));
@@ -552,7 +569,7 @@ struct hgks_pool {
     ProbDesc *d_probs = nullptr;
     int nprobs = 0;
     Tile *d_ct = nullptr, *d_ft = nullptr;
-    struct Group { bool mixed, tau0; int c0, c1, f0, f1; bool walls; };
+    struct Group { int prec; bool tau0; int c0, c1, f0, f1; bool walls; };
     std::vector<Group> groups;
     int n_ct = 0;
 };
@@ -566,14 +583,14 @@ size_t footprint_of(const hgks_params &p, int64_t nc) {
     const bool col = p.accumulation == HGKS_ACC_COLOURED;
     const int fw = (col || p.tau_mode == 0) ? FACE_TILE : 3 * GP_FACES;
     const int nft = (int)((nf + fw - 1) / fw) + (col ? 8 : 0);
-    Layout L = layout_for(nc, nf, nct, nft, p.precision == HGKS_FP32_MIXED, p.accumulation == HGKS_ACC_COLOURED);
+    Layout L = layout_for(nc, nf, nct, nft, p.precision, p.accumulation == HGKS_ACC_COLOURED);
     return L.total;
 }
 
 hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
     std::vector<int> key(slots, slots + n);
     if (key == P->last_key && P->tab) return HGKS_OK;
-    // group contexts by kernel variant; FP64 first, then FP32-mixed
+    // group contexts by kernel variant; FP64 first, then FP32-mixed, then FP32
     std::vector<int> order(key);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         auto ka = std::make_pair(P->slot[a]->prm.precision, P->slot[a]->prm.tau_mode);
@@ -585,9 +602,10 @@ hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
     P->groups.clear();
     for (size_t k = 0; k < order.size(); ++k) {
         hgks_ctx *c = P->slot[order[k]];
-        bool mixed = c->prm.precision == HGKS_FP32_MIXED, tau0 = c->prm.tau_mode == 0;
-        if (P->groups.empty() || P->groups.back().mixed != mixed || P->groups.back().tau0 != tau0)
-            P->groups.push_back({mixed, tau0, (int)ct.size(), (int)ct.size(), (int)ft.size(), (int)ft.size(), false});
+        const int prec = c->prm.precision;
+        const bool tau0 = c->prm.tau_mode == 0;
+        if (P->groups.empty() || P->groups.back().prec != prec || P->groups.back().tau0 != tau0)
+            P->groups.push_back({prec, tau0, (int)ct.size(), (int)ct.size(), (int)ft.size(), (int)ft.size(), false});
         P->groups.back().walls = P->groups.back().walls || c->walls;
         const int pid = (int)probs.size();
         probs.push_back(c->desc);
@@ -643,6 +661,7 @@ hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hg
 
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int npc, size_t *bytes) {
     if (!params || !bytes || n_cells <= 0 || npc != 4) return HGKS_E_INVALID_ARG;
+    if (check_params(params) != HGKS_OK) return HGKS_E_INVALID_ARG;
     *bytes = footprint_of(*params, n_cells);
     return HGKS_OK;
 }
@@ -685,8 +704,8 @@ hgks_status hgks_pool_step(hgks_pool *p, const int *slots, int n, int32_t nsteps
     for (int32_t it = 0; it < nsteps; ++it) {
         launch_dt_final(p->d_probs, p->nprobs, 0.0, s);
         for (int stage = 1; stage <= 2; ++stage) {
-            for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.mixed, g.walls, s);
-            for (auto &g : p->groups) launch_flux(p->d_probs, p->nprobs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.mixed, g.tau0, false, g.walls, s);
+            for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.prec, g.walls, s);
+            for (auto &g : p->groups) launch_flux(p->d_probs, p->nprobs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.prec != HGKS_FP64, g.tau0, false, g.walls, s);
             launch_update(p->d_probs, p->d_ct, p->n_ct, stage, false, s);
         }
     }

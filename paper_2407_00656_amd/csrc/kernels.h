@@ -13,7 +13,8 @@ struct ProbDesc {
     int32_t nc, nf;
     int32_t n_cell_tiles, pad0;
     const int32_t *sten;
-    const double *pinv0;
+    const double *pinv0;          // big-stencil pseudo-inverse, FP64 pair rows [72][nc]
+    const float *pinv32;          // the same rounded to FP32 as quad rows [36][nc] (FP32 form)
     const double *cen;            // centroids [3][nc]
     const uint32_t *sshift;       // periodic image codes of the stencil slots [4][nc]
     const double *cgeo;
@@ -50,7 +51,8 @@ constexpr int GP_FACES = 21;     // tau > 0 flux without colouring: faces per si
 constexpr int WENO_TILE = 64;    // cells per WENO workgroup (5 waves: one per variable)
 constexpr int UPD_TILE = 64;     // cells per update / dt workgroup
 
-void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool walls,
+// prec: 0 FP64, 1 FP32-mixed, 2 FP32 (the hgks_precision values)
+void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, int prec, bool walls,
                  hipStream_t s);
 void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0,
                  bool coloured, bool walls, hipStream_t s);

@@ -47,6 +47,9 @@ struct alignas(16) d2 {
 struct alignas(8) f2 {
     float x, y;
 };
+struct alignas(16) f4 {
+    float x, y, z, w;
+};
 
 #if defined(__HIP_DEVICE_COMPILE__)
 template <class T>
@@ -65,9 +68,17 @@ __device__ __forceinline__ d2 ldg_stream(const void *base, uint32_t off) {
     const v2d v = __builtin_nontemporal_load((gptr<const v2d>)((gptr<const char>)base + off));
     return {v.x, v.y};
 }
+__device__ __forceinline__ f4 ldg_stream_f4(const void *base, uint32_t off) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f v = __builtin_nontemporal_load((gptr<const v4f>)((gptr<const char>)base + off));
+    return {v.x, v.y, v.z, v.w};
+}
 #else
 __device__ __forceinline__ d2 ldg_stream(const void *base, uint32_t off) {
     return *(const d2 *)((const char *)base + off);
+}
+__device__ __forceinline__ f4 ldg_stream_f4(const void *base, uint32_t off) {
+    return *(const f4 *)((const char *)base + off);
 }
 template <class T>
 __device__ __forceinline__ T ldg(const void *base, uint32_t off) {
@@ -143,9 +154,9 @@ __device__ __forceinline__ T quad_form(const T M[6], T g0, T g1, T g2) {
 
 // Smoothness indicators, WENO-Z weights and the combined polynomial of one
 // variable of one cell, written as five coefficient pairs.
-template <class T, class PAIR>
-__device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint32_t nc, double qi, const double a64[9],
-                                             const double b64[4][3], const double geo[7], PAIR *C, bool store) {
+template <class T, class PAIR, class A>
+__device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint32_t nc, double qi, const A a64[9],
+                                             const A b64[4][3], const double geo[7], PAIR *C, bool store) {
     // basis order: x, y, z, xx, yy, zz, xy, xz, yz (scaled coordinates xi = (x-c)/h)
     // geo: 1/h and the six scaled second moments of the cell (cgeo rows 0..6)
     T a[9], b[4][3], M[6];
@@ -212,9 +223,11 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
 // the mean of the scaled linear basis over the member (the basis has zero mean over
 // the cell itself), and the pseudo-inverse is (A^T A)^-1 A^T over the distinct
 // members; a member met twice gets a zero column.  The 3x3 normal matrix is
-// inverted through its adjugate.  out[k][t]: row k (d/dxi_k), member t.
-template <bool WALLS>
-__device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, uint32_t m, double out[3][6]) {
+// inverted through its adjugate.  out[k][t]: row k (d/dxi_k), member t.  The rows
+// are formed in FP64 (differences of centroids); T is the precision of the normal
+// matrix, its inverse and the result (float in the FP32 form).
+template <bool WALLS, class T>
+__device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, uint32_t m, T out[3][6]) {
     const size_t nc = (size_t)P.nc;
     // first-layer slots of sub-stencil m, four bits each: SUBFIRST[m][t]
     constexpr uint64_t FIRST = (uint64_t)SUBFIRST[0][0] | (uint64_t)SUBFIRST[0][1] << 4 |
@@ -226,7 +239,7 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
     const double ih = P.cgeo[i];
     const double ci[3] = {P.cen[i], P.cen[nc + i], P.cen[2 * nc + i]};
     const uint32_t w0 = P.sshift[i], w1 = P.sshift[nc + i], w2 = P.sshift[2 * nc + i], w3 = P.sshift[3 * nc + i];
-    double A[6][3];
+    T A[6][3];
     int32_t id[6];
     uint32_t code[6];
 #pragma unroll
@@ -246,7 +259,7 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
                 const double mlo = P.mir[a][0], mhi = P.mir[a][1];
                 if (!(P.per[a] > 0.0)) x = sh[a] == 0 ? c : (sh[a] > 0 ? mhi : mlo) - c;
             }
-            A[t][a] = (x - ci[a]) * ih;
+            A[t][a] = (T)((x - ci[a]) * ih);
         }
     }
     bool dup[6];
@@ -256,24 +269,24 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
 #pragma unroll
         for (int u = 0; u < t; ++u) dup[t] = dup[t] || (id[u] == id[t] && code[u] == code[t]);
     }
-    double n00 = 0, n01 = 0, n02 = 0, n11 = 0, n12 = 0, n22 = 0;
+    T n00 = 0, n01 = 0, n02 = 0, n11 = 0, n12 = 0, n22 = 0;
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
-        const double x = dup[t] ? 0.0 : A[t][0], y = dup[t] ? 0.0 : A[t][1], z = dup[t] ? 0.0 : A[t][2];
+        const T x = dup[t] ? T(0) : A[t][0], y = dup[t] ? T(0) : A[t][1], z = dup[t] ? T(0) : A[t][2];
         n00 = fma(x, x, n00); n01 = fma(x, y, n01); n02 = fma(x, z, n02);
         n11 = fma(y, y, n11); n12 = fma(y, z, n12); n22 = fma(z, z, n22);
     }
-    const double c00 = n11 * n22 - n12 * n12, c01 = n02 * n12 - n01 * n22, c02 = n01 * n12 - n02 * n11;
-    const double c11 = n00 * n22 - n02 * n02, c12 = n01 * n02 - n00 * n12, c22 = n00 * n11 - n01 * n01;
-    const double idet = 1.0 / (n00 * c00 + n01 * c01 + n02 * c02);
-    const double inv[3][3] = {{c00 * idet, c01 * idet, c02 * idet},
-                              {c01 * idet, c11 * idet, c12 * idet},
-                              {c02 * idet, c12 * idet, c22 * idet}};
+    const T c00 = n11 * n22 - n12 * n12, c01 = n02 * n12 - n01 * n22, c02 = n01 * n12 - n02 * n11;
+    const T c11 = n00 * n22 - n02 * n02, c12 = n01 * n02 - n00 * n12, c22 = n00 * n11 - n01 * n01;
+    const T idet = T(1) / (n00 * c00 + n01 * c01 + n02 * c02);
+    const T inv[3][3] = {{c00 * idet, c01 * idet, c02 * idet},
+                         {c01 * idet, c11 * idet, c12 * idet},
+                         {c02 * idet, c12 * idet, c22 * idet}};
 #pragma unroll
     for (int t = 0; t < 6; ++t)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            out[k][t] = dup[t] ? 0.0 : inv[k][0] * A[t][0] + inv[k][1] * A[t][1] + inv[k][2] * A[t][2];
+            out[k][t] = dup[t] ? T(0) : inv[k][0] * A[t][0] + inv[k][1] * A[t][1] + inv[k][2] * A[t][2];
 }
 
 // Pseudo-inverse pair rows in LDS: 72 of the big stencil (row r, slots 2s, 2s+1 at
@@ -288,13 +301,23 @@ constexpr int WPAIRS0 = 72, WPAIRS = 108;
 template <int WC>
 constexpr int weno_threads() { return (5 * WC + 63) / 64 * 64; }
 
-template <bool MIXED, int WC, bool WALLS>
+template <int PREC, int WC, bool WALLS>
 __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__restrict__ probs,
                                                               const Tile *__restrict__ tiles, int stage) {
+    // PREC 0: FP64; 1: FP32-mixed (FP32 from the weights on); 2: FP32 form (the
+    // big-stencil pseudo-inverse arrives as FP32 quad rows, both contractions in FP32)
+    constexpr bool F32 = PREC == 2;
     constexpr int NT = weno_threads<WC>();
     constexpr int SPLIT = WENO_TILE / WC;              // workgroups per cell tile
     static_assert(4 * WC <= NT, "one sub-stencil fit per thread");
-    __shared__ d2 stage_buf[WPAIRS][WC];
+    // LDS: 72 big-stencil + 36 sub-stencil FP64 pair rows, or in the FP32 form 36
+    // big-stencil FP32 quad rows + 36 sub-stencil FP32 pair rows (two thirds less)
+    constexpr int ROWS = F32 ? 36 : WPAIRS0;           // streamed rows per cell
+    constexpr size_t LDS_BYTES = F32 ? (size_t)(36 * 16 + 36 * 8) * WC : (size_t)WPAIRS * 16 * WC;
+    __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
+    d2(*stage_buf)[WC] = reinterpret_cast<d2(*)[WC]>(smem);
+    f4(*big32)[WC] = reinterpret_cast<f4(*)[WC]>(smem);
+    f2(*sub32)[WC] = reinterpret_cast<f2(*)[WC]>(smem + 36 * 16 * WC);
     // Workgroups go to the eight XCDs round-robin by id, and the tile table is laid
     // out so that XCD x owns a contiguous run of tiles when each tile has one
     // workgroup.  A tile here has SPLIT workgroups, so renumber: XCD x takes a
@@ -316,31 +339,47 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     const uint32_t c0 = tl.begin + (bx % SPLIT) * WC;   // first cell of this workgroup
     const uint32_t last = (uint32_t)tl.end - 1;
     const d2 *p0 = reinterpret_cast<const d2 *>(P.pinv0);
+    const f4 *p32 = reinterpret_cast<const f4 *>(P.pinv32);
     // 1. stream the big-stencil pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the tile)
-    constexpr int PER = (WPAIRS0 * WC + NT - 1) / NT;
-    d2 reg[PER];
+    using SV = std::conditional_t<F32, f4, d2>;
+    using DT = std::conditional_t<F32, float, double>;   // contraction precision
+    constexpr int PER = (ROWS * WC + NT - 1) / NT;
+    SV reg[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(WPAIRS0 * WC)) {
+        if (e < (uint32_t)(ROWS * WC)) {
             const uint32_t row = e / WC, c = min(c0 + e % WC, last);
-            reg[k] = ldg_stream(p0 + (size_t)row * nc, c * 16u);
+            if constexpr (F32)
+                reg[k] = ldg_stream_f4(p32 + (size_t)row * nc, c * 16u);
+            else
+                reg[k] = ldg_stream(p0 + (size_t)row * nc, c * 16u);
         }
     }
     // 2. the sub-stencil fits: thread (m, c) for m < 4
     if (threadIdx.x < 4u * WC) {
         const uint32_t m = threadIdx.x / WC, cs = threadIdx.x % WC;
-        double ps[3][6];
+        DT ps[3][6];
         sub_stencil_pinv<WALLS>(P, min(c0 + cs, last), m, ps);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int u = 0; u < 3; ++u) stage_buf[WPAIRS0 + (m * 3 + k) * 3 + u][cs] = d2{ps[k][2 * u], ps[k][2 * u + 1]};
+            for (int u = 0; u < 3; ++u) {
+                if constexpr (F32)
+                    sub32[(m * 3 + k) * 3 + u][cs] = f2{ps[k][2 * u], ps[k][2 * u + 1]};
+                else
+                    stage_buf[WPAIRS0 + (m * 3 + k) * 3 + u][cs] = d2{ps[k][2 * u], ps[k][2 * u + 1]};
+            }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(WPAIRS0 * WC)) stage_buf[e / WC][e % WC] = reg[k];
+        if (e < (uint32_t)(ROWS * WC)) {
+            if constexpr (F32)
+                big32[e / WC][e % WC] = reg[k];
+            else
+                stage_buf[e / WC][e % WC] = reg[k];
+        }
     }
     // 2. this lane's variable and cell; gather the stencil differences meanwhile
     const uint32_t v = threadIdx.x / WC, cl = threadIdx.x % WC;
@@ -349,7 +388,8 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     const bool ok = active && i0 <= last;
     const uint32_t i = min(i0, last);
     const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)(active ? v : 0u) * nc;
-    double qi = 0.0, d[SLOTS], geo[7];
+    double qi = 0.0, geo[7];
+    DT d[SLOTS];
     if (active) {
         qi = ldg<double>(Qv, i * 8u);
 #pragma unroll
@@ -357,38 +397,67 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             const uint32_t j = (uint32_t)ldg<int32_t>(P.sten + (size_t)s * nc, i * 4u);
-            d[s] = ldg<double>(Qv, j * 8u) - qi;
+            d[s] = (DT)(ldg<double>(Qv, j * 8u) - qi);   // the difference in FP64, then rounded once
         }
     }
     __syncthreads();
     if (!active) return;
     // 3. a = Pinv0 (Q_k - Q_i) on the big stencil; b^m = Pinv_m (Q_k - Q_i) on sub-stencil m
-    double a[9], b[4][3];
+    DT a[9], b[4][3];
+    if constexpr (F32) {
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-        double acc = 0.0;
+        for (int r = 0; r < 9; ++r) {
+            float acc = 0.0f;
 #pragma unroll
-        for (int s2 = 0; s2 < SLOTS / 2; ++s2) {
-            const d2 pp = stage_buf[r * 8 + s2][cl];
-            acc = fma(pp.x, d[2 * s2], acc);
-            acc = fma(pp.y, d[2 * s2 + 1], acc);
+            for (int q = 0; q < 4; ++q) {
+                const f4 pp = big32[r * 4 + q][cl];
+                acc = fmaf(pp.x, d[4 * q], acc);
+                acc = fmaf(pp.y, d[4 * q + 1], acc);
+                acc = fmaf(pp.z, d[4 * q + 2], acc);
+                acc = fmaf(pp.w, d[4 * q + 3], acc);
+            }
+            a[r] = acc;
         }
-        a[r] = acc;
-    }
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < 3; ++k) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int t2 = 0; t2 < 3; ++t2) {
+                    const f2 pp = sub32[(m * 3 + k) * 3 + t2][cl];
+                    acc = fmaf(pp.x, d[sub_slot(m, 2 * t2)], acc);
+                    acc = fmaf(pp.y, d[sub_slot(m, 2 * t2 + 1)], acc);
+                }
+                b[m][k] = acc;
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
             double acc = 0.0;
 #pragma unroll
-            for (int t2 = 0; t2 < 3; ++t2) {
-                const d2 pp = stage_buf[WPAIRS0 + (m * 3 + k) * 3 + t2][cl];
-                acc = fma(pp.x, d[sub_slot(m, 2 * t2)], acc);
-                acc = fma(pp.y, d[sub_slot(m, 2 * t2 + 1)], acc);
+            for (int s2 = 0; s2 < SLOTS / 2; ++s2) {
+                const d2 pp = stage_buf[r * 8 + s2][cl];
+                acc = fma(pp.x, d[2 * s2], acc);
+                acc = fma(pp.y, d[2 * s2 + 1], acc);
             }
-            b[m][k] = acc;
+            a[r] = acc;
         }
-    if constexpr (MIXED)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int t2 = 0; t2 < 3; ++t2) {
+                    const d2 pp = stage_buf[WPAIRS0 + (m * 3 + k) * 3 + t2][cl];
+                    acc = fma(pp.x, d[sub_slot(m, 2 * t2)], acc);
+                    acc = fma(pp.y, d[sub_slot(m, 2 * t2 + 1)], acc);
+                }
+                b[m][k] = acc;
+            }
+    }
+    if constexpr (PREC != 0)
         weno_combine<float>(P, i, nc, qi, a, b, geo, reinterpret_cast<f2 *>(P.C32) + (size_t)v * 5 * nc, ok);
     else
         weno_combine<double>(P, i, nc, qi, a, b, geo, reinterpret_cast<d2 *>(P.C) + (size_t)v * 5 * nc, ok);
@@ -1540,13 +1609,14 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 // ----------------------------------------------------------------------------
 constexpr int WENO_CELLS = HGKS_WENO_CELLS;     // cells per WENO workgroup (16, 32 or 64)
 
-void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool mixed, bool walls,
+void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, int prec, bool walls,
                  hipStream_t s) {
     if (ntiles <= 0) return;
     dim3 g(ntiles * (WENO_TILE / WENO_CELLS)), b(weno_threads<WENO_CELLS>());
 #define HGKS_WENO(M, WA) hipLaunchKernelGGL((k_weno<M, WENO_CELLS, WA>), g, b, 0, s, probs, tiles, stage)
-    if (mixed) { if (walls) HGKS_WENO(true, true); else HGKS_WENO(true, false); }
-    else { if (walls) HGKS_WENO(false, true); else HGKS_WENO(false, false); }
+    if (prec == 2) { if (walls) HGKS_WENO(2, true); else HGKS_WENO(2, false); }
+    else if (prec == 1) { if (walls) HGKS_WENO(1, true); else HGKS_WENO(1, false); }
+    else { if (walls) HGKS_WENO(0, true); else HGKS_WENO(0, false); }
 #undef HGKS_WENO
 }
 

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhgks.so")
 
 OK, E_INVALID_ARG, E_BAD_MESH, E_STATE, E_OOM, E_DEVICE, E_NONPHYSICAL = range(7)
-FP64, FP32_MIXED = 0, 1
+FP64, FP32_MIXED, FP32 = 0, 1, 2
 ACC_GATHER, ACC_COLOURED = 0, 1
 KERNEL_IDS = {"dt": 0, "weno": 1, "flux": 2, "update": 3}
 

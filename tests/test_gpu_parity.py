@@ -2,7 +2,11 @@
 
 Bars (per conserved variable, normalised as in helpers.scaled_err):
   FP64 path      <= 1e-12 after one step from an identical state;
-  FP32-mixed     <= 1e-5 relative L1 after the full run.
+  FP32-mixed     <= 1e-5 relative L1 after the full run;
+  FP32           the same bar (the pseudo-inverse rounded once to FP32 adds a
+                 relative 6e-8 to each coefficient, the FP32 contractions about
+                 16 roundings of the largest product: the same order as the
+                 FP32-mixed form's own rounding of the weights and fluxes).
 """
 import sys
 
@@ -86,24 +90,42 @@ def test_fp64_coloured_accumulation():
         per_step_parity(mesh, q0, 2, accumulation=hgks.ACC_COLOURED)
 
 
-def test_fp32_mixed_config1_full_run():
-    say("case: fp32-mixed N=8 20 steps vs oracle")
+@pytest.mark.parametrize("prec", [hgks.FP32_MIXED, hgks.FP32])
+def test_fp32_config1_full_run(prec):
+    say(f"case: precision {prec} N=8 20 steps vs oracle")
     mesh, case, q0 = advection_case(8)
     om = O.Mesh.from_workload(mesh)
     vol = om.cells()[0]
     q_orc, _ = om.step(q0, 20)
-    s = make_solver(mesh, q0, precision=hgks.FP32_MIXED)
+    s = make_solver(mesh, q0, precision=prec)
     s.step(20)
     q32, _ = s.get_state()
     err = rel_l1(q32, q_orc, vol)
-    say("relative L1 (fp32-mixed vs fp64 oracle)", err)
+    say("relative L1 (reduced precision vs fp64 oracle)", err)
+    assert np.all(err <= TOL32), err
+
+
+def test_fp32_odd_ragged_tau_positive():
+    """The FP32 form on an odd, ragged mesh (tiles with a tail) with tau > 0."""
+    say("case: fp32 N=(7,5,4) tau_mode=1 8 steps vs oracle")
+    mesh = W.kuhn_box((7, 5, 4), (1.4, 1.0, 0.8), jitter=0.12, seed=4245)
+    q0 = smooth_state(mesh, 13)
+    om = O.Mesh.from_workload(mesh)
+    vol = om.cells()[0]
+    q_orc, _ = om.step(q0, 8, params=oracle_params(tau_mode=1))
+    s = make_solver(mesh, q0, precision=hgks.FP32, tau_mode=1)
+    s.step(8)
+    q32, _ = s.get_state()
+    s.close()
+    err = rel_l1(q32, q_orc, vol)
+    say("relative L1 (fp32 vs fp64 oracle)", err)
     assert np.all(err <= TOL32), err
 
 
 def test_bitwise_determinism_and_restart():
     say("case: determinism + checkpoint/restart N=6")
     mesh, case, q0 = advection_case(6, seed=110, vel=(0.5, 1.0, -0.2))
-    for prec in (hgks.FP64, hgks.FP32_MIXED):
+    for prec in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32):
         a = make_solver(mesh, q0, precision=prec)
         a.step(6)
         qa, ta = a.get_state()
@@ -129,7 +151,7 @@ def test_free_stream_and_conservation_on_gpu():
     mesh = W.kuhn_box(8, seed=111)
     vol = W.tet_volumes(mesh.cell_vertices)
     qu = W.uniform_state(mesh.n_cells, rho=1.2, vel=(0.4, -0.9, 0.3), p=0.8)
-    for prec in (hgks.FP64, hgks.FP32_MIXED):
+    for prec in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32):
         s = make_solver(mesh, qu, precision=prec)
         s.step(5)
         q, _ = s.get_state()
@@ -176,7 +198,7 @@ def test_pool_alone_vs_mix_bitwise():
     mixed pooled launch (different sizes, precisions and collision-time modes)."""
     say("case: pool alone vs mix")
     cases = [(6, 120, dict()), (8, 121, dict(precision=hgks.FP32_MIXED)), (5, 122, dict(tau_mode=1)),
-             (7, 123, dict())]
+             (7, 123, dict()), (6, 125, dict(precision=hgks.FP32)), (5, 126, dict(precision=hgks.FP32, tau_mode=1))]
     alone, solvers = [], []
     for n, seed, kw in cases:
         mesh, case, q0 = advection_case(n, seed=seed, vel=(0.7, 0.1, -0.5))
@@ -193,7 +215,7 @@ def test_pool_alone_vs_mix_bitwise():
         q, _ = s.get_state()
         assert np.array_equal(q, alone[k]), k
     used, n = pool.used()
-    assert n == 4 and used == sum(s.footprint() for s in solvers)
+    assert n == len(cases) and used == sum(s.footprint() for s in solvers)
     for sl in slots:
         pool.remove(sl)
     pool.close()
@@ -236,21 +258,22 @@ def test_full_size_config2_sampled_parity():
 
 
 def test_full_size_config2_fp32_mixed_vs_fp64():
-    """Config 2 in full: 100 steps at 6*64^3; FP32-mixed against the FP64 path,
-    whose every step matches the oracle."""
-    say("case: N=64 100 steps fp64 vs fp32-mixed")
+    """Config 2 in full: 100 steps at 6*64^3; FP32-mixed and FP32 against the FP64
+    path, whose every step matches the oracle."""
+    say("case: N=64 100 steps fp64 vs fp32-mixed and fp32")
     mesh, case, q0 = advection_case(64, seed=W.SEED_ADVECTION + 64)
     vol = W.tet_volumes(mesh.cell_vertices)
     out = {}
-    for prec in (hgks.FP64, hgks.FP32_MIXED):
+    for prec in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32):
         s = make_solver(mesh, q0, precision=prec)
         s.step(100)
         out[prec] = s.get_state()
         s.close()
-    err = rel_l1(out[hgks.FP32_MIXED][0], out[hgks.FP64][0], vol)
-    say("relative L1 fp32-mixed vs fp64 after 100 steps", err)
-    assert np.all(err <= TOL32), err
-    assert out[hgks.FP32_MIXED][1] == pytest.approx(out[hgks.FP64][1], rel=1e-5)
+    for prec in (hgks.FP32_MIXED, hgks.FP32):
+        err = rel_l1(out[prec][0], out[hgks.FP64][0], vol)
+        say(f"relative L1 precision {prec} vs fp64 after 100 steps", err)
+        assert np.all(err <= TOL32), err
+        assert out[prec][1] == pytest.approx(out[hgks.FP64][1], rel=1e-5)
 
 
 # ---------------------------------------------------------------------------
@@ -282,11 +305,11 @@ def test_fp64_shock_tube_coloured_accumulation():
 def test_fp32_mixed_shock_tube_against_fp64():
     """FP32-mixed against FP64 on the tube to t = 0.1 (tau_mode 1): the rounding
     difference stays small next to the scheme's own error at the shock."""
-    say("case: fp32-mixed vs fp64 shock tube nx=48 to t=0.1")
+    say("case: fp32-mixed and fp32 vs fp64 shock tube nx=48 to t=0.1")
     mesh, q0 = _sod(48, 4, 4)
     vol = W.tet_volumes(mesh.cell_vertices)
     out = {}
-    for prec in (hgks.FP64, hgks.FP32_MIXED):
+    for prec in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32):
         s = make_solver(mesh, q0, precision=prec, tau_mode=1)
         t = 0.0
         while t < 0.1 - 1e-14:
@@ -294,10 +317,11 @@ def test_fp32_mixed_shock_tube_against_fp64():
             _, t = s.get_state()
         out[prec] = s.get_state()[0]
         s.close()
-    e = rel_l1(out[hgks.FP32_MIXED], out[hgks.FP64], vol)
-    say("fp32-mixed vs fp64 relative L1", e)
-    assert np.all(np.isfinite(out[hgks.FP32_MIXED]))
-    assert e[0] < 1e-4 and e[4] < 1e-4, e
+    for prec in (hgks.FP32_MIXED, hgks.FP32):
+        e = rel_l1(out[prec], out[hgks.FP64], vol)
+        say(f"precision {prec} vs fp64 relative L1", e)
+        assert np.all(np.isfinite(out[prec]))
+        assert e[0] < 1e-4 and e[4] < 1e-4, e
 
 
 # ---------------------------------------------------------------------------
@@ -325,12 +349,12 @@ def test_fp64_walls_coloured_accumulation():
 
 
 def test_fp32_mixed_walls_shock_tube_against_fp64():
-    say("case: fp32-mixed vs fp64 shock tube with walls nx=32 to t=0.1")
+    say("case: fp32-mixed and fp32 vs fp64 shock tube with walls nx=32 to t=0.1")
     mesh, case = W.sod_box(32, 4, 4, walls=True)
     q0 = case.conservative(mesh)
     vol = W.tet_volumes(mesh.cell_vertices)
     out = {}
-    for prec in (hgks.FP64, hgks.FP32_MIXED):
+    for prec in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32):
         s = make_solver(mesh, q0, precision=prec, tau_mode=1)
         t = 0.0
         while t < 0.1 - 1e-14:
@@ -338,7 +362,8 @@ def test_fp32_mixed_walls_shock_tube_against_fp64():
             t = s.get_time()
         out[prec] = s.get_state()[0]
         s.close()
-    e = rel_l1(out[hgks.FP32_MIXED], out[hgks.FP64], vol)
-    say("fp32-mixed vs fp64 relative L1", e)
-    assert np.all(np.isfinite(out[hgks.FP32_MIXED]))
-    assert e[0] < 1e-4 and e[4] < 1e-4, e
+    for prec in (hgks.FP32_MIXED, hgks.FP32):
+        e = rel_l1(out[prec], out[hgks.FP64], vol)
+        say(f"precision {prec} vs fp64 relative L1", e)
+        assert np.all(np.isfinite(out[prec]))
+        assert e[0] < 1e-4 and e[4] < 1e-4, e

@@ -102,3 +102,16 @@ def test_oracle_sampled_step_equals_full_step():
     q1, dt = om.step(q, 1)
     cells = np.array([0, 7, 333, m.n_cells - 1])
     assert np.array_equal(om.step_sample(q, dt, cells), q1[cells])
+
+
+def test_footprint_by_precision():
+    """Device footprint per precision (host arithmetic only, no device call): the
+    FP32-mixed form stores the reconstruction in FP32 (200 of 400 B a cell), and the
+    FP32 form also the big-stencil pseudo-inverse (576 of 1152 B a cell)."""
+    nc = 6 * 40 ** 3
+    f = {p: hgks.pool_footprint(hgks.params(precision=p), nc) for p in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32)}
+    slack = 4096          # per-array alignment
+    assert abs((f[hgks.FP64] - f[hgks.FP32_MIXED]) - 200 * nc) <= slack
+    assert abs((f[hgks.FP32_MIXED] - f[hgks.FP32]) - 576 * nc) <= slack
+    with pytest.raises(hgks.HGKSError):
+        hgks.pool_footprint(hgks.params(precision=3), nc)
