@@ -358,12 +358,8 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     HIPCHK(c, h2d(D.sten, hm.sten.data(), hm.sten.size() * 4));
     if (prec == HGKS_FP32) {
         // pair rows 2k and 2k+1 of a cell become its quad row k, each value rounded once
-        const size_t n = (size_t)hm.nc;
         hvec<float> p32(hm.pinv0.size());
-        for (size_t k = 0; k < 36; ++k)
-            for (size_t i = 0; i < n; ++i)
-                for (size_t e = 0; e < 4; ++e)
-                    p32[(k * n + i) * 4 + e] = (float)hm.pinv0[((2 * k + e / 2) * n + i) * 2 + e % 2];
+        pinv0_quads_f32(hm, p32.data());
         HIPCHK(c, h2d(D.pinv32, p32.data(), p32.size() * 4));
         HIPCHK(c, hipStreamSynchronize(s));   // p32 is released on return
     } else {

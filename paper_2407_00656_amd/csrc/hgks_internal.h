@@ -107,4 +107,8 @@ hgks_status build_mesh(const hgks_params &prm, int64_t n_nodes, const double *xy
 
 int host_threads();
 
+// The big-stencil pseudo-inverse rounded to FP32 in quad rows: quad row k of cell i
+// holds pair rows 2k and 2k+1, out[(k * nc + i) * 4 + e] (FP32 form; multithreaded).
+void pinv0_quads_f32(const HostMesh &hm, float *out);
+
 }  // namespace hgks

@@ -292,14 +292,16 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
             out[k][t] = dup[t] ? T(0) : inv[k][0] * A[t][0] + inv[k][1] * A[t][1] + inv[k][2] * A[t][2];
 }
 
-// Pseudo-inverse pair rows in LDS: 72 of the big stencil (row r, slots 2s, 2s+1 at
-// pair r*8+s), then 36 of the sub-stencils (row k of sub-stencil m, members 2u,
-// 2u+1 at pair 72+(m*3+k)*3+u).  A workgroup handles WC cells: its threads copy
-// the WC cells' big-stencil rows from HBM (streamed, each value read once) while
-// 4 WC of them form the sub-stencil fits from the centroids, one barrier, then
-// lane (v, c) forms variable v of cell c from LDS.  Five variables x WC cells are
-// spread over whole waves; spare lanes only help with the copy.
-constexpr int WPAIRS0 = 72, WPAIRS = 108;
+// Pseudo-inverse pair rows in LDS (FP64 forms): 72 of the big stencil (row r,
+// slots 2s, 2s+1 at pair r*8+s); once the big contraction has read them, the first
+// 36 take the sub-stencil fits (row k of sub-stencil m, members 2u, 2u+1 at pair
+// (m*3+k)*3+u).  A workgroup handles WC cells: its threads copy the WC cells'
+// big-stencil rows from HBM (streamed, each value read once) while 4 WC of them
+// form the sub-stencil fits from the centroids into registers; one barrier, the big
+// contraction, two barriers around the fits' LDS write, then lane (v, c) finishes
+// variable v of cell c.  Five variables x WC cells are spread over whole waves;
+// spare lanes only help with the copy.
+constexpr int WPAIRS0 = 72;
 
 template <int WC>
 constexpr int weno_threads() { return (5 * WC + 63) / 64 * 64; }
@@ -313,14 +315,15 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     constexpr int NT = weno_threads<WC>();
     constexpr int SPLIT = WENO_TILE / WC;              // workgroups per cell tile
     static_assert(4 * WC <= NT, "one sub-stencil fit per thread");
-    // LDS: 72 big-stencil + 36 sub-stencil FP64 pair rows, or in the FP32 form 36
-    // big-stencil FP32 quad rows + 36 sub-stencil FP32 pair rows (two thirds less)
-    // followed by the cells' stencil ids and geometry (read once per cell there,
-    // not once per variable lane: with the smaller stream the per-lane loads of
-    // those cost more than the extra barrier; in the FP64 forms the reverse holds)
+    // LDS: 72 big-stencil FP64 pair rows, reused for the sub-stencil fits (18.4 KB
+    // at 16 cells: eight workgroups per CU), or in the FP32 form 36 big-stencil
+    // FP32 quad rows + 36 sub-stencil FP32 pair rows followed by the cells' stencil
+    // ids and geometry (read once per cell there, not once per variable lane: with
+    // the smaller stream the per-lane loads of those cost more than the extra
+    // barrier; in the FP64 forms the reverse holds)
     constexpr int ROWS = F32 ? 36 : WPAIRS0;           // streamed rows per cell
     constexpr size_t LDS_BYTES =
-        F32 ? (size_t)(36 * 16 + 36 * 8 + SLOTS * 4 + 7 * 8) * WC : (size_t)WPAIRS * 16 * WC;
+        F32 ? (size_t)(36 * 16 + 36 * 8 + SLOTS * 4 + 7 * 8) * WC : (size_t)WPAIRS0 * 16 * WC;
     __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
     d2(*stage_buf)[WC] = reinterpret_cast<d2(*)[WC]>(smem);
     f4(*big32)[WC] = reinterpret_cast<f4(*)[WC]>(smem);
@@ -374,20 +377,21 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
                 ldg<double>(P.cgeo + (size_t)(threadIdx.x / WC) * nc, min(c0 + threadIdx.x % WC, last) * 8u);
         __syncthreads();
     }
-    // 2. the sub-stencil fits: thread (m, c) for m < 4
-    if (threadIdx.x < 4u * WC) {
+    // 2. the sub-stencil fits: thread (m, c) for m < 4.  The FP32 form stages them
+    // now; the FP64 forms hold them in registers and write them over the first 36
+    // big-stencil rows once the big contraction has read those (LDS for 8 rather
+    // than 5 workgroups per CU)
+    const bool fitter = threadIdx.x < 4u * WC;
+    DT ps[3][6];
+    if (fitter) {
         const uint32_t m = threadIdx.x / WC, cs = threadIdx.x % WC;
-        DT ps[3][6];
         sub_stencil_pinv<WALLS, WC, F32>(P, min(c0 + cs, last), m, sid, sgeo, cs, ps);
+        if constexpr (F32) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                if constexpr (F32)
-                    sub32[(m * 3 + k) * 3 + u][cs] = f2{ps[k][2 * u], ps[k][2 * u + 1]};
-                else
-                    stage_buf[WPAIRS0 + (m * 3 + k) * 3 + u][cs] = d2{ps[k][2 * u], ps[k][2 * u + 1]};
-            }
+                for (int u = 0; u < 3; ++u) sub32[(m * 3 + k) * 3 + u][cs] = f2{ps[k][2 * u], ps[k][2 * u + 1]};
+        }
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -419,10 +423,10 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
         }
     }
     __syncthreads();
-    if (!active) return;
     // 3. a = Pinv0 (Q_k - Q_i) on the big stencil; b^m = Pinv_m (Q_k - Q_i) on sub-stencil m
     DT a[9], b[4][3];
     if constexpr (F32) {
+        if (!active) return;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
             float acc = 0.0f;
@@ -450,17 +454,29 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
                 b[m][k] = acc;
             }
     } else {
+        if (active) {
 #pragma unroll
-        for (int r = 0; r < 9; ++r) {
-            double acc = 0.0;
+            for (int r = 0; r < 9; ++r) {
+                double acc = 0.0;
 #pragma unroll
-            for (int s2 = 0; s2 < SLOTS / 2; ++s2) {
-                const d2 pp = stage_buf[r * 8 + s2][cl];
-                acc = fma(pp.x, d[2 * s2], acc);
-                acc = fma(pp.y, d[2 * s2 + 1], acc);
+                for (int s2 = 0; s2 < SLOTS / 2; ++s2) {
+                    const d2 pp = stage_buf[r * 8 + s2][cl];
+                    acc = fma(pp.x, d[2 * s2], acc);
+                    acc = fma(pp.y, d[2 * s2 + 1], acc);
+                }
+                a[r] = acc;
             }
-            a[r] = acc;
         }
+        __syncthreads();   // every lane has read the big rows
+        if (fitter) {
+            const uint32_t m = threadIdx.x / WC, cs = threadIdx.x % WC;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int u = 0; u < 3; ++u) stage_buf[(m * 3 + k) * 3 + u][cs] = d2{ps[k][2 * u], ps[k][2 * u + 1]};
+        }
+        __syncthreads();
+        if (!active) return;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -468,7 +484,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
                 double acc = 0.0;
 #pragma unroll
                 for (int t2 = 0; t2 < 3; ++t2) {
-                    const d2 pp = stage_buf[WPAIRS0 + (m * 3 + k) * 3 + t2][cl];
+                    const d2 pp = stage_buf[(m * 3 + k) * 3 + t2][cl];
                     acc = fma(pp.x, d[sub_slot(m, 2 * t2)], acc);
                     acc = fma(pp.y, d[sub_slot(m, 2 * t2 + 1)], acc);
                 }

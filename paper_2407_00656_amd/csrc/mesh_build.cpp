@@ -51,6 +51,17 @@ static void parallel_for(int64_t n, F &&f) {
     for (auto &x : th) x.join();
 }
 
+void pinv0_quads_f32(const HostMesh &hm, float *out) {
+    const int64_t n = hm.nc;
+    const double *p = hm.pinv0.data();
+    parallel_for(n, [&](int64_t b, int64_t e) {
+        for (int64_t k = 0; k < 36; ++k)
+            for (int64_t i = b; i < e; ++i)
+                for (int64_t q = 0; q < 4; ++q)
+                    out[(k * n + i) * 4 + q] = (float)p[((2 * k + q / 2) * n + i) * 2 + q % 2];
+    });
+}
+
 namespace {
 
 struct V3 {
