@@ -45,8 +45,8 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
 def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool = False) -> float:
     if kernel == "weno":
         return nc * (64 + 40 + (576 if pinv32 else 1152) + 56 + 24 + 16 + (200 if mixed else 400))
-    if kernel == "flux":
-        return nf * 264 + nc * ((200 + 40) if mixed else 400)
+    if kernel == "flux":   # 264 B a face in the first stage, 224 in the second (F not stored)
+        return nf * 244 + nc * ((200 + 40) if mixed else 400)
     if kernel == "update":
         return nc * (16 + 160 + 16 + 100)
     return 0.0

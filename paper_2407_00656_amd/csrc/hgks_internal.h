@@ -30,7 +30,8 @@
 //                                y = x - centroid, stored as five coefficient pairs
 //                                (k, k+1) per variable (FP32 pairs in the mixed form,
 //                                where c0 holds the deviation from the cell mean)
-//   FF     double [10][nf]       per face S * sum_G w_G (F, dF/dt)
+//   FF     double [10][nf]       per face S * sum_G w_G (F, dF/dt); with tau = 0 the
+//                                second stage stores only the dF/dt rows
 #pragma once
 
 #include <cstdint>

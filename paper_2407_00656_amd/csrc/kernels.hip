@@ -8,7 +8,8 @@
 //   k_flux_t0  gas-kinetic flux at tau = 0 (Sec. 2.1 Eq. flux, Sec. 2.2 time
 //              fit, Sec. 5.1): one lane per face loads both reconstruction
 //              records once, evaluates them at the three Gauss points and writes
-//              S * sum_G w_G (F, dF).
+//              S * sum_G w_G (F, dF) (dF only in the second stage, whose L(Q*)
+//              the S2O4 update does not use).
 //   k_flux     the same for tau > 0: one wave per Gauss point, the three
 //              contributions summed through LDS.
 //   k_update   S2O4 stage update (Sec. 2.2).  Each cell gathers its four face
@@ -1158,9 +1159,12 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
 // not the arithmetic, bound this kernel: loading every record byte once per face
 // rather than once per Gauss point is what counts), then evaluates the three
 // Gauss-point fluxes and writes S * sum_G w_G (F, dF).  No LDS and no barriers.
-template <bool MIXED, bool COLOURED, bool WALLS>
+// DF_ONLY (second stage, per-face buffer): only dF is stored, since the S2O4 update
+// of that stage does not use L(Q*).
+template <bool MIXED, bool COLOURED, bool WALLS, bool DF_ONLY = false>
 __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restrict__ probs,
                                                        const Tile *__restrict__ tiles, int stage) {
+    static_assert(!(DF_ONLY && COLOURED), "the coloured mode accumulates both");
     using T = typename std::conditional<MIXED, float, double>::type;
     // tiles in reverse order: the reconstruction records written last by the WENO
     // pass are the likeliest still to sit in the last-level cache
@@ -1211,13 +1215,14 @@ __global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restric
             double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
             stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - out[k]);
             if (!wall) stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + out[k]);
-        } else {
+        } else if (!DF_ONLY || k >= 5) {
             stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
         }
     }
     if constexpr (!COLOURED) {
         // the fix-up pass has work: a non-finite face (flag cleared by the stage update)
-        const uint64_t bad = __ballot(!(out[0] - out[0] == 0.0));
+        const double chk = DF_ONLY ? out[5] : out[0];
+        const uint64_t bad = __ballot(!(chk - chk == 0.0));
         if (bad != 0 && threadIdx.x == 0) P.flag[1] = 1;
     }
 }
@@ -1246,7 +1251,8 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) 
         const uint32_t f = tl.begin + threadIdx.x;
         if (f >= (uint32_t)tl.end) continue;
         const uint32_t nf = (uint32_t)P.nf;
-        const double f0 = ldg<double>(P.FF, f * 8u);
+        // the first row of F, or in the second stage (F not stored) of dF
+        const double f0 = ldg<double>(P.FF + (stage == 1 ? 0 : (size_t)5 * nf), f * 8u);
         if (f0 - f0 == 0.0) continue;            // finite
         const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
         const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
@@ -1672,13 +1678,14 @@ void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntile
     if (ntiles <= 0) return;
     if (tau0) {
         dim3 g(ntiles), b(FACE_TILE);
-#define HGKS_FLUX0(M, CO)                                                                                   \
+#define HGKS_FLUX0(M, CO, D)                                                                                \
     do {                                                                                                    \
-        if (walls) hipLaunchKernelGGL((k_flux_t0<M, CO, true>), g, b, 0, s, probs, tiles, stage);           \
-        else hipLaunchKernelGGL((k_flux_t0<M, CO, false>), g, b, 0, s, probs, tiles, stage);                \
+        if (walls) hipLaunchKernelGGL((k_flux_t0<M, CO, true, D>), g, b, 0, s, probs, tiles, stage);        \
+        else hipLaunchKernelGGL((k_flux_t0<M, CO, false, D>), g, b, 0, s, probs, tiles, stage);             \
     } while (0)
-        if (coloured) { if (mixed) HGKS_FLUX0(true, true); else HGKS_FLUX0(false, true); }
-        else { if (mixed) HGKS_FLUX0(true, false); else HGKS_FLUX0(false, false); }
+        if (coloured) { if (mixed) HGKS_FLUX0(true, true, false); else HGKS_FLUX0(false, true, false); }
+        else if (stage == 1) { if (mixed) HGKS_FLUX0(true, false, false); else HGKS_FLUX0(false, false, false); }
+        else { if (mixed) HGKS_FLUX0(true, false, true); else HGKS_FLUX0(false, false, true); }
 #undef HGKS_FLUX0
         if (!coloured) {
             const dim3 gf(std::min(ntiles, 8 * device_cus()));
