@@ -1160,9 +1160,12 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
 // rather than once per Gauss point is what counts), then evaluates the three
 // Gauss-point fluxes and writes S * sum_G w_G (F, dF).  No LDS and no barriers.
 // DF_ONLY (second stage, per-face buffer): only dF is stored, since the S2O4 update
-// of that stage does not use L(Q*).
+// of that stage does not use L(Q*).  The wall variants are held to two waves per
+// SIMD: left alone the FP64 one takes a few accumulation registers beyond 256 and
+// runs one wave (a few bytes of scratch per lane cost less than that).
 template <bool MIXED, bool COLOURED, bool WALLS, bool DF_ONLY = false>
-__global__ __launch_bounds__(FACE_TILE) void k_flux_t0(const ProbDesc *__restrict__ probs,
+__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(WALLS && !COLOURED ? 2 : 1))) void
+k_flux_t0(const ProbDesc *__restrict__ probs,
                                                        const Tile *__restrict__ tiles, int stage) {
     static_assert(!(DF_ONLY && COLOURED), "the coloured mode accumulates both");
     using T = typename std::conditional<MIXED, float, double>::type;
