@@ -60,11 +60,13 @@ typedef enum {
                                  FP64) */,
     HGKS_FP32 = 2             /* the FP32-mixed form with the big-stencil pseudo-inverse
                                  stored in FP32 (each coefficient rounded once at
-                                 mesh upload, half its bytes) and its contraction, the
-                                 sub-stencil fits' contraction and the stencil
-                                 differences in FP32: the storage and arithmetic side of
-                                 the single-precision build of Sec. 5.1 (memory and
-                                 speed against FP64) where it carries the bytes; the
+                                 mesh upload, half its bytes) and contracted in FP32;
+                                 the sub-stencil fits are formed in FP32 from FP64
+                                 centroid offsets and contracted in FP32, and the
+                                 stencil differences are formed in FP64 and rounded
+                                 once.  This is the storage and arithmetic side of the
+                                 single-precision build of Sec. 5.1 (memory and speed
+                                 against FP64), taken where it carries the bytes; the
                                  state, geometry, accumulation and update stay FP64 */
 } hgks_precision;
 
