@@ -276,6 +276,37 @@ def test_full_size_config2_fp32_mixed_vs_fp64():
         assert out[prec][1] == pytest.approx(out[hgks.FP64][1], rel=1e-5)
 
 
+@pytest.mark.timeout(900)
+def test_full_size_shock_tube_walls_sampled_parity():
+    """The 128^3 shock tube with walls in full (12.6 M tets, tau_mode 1, the shock-tube
+    driver's configuration): one GPU step against the oracle's step of 48 sampled
+    cells (at both walls, across the diaphragm and at random), plus the CFL dt.  The
+    oracle's mesh of this size takes about a minute and 55 GB of host memory."""
+    say("case: fp64 shock tube 128^3 with walls, tau_mode=1, sampled parity (12.6 M cells)")
+    mesh, case = W.sod_box(128, 128, 128, walls=True)
+    q0 = case.conservative(mesh)
+    s = make_solver(mesh, q0, tau_mode=1)
+    dt_gpu = s.step(1, want_dt=True)
+    q_gpu, _ = s.get_state()
+    s.close()
+    say("gpu step done; building the oracle mesh")
+    om = O.Mesh.from_workload(mesh)
+    dt_orc = om.cfl_dt(q0)
+    assert abs(dt_gpu - dt_orc) <= 1e-14 * dt_orc, (dt_gpu, dt_orc)
+    x = mesh.cell_vertices[:, :, 0].mean(axis=1)
+    rng = np.random.default_rng(128)
+
+    def pick(sel, k):
+        return rng.choice(np.flatnonzero(sel), k, replace=False)
+
+    cells = np.concatenate([pick(np.abs(x - 0.5) < 0.01, 16), pick(x < 0.01, 8), pick(x > 0.99, 8),
+                            rng.choice(mesh.n_cells, 16, replace=False)])
+    ref = om.step_sample(q0, dt_orc, cells, params=oracle_params(tau_mode=1))
+    e = scaled_err(q_gpu[cells], ref)
+    say("worst scaled error (sample)", e)
+    assert np.all(e <= TOL64), e
+
+
 # ---------------------------------------------------------------------------
 # Shock tube: discontinuous data, the positivity fallback at Gauss points
 # ---------------------------------------------------------------------------
