@@ -5,7 +5,7 @@ jittered Kuhn tetrahedra (periodic [0,2]^3, rho = 1 + 0.2 sin(pi(x+y+z)),
 U = V = W = 1, p = 1, CFL 0.3, tau = 0), inputs already resident in HBM.
 A step is one full two-stage S2O4 step (CFL dt, two WENO reconstructions,
 two face-flux passes, two stage updates).  Reports cell-updates/s for the FP64
-path (the headline value) and for the FP32-mixed form, the roofline position
+path (the headline value) and for the FP32-mixed and FP32 forms, the roofline position
 of the dominant kernel (per-kernel HIP events inside the timed region), and the
 CPU oracle timed on this host.
 
@@ -37,9 +37,11 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
 #   weno   per cell: 16 stencil ids (64) + own state (40) + big-stencil pseudo-inverse
 #          9x16 (1152) + 1/h and second moments (56) + own centroid (24) + slot image
 #          codes (16) + reconstruction written (400)                           = 1752
-#          (the sub-stencil fits are formed on the device from the centroids)
+#          (the sub-stencil fits are formed on the device from the centroids;
+#          FP32-mixed writes 200, and the FP32 form also reads a 576 B pseudo-inverse)
 #   flux   per face: cells (8) + normal, area, Gauss offsets (176) + flux written (80)
-#          = 264, plus per cell the reconstruction read once (400)
+#          = 264 in the first stage and 224 in the second (dF only), plus per cell
+#          the reconstruction read once (400)
 #   update per cell: face ids (16) + its faces' fluxes (2 faces' worth, 160) + 1/|V|
 #          and h (16) + state traffic (stage 1: 3 x 40, stage 2: 2 x 40)       ~ 292
 def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool = False) -> float:

@@ -1,0 +1,32 @@
+"""Host-side checks of bench.py's contract (no device work)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("mixed,pinv32,per_cell", [(False, False, 1752), (True, False, 1552), (True, True, 976)])
+def test_weno_algorithmic_bytes(mixed, pinv32, per_cell):
+    """Per-cell WENO bytes of the three precision forms: ids 64, state 40, pseudo-inverse
+    1152 (576 in FP32), geometry 56, centroid 24, image codes 16, record 400 (200)."""
+    assert bench.algorithmic_bytes("weno", 1000, 2000, mixed, pinv32) == 1000 * per_cell
+
+
+def test_flux_and_update_algorithmic_bytes():
+    nc, nf = 1000, 2000
+    # the mean of 264 (first stage) and 224 (second stage, dF only) per face
+    assert bench.algorithmic_bytes("flux", nc, nf, False) == nf * 244 + nc * 400
+    assert bench.algorithmic_bytes("update", nc, nf, False) == nc * 292
