@@ -227,9 +227,9 @@ __device__ __forceinline__ void weno_combine(const ProbDesc &P, uint32_t i, uint
 // inverted through its adjugate.  out[k][t]: row k (d/dxi_k), member t.  The rows
 // are formed in FP64 (differences of centroids); T is the precision of the normal
 // matrix, its inverse and the result (float in the FP32 form).
-// With LDSID the stencil ids and 1/h come from the workgroup's LDS copy (sid, sgeo,
-// column cs) rather than from global memory.
-template <bool WALLS, int WC, bool LDSID, class T>
+// With LDSID the stencil ids, and with LDSGEO 1/h, come from the workgroup's LDS
+// copy (sid, sgeo, column cs) rather than from global memory.
+template <bool WALLS, int WC, bool LDSID, class T, bool LDSGEO = LDSID>
 __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, uint32_t m, const int32_t (*sid)[WC],
                                                  const double (*sgeo)[WC], uint32_t cs, T out[3][6]) {
     const size_t nc = (size_t)P.nc;
@@ -240,7 +240,7 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
                                (uint64_t)SUBFIRST[2][0] << 24 | (uint64_t)SUBFIRST[2][1] << 28 |
                                (uint64_t)SUBFIRST[2][2] << 32 | (uint64_t)SUBFIRST[3][0] << 36 |
                                (uint64_t)SUBFIRST[3][1] << 40 | (uint64_t)SUBFIRST[3][2] << 44;
-    const double ih = LDSID ? sgeo[0][cs] : P.cgeo[i];
+    const double ih = LDSGEO ? sgeo[0][cs] : P.cgeo[i];
     const double ci[3] = {P.cen[i], P.cen[nc + i], P.cen[2 * nc + i]};
     const uint32_t w0 = P.sshift[i], w1 = P.sshift[nc + i], w2 = P.sshift[2 * nc + i], w3 = P.sshift[3 * nc + i];
     T A[6][3];
@@ -316,21 +316,22 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     constexpr int NT = weno_threads<WC>();
     constexpr int SPLIT = WENO_TILE / WC;              // workgroups per cell tile
     static_assert(4 * WC <= NT, "one sub-stencil fit per thread");
-    // LDS: 72 big-stencil FP64 pair rows, reused for the sub-stencil fits (18.4 KB
-    // at 16 cells: eight workgroups per CU), or in the FP32 form 36 big-stencil
-    // FP32 quad rows + 36 sub-stencil FP32 pair rows followed by the cells' stencil
-    // ids and geometry (read once per cell there, not once per variable lane: with
-    // the smaller stream the per-lane loads of those cost more than the extra
-    // barrier; in the FP64 forms the reverse holds)
+    // LDS: 72 big-stencil FP64 pair rows, reused for the sub-stencil fits, then the
+    // cells' stencil ids (19.5 KB at 16 cells: eight workgroups per CU); or in the
+    // FP32 form 36 big-stencil FP32 quad rows + 36 sub-stencil FP32 pair rows, then
+    // the cells' geometry and stencil ids.  Ids (and the FP32 form's geometry) are
+    // read once per cell rather than once per variable lane, at the cost of one
+    // barrier; the FP64 forms keep per-lane geometry loads, which start before the
+    // barrier and need no LDS.
     constexpr int ROWS = F32 ? 36 : WPAIRS0;           // streamed rows per cell
     constexpr size_t LDS_BYTES =
-        F32 ? (size_t)(36 * 16 + 36 * 8 + SLOTS * 4 + 7 * 8) * WC : (size_t)WPAIRS0 * 16 * WC;
+        F32 ? (size_t)(36 * 16 + 36 * 8 + SLOTS * 4 + 7 * 8) * WC : (size_t)(WPAIRS0 * 16 + SLOTS * 4) * WC;
     __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
     d2(*stage_buf)[WC] = reinterpret_cast<d2(*)[WC]>(smem);
     f4(*big32)[WC] = reinterpret_cast<f4(*)[WC]>(smem);
     f2(*sub32)[WC] = reinterpret_cast<f2(*)[WC]>(smem + 36 * 16 * WC);
     double(*sgeo)[WC] = reinterpret_cast<double(*)[WC]>(smem + (36 * 16 + 36 * 8) * WC);   // FP32 form only
-    int32_t(*sid)[WC] = reinterpret_cast<int32_t(*)[WC]>(smem + (36 * 16 + 36 * 8 + 7 * 8) * WC);
+    int32_t(*sid)[WC] = reinterpret_cast<int32_t(*)[WC]>(smem + (F32 ? 36 * 16 + 36 * 8 + 7 * 8 : WPAIRS0 * 16) * WC);
     // Workgroups go to the eight XCDs round-robin by id, and the tile table is laid
     // out so that XCD x owns a contiguous run of tiles when each tile has one
     // workgroup.  A tile here has SPLIT workgroups, so renumber: XCD x takes a
@@ -369,11 +370,11 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
                 reg[k] = ldg_stream(p0 + (size_t)row * nc, c * 16u);
         }
     }
-    if constexpr (F32) {   // the cells' stencil ids and geometry, once per cell
+    {   // the cells' stencil ids (and in the FP32 form geometry), once per cell
 #pragma unroll
         for (uint32_t e = threadIdx.x; e < (uint32_t)(SLOTS * WC); e += NT)
             sid[e / WC][e % WC] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
-        if (threadIdx.x < 7u * WC)
+        if (F32 && threadIdx.x < 7u * WC)
             sgeo[threadIdx.x / WC][threadIdx.x % WC] =
                 ldg<double>(P.cgeo + (size_t)(threadIdx.x / WC) * nc, min(c0 + threadIdx.x % WC, last) * 8u);
         __syncthreads();
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     DT ps[3][6];
     if (fitter) {
         const uint32_t m = threadIdx.x / WC, cs = threadIdx.x % WC;
-        sub_stencil_pinv<WALLS, WC, F32>(P, min(c0 + cs, last), m, sid, sgeo, cs, ps);
+        sub_stencil_pinv<WALLS, WC, true, DT, F32>(P, min(c0 + cs, last), m, sid, sgeo, cs, ps);
         if constexpr (F32) {
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
         for (int q = 0; q < 7; ++q) geo[q] = F32 ? sgeo[q][cl] : ldg<double>(P.cgeo + (size_t)q * nc, i * 8u);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-            const uint32_t j = F32 ? (uint32_t)sid[s][cl] : (uint32_t)ldg<int32_t>(P.sten + (size_t)s * nc, i * 4u);
+            const uint32_t j = (uint32_t)sid[s][cl];
             d[s] = (DT)(ldg<double>(Qv, j * 8u) - qi);   // the difference in FP64, then rounded once
         }
     }
