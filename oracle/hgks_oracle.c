@@ -933,10 +933,17 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
 /*
  * Positivity fallback (not in the paper, which has no limiter): at a Gauss point
  * where the reconstructed state of either side has rho <= 0 or p <= 0, the point
- * is evaluated at first order: both sides' gradients are zero and each
- * non-physical side takes its cell average.  It never acts in smooth flow; at a
- * strong discontinuity (the shock tube) the quadratic reconstruction would
- * otherwise hand the flux a state with negative pressure on the first step.
+ * takes the first-order gas-kinetic flux, the flux of piecewise-constant data:
+ * no slopes on either side, and each non-physical side's value replaced by its
+ * cell average (a physical side keeps its point value).  Both slopes go because
+ * in Eq. (flux) they do not act separately: the equilibrium slope is formed from
+ * both sides, dQ0 = (dQ_l + dQ_r)/2, and the time slopes follow from the spatial
+ * ones through the compatibility condition, so once one side's gradient is
+ * unusable the equilibrium part has no consistent slope left; dropping only that
+ * side would leave the equilibrium half of the other side's slope, which belongs
+ * to no reconstruction.  It never acts in smooth flow; at a strong discontinuity
+ * (the shock tube) the quadratic reconstruction would otherwise hand the flux a
+ * state with negative pressure on the first step.
  */
 static int physical_point(const orc_params *p, const double *v) {
     const double rho = v[0];
@@ -1125,6 +1132,65 @@ int orc_reconstruct(const orc_mesh *m, const orc_params *p, const double *Q, int
     weno_eval(m, p, Q, i, &w, x, val, g);
     memcpy(grad, g, sizeof(g));
     return ORC_OK;
+}
+
+/* S * sum_G w_G (F, dF) of face f for the state Q (WENO of both cells formed here). */
+int orc_face_flux(const orc_mesh *m, const orc_params *p, const double *Q, int64_t f, double dt, double *out) {
+    if (f < 0 || f >= m->nf) return ORC_E_ARG;
+    orc_weno *W = malloc(sizeof(orc_weno) * m->nc);
+    const int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+    int rc = weno_cell(m, p, Q, l, &W[l]);
+    if (!rc && r >= 0) rc = weno_cell(m, p, Q, r, &W[r]);
+    if (!rc) rc = face_flux(m, p, Q, W, f, dt, out);
+    free(W);
+    return rc;
+}
+
+/*
+ * Census of the positivity fallback for the state Q: out[0] Gauss points where it
+ * acts, out[1] of those the points with exactly one non-physical side, out[2] of
+ * those the points where the physical side's reconstructed gradient is nonzero
+ * (some component above 1e-6 of that side's value scale).
+ */
+int orc_fallback_census(const orc_mesh *m, const orc_params *p, const double *Q, int64_t *out) {
+    orc_weno *W = malloc(sizeof(orc_weno) * m->nc);
+    int rc = ORC_OK;
+    for (int64_t i = 0; i < m->nc && !rc; ++i) rc = weno_cell(m, p, Q, i, &W[i]);
+    int64_t all = 0, one = 0, one_grad = 0;
+    for (int64_t f = 0; f < m->nf && !rc; ++f) {
+        const int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+        const double *n = m->fnrm[f];
+        for (int g = 0; g < 3; ++g) {
+            double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3];
+            for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
+            weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
+            if (r >= 0) {
+                weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+            } else {
+                for (int q = 0; q < 5; ++q) {
+                    const double gn = gl[q][0] * n[0] + gl[q][1] * n[1] + gl[q][2] * n[2];
+                    vr[q] = vl[q];
+                    for (int a = 0; a < 3; ++a) gr[q][a] = gl[q][a] - 2.0 * gn * n[a];
+                }
+            }
+            const int okl = physical_point(p, vl), okr = physical_point(p, vr);
+            if (okl && okr) continue;
+            ++all;
+            if (okl == okr) continue;
+            ++one;
+            const double *v = okl ? vl : vr;
+            double (*gg)[3] = okl ? gl : gr;
+            double vs = 0.0, gs = 0.0;
+            for (int q = 0; q < 5; ++q) {
+                if (fabs(v[q]) > vs) vs = fabs(v[q]);
+                for (int a = 0; a < 3; ++a) if (fabs(gg[q][a]) > gs) gs = fabs(gg[q][a]);
+            }
+            if (gs > 1e-6 * vs) ++one_grad;
+        }
+    }
+    free(W);
+    out[0] = all; out[1] = one; out[2] = one_grad;
+    return rc;
 }
 
 /* mean over cell i of the scaled monomials, as used by the least-squares rows */

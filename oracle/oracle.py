@@ -50,46 +50,62 @@ def default_params(**kw) -> Params:
 _lib = None
 
 
+def _configure(L):
+    """Declares the argument and return types of the oracle's C entry points."""
+    L.orc_mesh_new.restype = C.c_void_p
+    L.orc_mesh_new.argtypes = [C.c_int64, _dp, C.c_int64, _i64p, _dp, C.c_char_p, C.c_int]
+    L.orc_mesh_free.argtypes = [C.c_void_p]
+    L.orc_mesh_nfaces.restype = C.c_int64
+    L.orc_mesh_nfaces.argtypes = [C.c_void_p]
+    L.orc_mesh_cells.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_mesh_faces.argtypes = [C.c_void_p, _i64p, _dp, _dp, _dp, _dp]
+    L.orc_mesh_stencil.restype = C.c_int
+    L.orc_mesh_stencil.argtypes = [C.c_void_p, C.c_int64, _i64p, _dp, _ip, _i64p]
+    L.orc_mesh_neighbors.argtypes = [C.c_void_p, _i64p]
+    L.orc_gks_flux.restype = C.c_int
+    L.orc_gks_flux.argtypes = [C.POINTER(Params), _dp, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp]
+    L.orc_rhs.restype = C.c_int
+    L.orc_rhs.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_double, _dp, _dp]
+    L.orc_cfl_dt.restype = C.c_double
+    L.orc_cfl_dt.argtypes = [C.c_void_p, C.POINTER(Params), _dp]
+    L.orc_s2o4_stage1.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, _dp]
+    L.orc_s2o4_stage2.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, _dp]
+    L.orc_step.restype = C.c_int
+    L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int, C.c_double, _dp]
+    L.orc_moments_1d.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]
+    L.orc_slope.restype = C.c_int
+    L.orc_slope.argtypes = [C.c_double] * 5 + [_dp, _dp]
+    L.orc_collision.argtypes = [C.POINTER(Params), _dp, _dp, _dp]
+    L.orc_weno_cell.restype = C.c_int
+    L.orc_weno_cell.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int64, _dp, _dp, _dp, _dp]
+    L.orc_reconstruct.restype = C.c_int
+    L.orc_reconstruct.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int64, _dp, _dp, _dp]
+    L.orc_cell_monomial_means.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_double, _dp]
+    L.orc_face_flux.restype = C.c_int
+    L.orc_face_flux.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int64, C.c_double, _dp]
+    L.orc_fallback_census.restype = C.c_int
+    L.orc_fallback_census.argtypes = [C.c_void_p, C.POINTER(Params), _dp, _i64p]
+    L.orc_threads.restype = C.c_int
+    L.orc_step_sample.restype = C.c_int
+    L.orc_step_sample.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_double, C.c_int64, _i64p, _dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
-        L = C.CDLL(LIB)
-        L.orc_mesh_new.restype = C.c_void_p
-        L.orc_mesh_new.argtypes = [C.c_int64, _dp, C.c_int64, _i64p, _dp, C.c_char_p, C.c_int]
-        L.orc_mesh_free.argtypes = [C.c_void_p]
-        L.orc_mesh_nfaces.restype = C.c_int64
-        L.orc_mesh_nfaces.argtypes = [C.c_void_p]
-        L.orc_mesh_cells.argtypes = [C.c_void_p, _dp, _dp, _dp]
-        L.orc_mesh_faces.argtypes = [C.c_void_p, _i64p, _dp, _dp, _dp, _dp]
-        L.orc_mesh_stencil.restype = C.c_int
-        L.orc_mesh_stencil.argtypes = [C.c_void_p, C.c_int64, _i64p, _dp, _ip, _i64p]
-        L.orc_mesh_neighbors.argtypes = [C.c_void_p, _i64p]
-        L.orc_gks_flux.restype = C.c_int
-        L.orc_gks_flux.argtypes = [C.POINTER(Params), _dp, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp]
-        L.orc_rhs.restype = C.c_int
-        L.orc_rhs.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_double, _dp, _dp]
-        L.orc_cfl_dt.restype = C.c_double
-        L.orc_cfl_dt.argtypes = [C.c_void_p, C.POINTER(Params), _dp]
-        L.orc_s2o4_stage1.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, _dp]
-        L.orc_s2o4_stage2.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, _dp]
-        L.orc_step.restype = C.c_int
-        L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int, C.c_double, _dp]
-        L.orc_moments_1d.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]
-        L.orc_slope.restype = C.c_int
-        L.orc_slope.argtypes = [C.c_double] * 5 + [_dp, _dp]
-        L.orc_collision.argtypes = [C.POINTER(Params), _dp, _dp, _dp]
-        L.orc_weno_cell.restype = C.c_int
-        L.orc_weno_cell.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int64, _dp, _dp, _dp, _dp]
-        L.orc_reconstruct.restype = C.c_int
-        L.orc_reconstruct.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_int64, _dp, _dp, _dp]
-        L.orc_cell_monomial_means.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_double, _dp]
-        L.orc_threads.restype = C.c_int
-        L.orc_step_sample.restype = C.c_int
-        L.orc_step_sample.argtypes = [C.c_void_p, C.POINTER(Params), _dp, C.c_double, C.c_int64, _i64p, _dp]
-        _lib = L
+        _lib = _configure(C.CDLL(LIB))
     return _lib
+
+
+def build_variant(src: str, out: str):
+    """Compiles a variant of the oracle source (the tests plant mistakes in copies
+    to show that the pins catch them) with the oracle's own flags and loads it."""
+    cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", src, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _configure(C.CDLL(out))
 
 
 def _d(a):
@@ -201,6 +217,27 @@ class Mesh:
         if rc:
             raise OracleError(f"orc_step_sample failed ({rc})")
         return out
+
+    def face_flux(self, q, f, dt, params=None):
+        """S * sum_G w_G (F, dF/dt) of face f, 10 values (global frame)."""
+        p = params or default_params()
+        q = _f64(q, (self.nc, 5))
+        out = np.empty(10)
+        rc = lib().orc_face_flux(self._h, C.byref(p), _d(q), int(f), float(dt), _d(out))
+        if rc:
+            raise OracleError(f"orc_face_flux failed ({rc})")
+        return out
+
+    def fallback_census(self, q, params=None):
+        """Gauss points where the positivity fallback acts: (all, one-sided, one-sided
+        with a nonzero gradient on the physical side)."""
+        p = params or default_params()
+        q = _f64(q, (self.nc, 5))
+        out = np.zeros(3, dtype=np.int64)
+        rc = lib().orc_fallback_census(self._h, C.byref(p), _d(q), out.ctypes.data_as(_i64p))
+        if rc:
+            raise OracleError(f"orc_fallback_census failed ({rc})")
+        return tuple(int(x) for x in out)
 
     def weno_cell(self, q, i, params=None):
         p = params or default_params()
