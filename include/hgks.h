@@ -174,6 +174,8 @@ hgks_status hgks_profile_read(hgks_ctx *ctx, int kernel_id, double *ms_total, in
 hgks_status hgks_profile_reset(hgks_ctx *ctx);
 
 const char *hgks_last_error(const hgks_ctx *ctx);
+/* Frees the context; a context still in a pool is first removed from it (after the
+ * pool's queued steps finish). */
 void hgks_destroy(hgks_ctx *ctx);
 
 /*
@@ -207,8 +209,9 @@ hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hg
  * periodic mesh, wall faces add 8 + 176 + 80 bytes each).  HGKS_E_INVALID_ARG for
  * parameters hgks_create would reject, n_cells <= 0 or nodes_per_cell != 4. */
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int nodes_per_cell, size_t *bytes);
-/* Adds a context (mesh uploaded, state initialised); returns its slot id.
- * Errors: STATE, INVALID_ARG (other device), OOM (budget exceeded). */
+/* Adds a context (mesh uploaded, state initialised); returns its slot id.  A context
+ * belongs to at most one pool at a time.
+ * Errors: STATE, INVALID_ARG (other device, already in a pool), OOM (budget exceeded). */
 hgks_status hgks_pool_add(hgks_pool *pool, hgks_ctx *ctx, int *slot);
 /* Advances the listed slots by nsteps S2O4 steps each (CFL dt per slot). */
 hgks_status hgks_pool_step(hgks_pool *pool, const int *slots, int n, int32_t nsteps);

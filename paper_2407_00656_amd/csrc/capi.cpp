@@ -101,8 +101,11 @@ struct hgks_ctx {
     double prof_ms[4] = {0, 0, 0, 0};
     int64_t prof_n[4] = {0, 0, 0, 0};
     int pool_refs = 0;
+    hgks_pool *pool = nullptr;            // the pool holding this context (at most one)
     hipStream_t pool_stream = nullptr;    // stream of the pool holding this context
 };
+
+void pool_detach(hgks_pool *p, hgks_ctx *c);
 
 namespace {
 
@@ -514,6 +517,9 @@ const char *hgks_last_error(const hgks_ctx *c) { return c ? c->err.c_str() : "nu
 
 void hgks_destroy(hgks_ctx *c) {
     if (!c) return;
+    // A pooled context leaves its pool first (which waits for the pool's queued
+    // steps), so the pool never launches on memory freed here.
+    if (c->pool) pool_detach(c->pool, c);
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     collect_profile(c);
@@ -583,38 +589,65 @@ size_t footprint_of(const hgks_params &p, int64_t nc) {
     return L.total;
 }
 
-hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
-    std::vector<int> key(slots, slots + n);
-    if (key == P->last_key && P->tab) return HGKS_OK;
-    // group contexts by kernel variant; FP64 first, then FP32-mixed, then FP32
+// The launch tables of a batch, built on the host: problem descriptors, cell and
+// face tiles grouped by kernel variant (FP64 first, then FP32-mixed, then FP32).
+struct Plan {
+    std::vector<ProbDesc> probs;
+    std::vector<Tile> ct, ft;
+    std::vector<hgks_pool::Group> groups;
+    size_t bytes() const {
+        return up(probs.size() * sizeof(ProbDesc)) + up(ct.size() * sizeof(Tile)) + up(ft.size() * sizeof(Tile));
+    }
+};
+
+Plan make_plan(const hgks_pool *P, const std::vector<int> &key) {
+    Plan pl;
     std::vector<int> order(key);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         auto ka = std::make_pair(P->slot[a]->prm.precision, P->slot[a]->prm.tau_mode);
         auto kb = std::make_pair(P->slot[b]->prm.precision, P->slot[b]->prm.tau_mode);
         return ka < kb;
     });
-    std::vector<ProbDesc> probs;
-    std::vector<Tile> ct, ft;
-    P->groups.clear();
     for (size_t k = 0; k < order.size(); ++k) {
         hgks_ctx *c = P->slot[order[k]];
         const int prec = c->prm.precision;
         const bool tau0 = c->prm.tau_mode == 0;
-        if (P->groups.empty() || P->groups.back().prec != prec || P->groups.back().tau0 != tau0)
-            P->groups.push_back({prec, tau0, (int)ct.size(), (int)ct.size(), (int)ft.size(), (int)ft.size(), false});
-        P->groups.back().walls = P->groups.back().walls || c->walls;
-        const int pid = (int)probs.size();
-        probs.push_back(c->desc);
-        for (Tile t : c->h_ctiles) { t.prob = pid; ct.push_back(t); }
-        for (Tile t : c->h_ftiles) { t.prob = pid; ft.push_back(t); }
-        P->groups.back().c1 = (int)ct.size();
-        P->groups.back().f1 = (int)ft.size();
+        if (pl.groups.empty() || pl.groups.back().prec != prec || pl.groups.back().tau0 != tau0)
+            pl.groups.push_back({prec, tau0, (int)pl.ct.size(), (int)pl.ct.size(), (int)pl.ft.size(),
+                                 (int)pl.ft.size(), false});
+        pl.groups.back().walls = pl.groups.back().walls || c->walls;
+        const int pid = (int)pl.probs.size();
+        pl.probs.push_back(c->desc);
+        for (Tile t : c->h_ctiles) { t.prob = pid; pl.ct.push_back(t); }
+        for (Tile t : c->h_ftiles) { t.prob = pid; pl.ft.push_back(t); }
+        pl.groups.back().c1 = (int)pl.ct.size();
+        pl.groups.back().f1 = (int)pl.ft.size();
     }
-    for (auto &g : P->groups) {
-        xcd_order(ct, g.c0, g.c1);
-        xcd_order(ft, g.f0, g.f1);
+    for (auto &g : pl.groups) {
+        xcd_order(pl.ct, g.c0, g.c1);
+        xcd_order(pl.ft, g.f0, g.f1);
     }
-    size_t need = up(probs.size() * sizeof(ProbDesc)) + up(ct.size() * sizeof(Tile)) + up(ft.size() * sizeof(Tile));
+    return pl;
+}
+
+// Copies a plan's tables to device memory at `dev` (synchronous; the caller has
+// made sure that no queued launch still reads that memory).
+hgks_status upload_plan(const Plan &pl, char *dev, ProbDesc **probs, Tile **ct, Tile **ft) {
+    *probs = (ProbDesc *)dev;
+    *ct = (Tile *)(dev + up(pl.probs.size() * sizeof(ProbDesc)));
+    *ft = (Tile *)((char *)*ct + up(pl.ct.size() * sizeof(Tile)));
+    if (hipMemcpy(*probs, pl.probs.data(), pl.probs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(*ct, pl.ct.data(), pl.ct.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(*ft, pl.ft.data(), pl.ft.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
+        return HGKS_E_DEVICE;
+    return HGKS_OK;
+}
+
+hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
+    std::vector<int> key(slots, slots + n);
+    if (key == P->last_key && P->tab) return HGKS_OK;
+    Plan pl = make_plan(P, key);
+    const size_t need = pl.bytes();
     if (need > P->tab_bytes) {
         if (P->tab) {
             (void)hipStreamSynchronize(P->stream);
@@ -625,20 +658,53 @@ hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
         P->tab_bytes = need * 2;
     }
     (void)hipStreamSynchronize(P->stream);
-    P->d_probs = (ProbDesc *)P->tab;
-    P->d_ct = (Tile *)(P->tab + up(probs.size() * sizeof(ProbDesc)));
-    P->d_ft = (Tile *)((char *)P->d_ct + up(ct.size() * sizeof(Tile)));
-    if (hipMemcpy(P->d_probs, probs.data(), probs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->d_ct, ct.data(), ct.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->d_ft, ft.data(), ft.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
-        return HGKS_E_DEVICE;
-    P->nprobs = (int)probs.size();
-    P->n_ct = (int)ct.size();
+    hgks_status st = upload_plan(pl, P->tab, &P->d_probs, &P->d_ct, &P->d_ft);
+    if (st != HGKS_OK) return st;
+    P->groups = pl.groups;
+    P->nprobs = (int)pl.probs.size();
+    P->n_ct = (int)pl.ct.size();
     P->last_key = key;
     return HGKS_OK;
 }
 
+void enqueue_pool_steps(const ProbDesc *probs, int nprobs, const Tile *ct, int n_ct, const Tile *ft,
+                        const std::vector<hgks_pool::Group> &groups, int32_t nsteps, hipStream_t s) {
+    for (int32_t it = 0; it < nsteps; ++it) {
+        launch_dt_final(probs, nprobs, 0.0, s);
+        for (int stage = 1; stage <= 2; ++stage) {
+            for (auto &g : groups) launch_weno(probs, ct + g.c0, g.c1 - g.c0, stage, g.prec, g.walls, s);
+            for (auto &g : groups)
+                launch_flux(probs, nprobs, ft + g.f0, g.f1 - g.f0, stage, g.prec != HGKS_FP64, g.tau0, false, g.walls, s);
+            launch_update(probs, ct, n_ct, stage, false, s);
+        }
+    }
+}
+
+hgks_status check_slots(const hgks_pool *p, const int *slots, int n) {
+    for (int k = 0; k < n; ++k) {
+        if (slots[k] < 0 || slots[k] >= (int)p->slot.size() || !p->slot[slots[k]]) return HGKS_E_INVALID_ARG;
+        for (int j = 0; j < k; ++j)
+            if (slots[j] == slots[k]) return HGKS_E_INVALID_ARG;
+    }
+    return HGKS_OK;
+}
+
 }  // namespace
+
+// Removes context c from pool p after the pool's queued work is done.
+void pool_detach(hgks_pool *p, hgks_ctx *c) {
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    for (auto &x : p->slot)
+        if (x == c) {
+            x = nullptr;
+            p->used -= c->bytes;
+        }
+    c->pool_refs = 0;
+    c->pool = nullptr;
+    c->pool_stream = nullptr;
+    p->last_key.clear();
+}
 
 extern "C" {
 
@@ -667,8 +733,7 @@ hgks_status hgks_pool_add(hgks_pool *p, hgks_ctx *c, int *slot) {
     if (!c->has_state) return HGKS_E_STATE;
     if (c->device != p->device || c->prm.accumulation != HGKS_ACC_GATHER) return HGKS_E_INVALID_ARG;
     if (p->budget && p->used + c->bytes > p->budget) return HGKS_E_OOM;
-    for (auto *x : p->slot)
-        if (x == c) return HGKS_E_INVALID_ARG;
+    if (c->pool) return HGKS_E_INVALID_ARG;     // a context belongs to one pool at a time
     // the pool runs on its own stream: finish the context's queued work first
     (void)hipSetDevice(p->device);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return HGKS_E_DEVICE;
@@ -679,6 +744,7 @@ hgks_status hgks_pool_add(hgks_pool *p, hgks_ctx *c, int *slot) {
     p->slot[s] = c;
     p->used += c->bytes;
     c->pool_refs++;
+    c->pool = p;
     c->pool_stream = p->stream;
     p->last_key.clear();
     *slot = s;
@@ -688,36 +754,18 @@ hgks_status hgks_pool_add(hgks_pool *p, hgks_ctx *c, int *slot) {
 hgks_status hgks_pool_step(hgks_pool *p, const int *slots, int n, int32_t nsteps) {
     if (!p || (n > 0 && !slots) || n < 0 || nsteps < 0) return HGKS_E_INVALID_ARG;
     if (n == 0 || nsteps == 0) return HGKS_OK;
-    for (int k = 0; k < n; ++k) {
-        if (slots[k] < 0 || slots[k] >= (int)p->slot.size() || !p->slot[slots[k]]) return HGKS_E_INVALID_ARG;
-        for (int j = 0; j < k; ++j)
-            if (slots[j] == slots[k]) return HGKS_E_INVALID_ARG;
-    }
+    if (check_slots(p, slots, n) != HGKS_OK) return HGKS_E_INVALID_ARG;
     if (hipSetDevice(p->device) != hipSuccess) return HGKS_E_DEVICE;
     hgks_status st = pool_plan(p, slots, n);
     if (st != HGKS_OK) return st;
-    hipStream_t s = p->stream;
-    for (int32_t it = 0; it < nsteps; ++it) {
-        launch_dt_final(p->d_probs, p->nprobs, 0.0, s);
-        for (int stage = 1; stage <= 2; ++stage) {
-            for (auto &g : p->groups) launch_weno(p->d_probs, p->d_ct + g.c0, g.c1 - g.c0, stage, g.prec, g.walls, s);
-            for (auto &g : p->groups) launch_flux(p->d_probs, p->nprobs, p->d_ft + g.f0, g.f1 - g.f0, stage, g.prec != HGKS_FP64, g.tau0, false, g.walls, s);
-            launch_update(p->d_probs, p->d_ct, p->n_ct, stage, false, s);
-        }
-    }
+    enqueue_pool_steps(p->d_probs, p->nprobs, p->d_ct, p->n_ct, p->d_ft, p->groups, nsteps, p->stream);
     if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
     return HGKS_OK;
 }
 
 hgks_status hgks_pool_remove(hgks_pool *p, int slot) {
     if (!p || slot < 0 || slot >= (int)p->slot.size() || !p->slot[slot]) return HGKS_E_INVALID_ARG;
-    (void)hipSetDevice(p->device);
-    (void)hipStreamSynchronize(p->stream);
-    hgks_ctx *c = p->slot[slot];
-    p->used -= c->bytes;
-    c->pool_refs--;
-    p->slot[slot] = nullptr;
-    p->last_key.clear();
+    pool_detach(p, p->slot[slot]);
     return HGKS_OK;
 }
 
@@ -734,10 +782,10 @@ hgks_status hgks_pool_used(const hgks_pool *p, size_t *bytes, int *n_slots) {
 
 void hgks_pool_destroy(hgks_pool *p) {
     if (!p) return;
+    for (auto *c : p->slot)
+        if (c) pool_detach(p, c);
     (void)hipSetDevice(p->device);
     (void)hipStreamSynchronize(p->stream);
-    for (auto *c : p->slot)
-        if (c) c->pool_refs--;
     if (p->tab) (void)hipFree(p->tab);
     delete p;
 }

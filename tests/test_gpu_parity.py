@@ -398,3 +398,31 @@ def test_fp32_mixed_walls_shock_tube_against_fp64():
         say(f"precision {prec} vs fp64 relative L1", e)
         assert np.all(np.isfinite(out[prec]))
         assert e[0] < 1e-4 and e[4] < 1e-4, e
+
+
+def test_destroying_a_pooled_context_detaches_it():
+    """A context closed while in a pool leaves the pool first: the pool's
+    accounting drops it and the remaining slots keep stepping."""
+    say("case: destroy a pooled context")
+    mesh, case, q0 = advection_case(5, seed=127)
+    a = make_solver(mesh, q0)
+    b = make_solver(mesh, q0)
+    ref = make_solver(mesh, q0)
+    pool = hgks.Pool()
+    sa = pool.add(a)
+    sb = pool.add(b)
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.Pool().add(a)                    # one pool at a time
+    assert e.value.status == hgks.E_INVALID_ARG
+    pool.step([sa, sb], 1)
+    a.close()
+    assert pool.used() == (b.footprint(), 1)
+    with pytest.raises(hgks.HGKSError):
+        pool.step([sa, sb], 1)                # the freed slot is gone
+    pool.step([sb], 1)
+    ref.step(2)
+    assert np.array_equal(b.get_state()[0], ref.get_state()[0])
+    pool.close()
+    b.step(1)                                 # out of the pool, the context steps alone again
+    b.close()
+    ref.close()
