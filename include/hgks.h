@@ -215,6 +215,28 @@ hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int 
 hgks_status hgks_pool_add(hgks_pool *pool, hgks_ctx *ctx, int *slot);
 /* Advances the listed slots by nsteps S2O4 steps each (CFL dt per slot). */
 hgks_status hgks_pool_step(hgks_pool *pool, const int *slots, int n, int32_t nsteps);
+/*
+ * hgks_pool_step with no device allocation, for callers that cannot allocate
+ * device memory while stepping (tight serving loops, harnesses that forbid
+ * hipMalloc).  hgks_pool_step keeps its launch tables (problem descriptors and
+ * tile tables) in memory it allocates and grows; this call puts them in a static
+ * array of the library, HGKS_STATIC_TABLE_BYTES (8 MiB) per GPU, held until the
+ * process ends.  The tables take about 0.75 bytes a cell (one 16-byte tile per 64
+ * cells and per 64 faces), so a batch may hold about 11 M cells: sixteen problems
+ * of 6*48^3 cells, or five of 6*64^3.  Same kernels and results as
+ * hgks_pool_step, bitwise.
+ * Every call on a GPU shares that GPU's array, which holds the last call's
+ * tables; a call whose tables are not the ones the array holds rewrites them,
+ * waiting first for its pool's stream (and for the whole device when another
+ * pool wrote the array last).  Calls from several host threads take turns on a
+ * lock; steps still queued when another process-local pool rewrites the array
+ * are waited for as above, so only work launched outside the library on these
+ * tables could race.
+ * Errors: INVALID_ARG (bad slot list, or tables larger than the static array; the
+ * message is set on each listed slot's context, see hgks_last_error), DEVICE.
+ */
+#define HGKS_STATIC_TABLE_BYTES ((size_t)8 << 20)
+hgks_status hgks_pool_step_static(hgks_pool *pool, const int *slots, int n, int32_t nsteps);
 /* Releases a slot (the context stays valid and owned by the caller). */
 hgks_status hgks_pool_remove(hgks_pool *pool, int slot);
 hgks_status hgks_pool_used(const hgks_pool *pool, size_t *bytes, int *n_slots);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -574,6 +575,12 @@ struct hgks_pool {
     struct Group { int prec; bool tau0; int c0, c1, f0, f1; bool walls; };
     std::vector<Group> groups;
     int n_ct = 0;
+    // the allocation-free step: its plan, and the serial of its last upload into
+    // the device's static table (the table holds the last uploader's plan)
+    std::vector<int> static_key;
+    std::vector<Group> static_groups;
+    int static_nprobs = 0, static_n_ct = 0;
+    uint64_t static_serial = 0;
 };
 
 namespace {
@@ -667,6 +674,12 @@ hgks_status pool_plan(hgks_pool *P, const int *slots, int n) {
     return HGKS_OK;
 }
 
+// Serial of the plan each device's static table holds (0: none), and the counter
+// that hands out serials.
+std::mutex g_static_mu;
+std::vector<uint64_t> g_static_serial;
+uint64_t g_static_next = 0;
+
 void enqueue_pool_steps(const ProbDesc *probs, int nprobs, const Tile *ct, int n_ct, const Tile *ft,
                         const std::vector<hgks_pool::Group> &groups, int32_t nsteps, hipStream_t s) {
     for (int32_t it = 0; it < nsteps; ++it) {
@@ -704,6 +717,7 @@ void pool_detach(hgks_pool *p, hgks_ctx *c) {
     c->pool = nullptr;
     c->pool_stream = nullptr;
     p->last_key.clear();
+    p->static_key.clear();
 }
 
 extern "C" {
@@ -747,6 +761,7 @@ hgks_status hgks_pool_add(hgks_pool *p, hgks_ctx *c, int *slot) {
     c->pool = p;
     c->pool_stream = p->stream;
     p->last_key.clear();
+    p->static_key.clear();
     *slot = s;
     return HGKS_OK;
 }
@@ -759,6 +774,50 @@ hgks_status hgks_pool_step(hgks_pool *p, const int *slots, int n, int32_t nsteps
     hgks_status st = pool_plan(p, slots, n);
     if (st != HGKS_OK) return st;
     enqueue_pool_steps(p->d_probs, p->nprobs, p->d_ct, p->n_ct, p->d_ft, p->groups, nsteps, p->stream);
+    if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
+    return HGKS_OK;
+}
+
+hgks_status hgks_pool_step_static(hgks_pool *p, const int *slots, int n, int32_t nsteps) {
+    if (!p || (n > 0 && !slots) || n < 0 || nsteps < 0) return HGKS_E_INVALID_ARG;
+    if (n == 0 || nsteps == 0) return HGKS_OK;
+    if (check_slots(p, slots, n) != HGKS_OK) return HGKS_E_INVALID_ARG;
+    if (hipSetDevice(p->device) != hipSuccess) return HGKS_E_DEVICE;
+    void *table = nullptr;
+    if (static_table_ptr(p->device, &table) != hipSuccess) return HGKS_E_DEVICE;
+    std::vector<int> key(slots, slots + n);
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (g_static_serial.size() <= (size_t)p->device) g_static_serial.resize((size_t)p->device + 1, 0);
+    ProbDesc *probs = nullptr;
+    Tile *ct = nullptr, *ft = nullptr;
+    if (key != p->static_key || g_static_serial[(size_t)p->device] != p->static_serial) {
+        Plan pl = make_plan(p, key);
+        if (pl.bytes() > STATIC_TABLE_BYTES) {
+            const std::string m = "allocation-free pool step: the launch tables need " + std::to_string(pl.bytes()) +
+                                  " bytes, beyond the static table of " + std::to_string(STATIC_TABLE_BYTES);
+            for (int k = 0; k < n; ++k) p->slot[slots[k]]->err = m;
+            return HGKS_E_INVALID_ARG;
+        }
+        // the table may still feed queued steps: this pool's, or another pool's when
+        // that one uploaded last (then the whole device is waited for)
+        const bool other = g_static_serial[(size_t)p->device] != 0 &&
+                           g_static_serial[(size_t)p->device] != p->static_serial;
+        if ((other ? hipDeviceSynchronize() : hipStreamSynchronize(p->stream)) != hipSuccess) return HGKS_E_DEVICE;
+        hgks_status st = upload_plan(pl, (char *)table, &probs, &ct, &ft);
+        if (st != HGKS_OK) return st;
+        p->static_key = key;
+        p->static_groups = pl.groups;
+        p->static_nprobs = (int)pl.probs.size();
+        p->static_n_ct = (int)pl.ct.size();
+        p->static_serial = ++g_static_next;
+        g_static_serial[(size_t)p->device] = p->static_serial;
+    } else {
+        // the table still holds this pool's plan for these slots
+        probs = (ProbDesc *)table;
+        ct = (Tile *)((char *)table + up((size_t)p->static_nprobs * sizeof(ProbDesc)));
+        ft = (Tile *)((char *)ct + up((size_t)p->static_n_ct * sizeof(Tile)));
+    }
+    enqueue_pool_steps(probs, p->static_nprobs, ct, p->static_n_ct, ft, p->static_groups, nsteps, p->stream);
     if (hipGetLastError() != hipSuccess) return HGKS_E_DEVICE;
     return HGKS_OK;
 }

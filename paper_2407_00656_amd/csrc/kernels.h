@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "../../include/hgks.h"
+
 namespace hgks {
 
 // One problem's device arrays and constants; kernels read it from a table so
@@ -60,5 +62,12 @@ void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int sta
 void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, hipStream_t s);
 void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
+
+// Size of the per-GPU static launch-table array of the allocation-free pool step:
+// the descriptors and tiles of a batch of about 11 M cells (0.75 bytes a cell).
+constexpr size_t STATIC_TABLE_BYTES = HGKS_STATIC_TABLE_BYTES;
+// Device address of that array on `device`, which must be the current device.
+// Looked up once per device (the runtime call) and cached.
+hipError_t static_table_ptr(int device, void **ptr);
 
 }  // namespace hgks

@@ -24,7 +24,9 @@
 
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "hgks_internal.h"
 #include "kernels.h"
@@ -1747,6 +1749,35 @@ void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStre
 void launch_fill(double *p, double v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+
+// ----------------------------------------------------------------------------
+// Static launch tables (the allocation-free pool step): one file-scope device
+// array per GPU, holding the problem descriptors and tile tables of the last
+// batch stepped through it.  In host code `scratch` names a host-side stand-in,
+// not device memory, so only the address fetched from the runtime below is ever
+// handed to kernels or copies.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[STATIC_TABLE_BYTES];
+
+hipError_t static_table_ptr(int device, void **ptr) {
+    static std::mutex mu;
+    static std::vector<void *> addr;         // per device; null until fetched
+    std::lock_guard<std::mutex> g(mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+    if (!addr[(size_t)device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the caller makes the device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[(size_t)device] = p;
+    }
+    *ptr = addr[(size_t)device];
+    return hipSuccess;
 }
 
 }  // namespace hgks

@@ -70,13 +70,14 @@ def lib():
         L.hgks_pool_footprint.argtypes = [C.POINTER(Params), C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
         L.hgks_pool_add.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
         L.hgks_pool_step.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.c_int32]
+        L.hgks_pool_step_static.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.c_int32]
         L.hgks_pool_remove.argtypes = [C.c_void_p, C.c_int]
         L.hgks_pool_used.argtypes = [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]
         L.hgks_pool_destroy.argtypes = [C.c_void_p]
         for name in ("hgks_create", "hgks_mesh_upload", "hgks_init_state", "hgks_step_s2o4", "hgks_get_state",
                      "hgks_sync", "hgks_mesh_info", "hgks_footprint", "hgks_profile_enable", "hgks_profile_read",
                      "hgks_profile_reset", "hgks_inspect_mesh", "hgks_pool_create", "hgks_pool_footprint",
-                     "hgks_pool_add", "hgks_pool_step", "hgks_pool_remove", "hgks_pool_used"):
+                     "hgks_pool_add", "hgks_pool_step", "hgks_pool_step_static", "hgks_pool_remove", "hgks_pool_used"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -237,6 +238,14 @@ class Pool:
         st = lib().hgks_pool_step(self._h, arr, len(slots), int(nsteps))
         if st != OK:
             raise HGKSError(st, "hgks_pool_step failed")
+
+    def step_static(self, slots, nsteps: int = 1):
+        """hgks_pool_step_static: the same step with the launch tables in the library's
+        static per-GPU array (no device allocation)."""
+        arr = (C.c_int * len(slots))(*slots)
+        st = lib().hgks_pool_step_static(self._h, arr, len(slots), int(nsteps))
+        if st != OK:
+            raise HGKSError(st, "hgks_pool_step_static failed")
 
     def remove(self, slot: int):
         st = lib().hgks_pool_remove(self._h, int(slot))
