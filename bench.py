@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -52,6 +53,15 @@ def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool =
     if kernel == "update":
         return nc * (16 + 160 + 16 + 100)
     return 0.0
+
+
+# Lower bound on the bytes a cell-update must move whatever the design (FP64, Kuhn
+# tets, K = 14, two stages): per stage the state (40), cell geometry (80), stencil
+# ids and sub-stencil positions (80), a 9 x 14 big-stencil pseudo-inverse (1008), four
+# 3 x 6 sub-stencil pseudo-inverses (576), two faces' geometry (224), L and dL/dt
+# written (80) and the update's state traffic (40-120), with the time-step pass:
+# about 4.34 KB, the HBM roofline 8 TB/s / 4.34 KB = 1.84e9 cell-updates/s.
+TABLE_BOUND_BYTES_PER_CELL_UPDATE = 4340.0
 
 
 def reduced_weno(r, nc: int, nf: int, pinv32: bool):
@@ -109,19 +119,47 @@ def run_gpu(mesh, q0, precision, steps, warmup):
     return {"seconds": el, "setup_s": t_setup, "prof": prof, "info": info, "footprint": foot, "t": t, "q": q}
 
 
-def cpu_baseline(n_sample: int = 32):
-    """One oracle S2O4 step on 6*n^3 tets of the same advection data (all host threads)."""
+def cpu_oracle_step(mesh, q0):
+    """Seconds of one FP64 oracle S2O4 step on `mesh` (its mesh precompute not timed)."""
     from oracle import oracle as O
-    from paper_2407_00656_amd import workloads as W
-    mesh = W.kuhn_box(n_sample, seed=W.SEED_ADVECTION + n_sample)
-    q0 = W.AdvectionCase().conservative(mesh)
     om = O.Mesh.from_workload(mesh)
     t0 = time.perf_counter()
     om.step(q0, 1)
-    el = time.perf_counter() - t0
-    return {"value": mesh.n_cells / el, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"one S2O4 step of the FP64 oracle on 6*{n_sample}^3 = {mesh.n_cells} tets "
-                      f"(same advection data), {el:.1f} s"}
+    return time.perf_counter() - t0
+
+
+def cpu_single_thread(n: int) -> dict:
+    """Child-process leg: one oracle step on 6*n^3 tets, one OpenMP thread pinned to one
+    core (this process never touches the GPU)."""
+    from oracle import oracle as O
+    from paper_2407_00656_amd import workloads as W
+    core = min(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {core})
+    mesh = W.kuhn_box(n, seed=W.SEED_ADVECTION + n)
+    q0 = W.AdvectionCase().conservative(mesh)
+    el = cpu_oracle_step(mesh, q0)
+    return {"value": mesh.n_cells / el, "cells": mesh.n_cells, "seconds": el, "threads": O.threads(), "core": core}
+
+
+def cpu_baseline(mesh, q0, workload: str, n_single: int = 32):
+    """The FP64 oracle on this host: one step of the bench's own mesh on all host threads
+    (the reported value), and one step of 6*n_single^3 tets single-threaded, pinned."""
+    from oracle import oracle as O
+    el = cpu_oracle_step(mesh, q0)
+    out = {"value": mesh.n_cells / el, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
+           "sample": f"one S2O4 step of the FP64 oracle on the bench mesh ({workload}, {mesh.n_cells} tets) "
+                     f"on {O.threads()} OpenMP threads, {el:.1f} s"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-single", str(n_single)], env=env,
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode == 0 and r.stdout.strip():
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": one["value"], "unit": "cell-updates/s", "cores": one["threads"],
+                                "sample": f"one S2O4 step on 6*{n_single}^3 = {one['cells']} tets, one thread "
+                                          f"pinned to core {one['core']}, {one['seconds']:.1f} s"}
+    else:
+        out["single_thread"] = {"error": (r.stderr or "")[-300:]}
+    return out
 
 
 def serve_bench(count: int, steps: int, budget_gb: float):
@@ -162,9 +200,13 @@ def main():
     ap.add_argument("--serve", type=int, default=24, help="requests in the serve-loop run (0 skips it)")
     ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--cpu-single", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (x5) to calibrate HBM byte counters")
     args = ap.parse_args()
+    if args.cpu_single:          # the single-threaded oracle leg, run as a child process
+        print(json.dumps(cpu_single_thread(args.cpu_single)), flush=True)
+        return
     if args.copy_calibration:
         import torch
         x = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
@@ -214,6 +256,14 @@ def main():
         kernels[k] = {"avg_us": 1e3 * ms / max(1, cnt), "launches": cnt,
                       "share": ms / max(1e-12, sum(v[0] for v in prof.values())),
                       "alg_GBps": (b / (ms / 1e3 / max(1, cnt)) / 1e9) if b and cnt else None}
+    # the whole step: every kernel's algorithmic bytes over the measured step time
+    step_bytes = sum(algorithmic_bytes(k, nc, nf, False) * prof[k][1] for k in ("weno", "flux", "update")) / args.steps
+    step_s = r64["seconds"] / args.steps
+    path = {"alg_bytes_per_step": step_bytes, "alg_bytes_per_cell_update": round(step_bytes / nc, 1),
+            "achieved_GBps": round(step_bytes / step_s / 1e9, 1),
+            "frac": round(step_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+            "table_bound_cell_updates_per_s": round(HBM_PEAK_GBS * 1e9 / TABLE_BOUND_BYTES_PER_CELL_UPDATE, 1),
+            "frac_of_table_bound": round(value / (HBM_PEAK_GBS * 1e9 / TABLE_BOUND_BYTES_PER_CELL_UPDATE), 4)}
     traffic = measured_traffic(dom, workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
@@ -222,7 +272,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(32 if n >= 32 else n)
+        cpu = cpu_baseline(mesh, q0, workload, 32 if n >= 32 else n)
 
     srv = None
     if args.serve > 0:
@@ -245,6 +295,7 @@ def main():
         "config": {"workload": f"{workload}, periodic [0,2]^3, jitter 0.1h, rho=1+0.2sin(pi(x+y+z)), "
                                f"U=(1,1,1), p=1, CFL 0.3, tau=0", "cells": nc, "faces": nf},
         "roofline": roofline,
+        "path_roofline": path,
         "cpu_baseline": cpu,
         "fp32_mixed": None if r32 is None else {
             "value": round(nc * args.steps / r32["seconds"], 1),
