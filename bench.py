@@ -9,12 +9,15 @@ path (the headline value) and for the FP32-mixed and FP32 forms, the roofline po
 of the dominant kernel (per-kernel HIP events inside the timed region), and the
 CPU oracle timed on this host.
 
-The serve loop (continuous batching of many smaller solves) runs last: a
-seeded stream of requests (Kuhn boxes of 6 N^3 cells, N ~ U{8..48}, random
-smooth data, Mach 0.1-2, FP64 or FP32-mixed, 200 steps each) is served twice,
-first all at once to measure the loop's capacity, then with Poisson arrivals
-at 0.8 of that capacity; the line reports p50/p99 latency (arrival to result
-on the host, host mesh precompute included) and aggregate cell-updates/s.
+The serve loop (continuous batching of many smaller solves) runs after the
+step timings: a seeded stream of 256 requests (Kuhn boxes of 6 N^3 cells,
+N ~ U{8..48}, random smooth data, Mach 0.1-2, FP64 or FP32-mixed, 200 steps
+each); the first 64 are served all at once to measure the loop's capacity, then
+all 256 with Poisson arrivals at 0.8 of that capacity; the line reports p50/p99
+latency (arrival to result on the host, host mesh precompute included),
+aggregate cell-updates/s, and (with the CPU leg) the oracle's verdict on the
+served requests with N = 8 over their whole run and on two steps of eight
+sampled larger ones.
 
     python bench.py [--steps K] [--warmup W] [--n N] [--no-cpu-baseline] [--serve R]
 """
@@ -40,16 +43,16 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
 #          codes (16) + reconstruction written (400)                           = 1752
 #          (the sub-stencil fits are formed on the device from the centroids;
 #          FP32-mixed writes 200, and the FP32 form also reads a 576 B pseudo-inverse)
-#   flux   per face: cells (8) + normal, area, Gauss offsets (176) + flux written (80)
-#          = 264 in the first stage and 224 in the second (dF only), plus per cell
-#          the reconstruction read once (400)
+#   flux   per face: cells (8) + normal, area, Gauss offsets and the centroid difference
+#          (128) + flux written (80) = 216 in the first stage and 176 in the second (dF
+#          only), plus per cell the reconstruction read once (400)
 #   update per cell: face ids (16) + its faces' fluxes (2 faces' worth, 160) + 1/|V|
 #          and h (16) + state traffic (stage 1: 3 x 40, stage 2: 2 x 40)       ~ 292
 def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool = False) -> float:
     if kernel == "weno":
         return nc * (64 + 40 + (576 if pinv32 else 1152) + 56 + 24 + 16 + (200 if mixed else 400))
-    if kernel == "flux":   # 264 B a face in the first stage, 224 in the second (F not stored)
-        return nf * 244 + nc * ((200 + 40) if mixed else 400)
+    if kernel == "flux":   # 216 B a face in the first stage, 176 in the second (F not stored)
+        return nf * 196 + nc * ((200 + 40) if mixed else 400)
     if kernel == "update":
         return nc * (16 + 160 + 16 + 100)
     return 0.0
@@ -162,31 +165,90 @@ def cpu_baseline(mesh, q0, workload: str, n_single: int = 32):
     return out
 
 
-def serve_bench(count: int, steps: int, budget_gb: float):
-    """Closed-loop capacity, then Poisson arrivals at 0.8 of it (requests/s)."""
+def serve_bench(count: int, steps: int, budget_gb: float, capacity_count: int, two_step_sample: int = 8):
+    """Closed-loop capacity on the first `capacity_count` requests, then all `count`
+    requests with Poisson arrivals at 0.8 of that capacity (requests/s).  Also runs a
+    seeded sample of the larger requests alone for two steps on the GPU (alone and in
+    the mix are bitwise the same), for the oracle check of the CPU leg."""
+    from paper_2407_00656_amd import hgks
     from paper_2407_00656_amd import serve
     from paper_2407_00656_amd import workloads as W
     reqs = W.serve_requests(count, seed=2407, n_range=(8, 48), steps=steps, rate=1.0)
-    for r in reqs:
-        r.arrival = 0.0
     budget = int(budget_gb * 1e9)
+    print(f"bench: serve payloads for {count} requests", file=sys.stderr, flush=True)
     payloads = serve.make_payloads(reqs)          # the clients' meshes and initial states
-    burst = serve.run(reqs, budget, workers=4, payloads=payloads)
+    first = reqs[:capacity_count]
+    for r in first:
+        r.arrival = 0.0
+    print(f"bench: serve capacity pass ({capacity_count} requests at once)", file=sys.stderr, flush=True)
+    burst = serve.run(first, budget, workers=4, payloads=payloads)
     capacity = burst["requests"] / burst["makespan_s"]
     rate = 0.8 * capacity
     reqs = W.serve_requests(count, seed=2407, n_range=(8, 48), steps=steps, rate=rate)
-    res = serve.run(reqs, budget, workers=4, payloads=payloads)
+    print(f"bench: serve Poisson pass ({count} requests at {rate:.2f}/s)", file=sys.stderr, flush=True)
+    res = serve.run(reqs, budget, workers=4, payloads=payloads,
+                    log=lambda m: print("bench: serve " + m, file=sys.stderr, flush=True)
+                    if m.startswith("done") and int(m.split("rid=")[1].split()[0]) % 32 == 0 else None)
     errs = serve.exact_errors(res["jobs"])
     cells = [j.mesh.n_cells for j in res["jobs"]]
-    return {"requests": res["requests"], "steps_each": steps, "n_range": [8, 48],
-            "cells_mean": round(float(sum(cells)) / len(cells), 1),
-            "precision_mix_fp32": sum(j.req.precision for j in res["jobs"]),
-            "rate_req_per_s": round(rate, 4), "capacity_req_per_s": round(capacity, 4),
-            "p50_s": round(res["p50_s"], 4), "p99_s": round(res["p99_s"], 4),
-            "cell_updates_per_s": round(res["cell_updates_per_s"], 1),
-            "cell_updates_per_gpu_busy_s": round(res["cell_updates_per_busy_s"], 1),
-            "ticks": res["ticks"], "hbm_budget_GB": budget_gb,
-            "rel_L1_rho_vs_exact_max": max(errs)}
+    # two-step GPU results of a seeded sample of the requests with N > 8
+    big = [j for j in res["jobs"] if j.req.n > 8]
+    pick = sorted(big, key=lambda j: (j.req.rid * 2654435761) % 4294967296)[:two_step_sample]
+    two = []
+    for j in pick:
+        s = hgks.Solver(hgks.params(precision=j.req.precision))
+        s.mesh_upload(j.mesh.nodes, j.mesh.cell_nodes, j.mesh.period)
+        s.init_state(j.q0)
+        s.step(2)
+        two.append((j, s.get_state()[0]))
+        s.close()
+    out = {"requests": res["requests"], "steps_each": steps, "n_range": [8, 48],
+           "cells_mean": round(float(sum(cells)) / len(cells), 1),
+           "precision_mix_fp32": sum(j.req.precision for j in res["jobs"]),
+           "rate_req_per_s": round(rate, 4), "capacity_req_per_s": round(capacity, 4),
+           "capacity_pass_requests": capacity_count,
+           "p50_s": round(res["p50_s"], 4), "p99_s": round(res["p99_s"], 4),
+           "cell_updates_per_s": round(res["cell_updates_per_s"], 1),
+           "cell_updates_per_gpu_busy_s": round(res["cell_updates_per_busy_s"], 1),
+           "ticks": res["ticks"], "hbm_budget_GB": budget_gb,
+           "rel_L1_rho_vs_exact_max": max(errs)}
+    return out, res["jobs"], two
+
+
+def serve_oracle_check(jobs, two) -> dict:
+    """The CPU oracle on served requests: every served request with N = 8 over its whole
+    run, and the two-step results of the sampled larger ones.  FP64 requests report the
+    largest scaled error per conserved variable (the norm of the GPU parity tests),
+    FP32-mixed ones the relative L1 of density against the FP64 oracle."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2407_00656_amd import workloads as W
+
+    def compare(j, q_gpu, nsteps):
+        om = O.Mesh.from_workload(j.mesh)
+        q_orc, _ = om.step(j.q0, nsteps)
+        vol = W.tet_volumes(j.mesh.cell_vertices)
+        rho = q_orc[:, 0]
+        l1 = float(np.sum(np.abs(q_gpu[:, 0] - rho) * vol) / np.sum(np.abs(rho) * vol))
+        m = q_orc[:, 1:4]
+        pr = 0.4 * (q_orc[:, 4] - 0.5 * np.sum(m * m, axis=1) / rho)
+        ms = max(np.sqrt(np.sum(m * m, axis=1)).max(), np.max(rho * np.sqrt(1.4 * pr / rho)))
+        scale = np.array([np.abs(rho).max(), ms, ms, ms, np.abs(q_orc[:, 4]).max()])
+        scaled = float((np.abs(q_gpu - q_orc).max(axis=0) / scale).max())
+        return {"rid": j.req.rid, "n": j.req.n, "precision": "fp32_mixed" if j.req.precision else "fp64",
+                "steps": nsteps, "max_scaled_err": scaled, "rel_L1_rho": l1}
+
+    t0 = time.perf_counter()
+    full = [compare(j, j.q, j.req.steps) for j in jobs if j.req.n == 8]
+    short = [compare(j, q2, 2) for j, q2 in two]
+    rows = full + short
+
+    def worst(prec, key):
+        v = [r[key] for r in rows if r["precision"] == prec]
+        return max(v) if v else None
+    return {"full_runs": len(full), "two_step_runs": len(short), "seconds": round(time.perf_counter() - t0, 1),
+            "fp64_max_scaled_err": worst("fp64", "max_scaled_err"),
+            "fp32_mixed_max_rel_L1_rho": worst("fp32_mixed", "rel_L1_rho"), "requests": rows}
 
 
 def main():
@@ -197,7 +259,9 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--serve", type=int, default=24, help="requests in the serve-loop run (0 skips it)")
+    ap.add_argument("--serve", type=int, default=256, help="requests in the serve-loop run (0 skips it)")
+    ap.add_argument("--serve-capacity", type=int, default=64,
+                    help="requests of the closed-loop pass that measures the loop's capacity")
     ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--cpu-single", type=int, default=0, help=argparse.SUPPRESS)
@@ -269,15 +333,19 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
 
+    srv = jobs = two = None
+    if args.serve > 0:
+        print("bench: serve loop", file=sys.stderr, flush=True)
+        srv, jobs, two = serve_bench(args.serve, args.serve_steps, args.serve_budget_gb,
+                                     min(args.serve, args.serve_capacity))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(mesh, q0, workload, 32 if n >= 32 else n)
-
-    srv = None
-    if args.serve > 0:
-        print("bench: serve loop", file=sys.stderr, flush=True)
-        srv = serve_bench(args.serve, args.serve_steps, args.serve_budget_gb)
+        if srv is not None:
+            print("bench: CPU oracle on served requests", file=sys.stderr, flush=True)
+            srv["vs_oracle"] = serve_oracle_check(jobs, two)
 
     out = {
         "metric": "cell-updates/s per S2O4 step on 1 MI355X (FP64 vs FP32-mixed); serve p50/p99",

@@ -105,8 +105,14 @@ typedef struct {
 
 typedef struct hgks_ctx hgks_ctx;
 
+/* Passed as the stream of hgks_create or hgks_pool_create: the context (pool)
+ * creates a non-blocking stream of default priority for its work and destroys it
+ * with itself, so that work of different contexts and pools can overlap. */
+#define HGKS_OWN_STREAM ((void *)1)
+
 /* Creates a context on HIP device `device`, queueing work on `hip_stream`
- * (a hipStream_t; NULL selects the device's null stream).  `alloc` may be NULL.
+ * (a hipStream_t; NULL selects the device's null stream; HGKS_OWN_STREAM a stream
+ * of its own).  `alloc` may be NULL.
  * Errors: INVALID_ARG (bad params or device), DEVICE. */
 hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream,
                         const hgks_allocator *alloc, hgks_ctx **out);
@@ -159,7 +165,9 @@ hgks_status hgks_get_state(hgks_ctx *ctx, double *q_out, double *t_out);
 /* Waits for the context's queued work.  Errors: DEVICE, NONPHYSICAL. */
 hgks_status hgks_sync(hgks_ctx *ctx);
 
-/* Mesh sizes after upload: cells, faces, two-layer stencil slots, colour classes. */
+/* Mesh sizes after upload: cells, faces, two-layer stencil slots, colour classes
+ * (with HGKS_ACC_COLOURED: 4 when the cell graph is bipartite, else at most 5;
+ * 1 with the gather accumulation). */
 hgks_status hgks_mesh_info(const hgks_ctx *ctx, int64_t *n_cells, int64_t *n_faces,
                            int32_t *stencil_slots, int32_t *n_colours);
 
@@ -203,10 +211,11 @@ hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const 
  */
 typedef struct hgks_pool hgks_pool;
 
-/* hbm_budget: admission limit on the summed footprints of the slots (0 = none). */
+/* hbm_budget: admission limit on the summed footprints of the slots (0 = none).
+ * hip_stream as in hgks_create (HGKS_OWN_STREAM: the pool's own stream). */
 hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hgks_pool **out);
 /* Bytes a context with this mesh size will hold (used for admission; exact for a
- * periodic mesh, wall faces add 8 + 176 + 80 bytes each).  HGKS_E_INVALID_ARG for
+ * periodic mesh, wall faces add 8 + 128 + 80 bytes each).  HGKS_E_INVALID_ARG for
  * parameters hgks_create would reject, n_cells <= 0 or nodes_per_cell != 4. */
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int nodes_per_cell, size_t *bytes);
 /* Adds a context (mesh uploaded, state initialised); returns its slot id.  A context

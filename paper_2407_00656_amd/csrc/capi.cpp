@@ -101,6 +101,7 @@ struct hgks_ctx {
     std::vector<hipEvent_t> spare;
     double prof_ms[4] = {0, 0, 0, 0};
     int64_t prof_n[4] = {0, 0, 0, 0};
+    bool own_stream = false;              // the stream was created here (HGKS_OWN_STREAM)
     int pool_refs = 0;
     hgks_pool *pool = nullptr;            // the pool holding this context (at most one)
     hipStream_t pool_stream = nullptr;    // stream of the pool holding this context
@@ -252,6 +253,14 @@ hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream,
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return HGKS_E_DEVICE;
+    }
+    if (hip_stream == HGKS_OWN_STREAM) {
+        c->stream = nullptr;
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return HGKS_E_DEVICE;
+        }
+        c->own_stream = true;
     }
     *out = c;
     return HGKS_OK;
@@ -526,6 +535,7 @@ void hgks_destroy(hgks_ctx *c) {
     collect_profile(c);
     for (auto e : c->spare) (void)hipEventDestroy(e);
     release(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -562,6 +572,7 @@ hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const 
 struct hgks_pool {
     int device = 0;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
     size_t budget = 0, used = 0;
     std::vector<hgks_ctx *> slot;
     // device tables for the current batch
@@ -731,6 +742,15 @@ hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hg
     p->device = device;
     p->stream = (hipStream_t)hip_stream;
     p->budget = hbm_budget;
+    if (hip_stream == HGKS_OWN_STREAM) {
+        p->stream = nullptr;
+        if (hipSetDevice(device) != hipSuccess ||
+            hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return HGKS_E_DEVICE;
+        }
+        p->own_stream = true;
+    }
     *out = p;
     return HGKS_OK;
 }
@@ -846,6 +866,7 @@ void hgks_pool_destroy(hgks_pool *p) {
     (void)hipSetDevice(p->device);
     (void)hipStreamSynchronize(p->stream);
     if (p->tab) (void)hipFree(p->tab);
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
     delete p;
 }
 

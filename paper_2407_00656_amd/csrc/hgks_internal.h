@@ -23,8 +23,10 @@
 //   fcell  int32  [2][nf]        left, right cell of each face (normal points left->right);
 //                                right = -1 at a wall face (the ghost: the left cell's
 //                                mirror image, evaluated from the left cell's record)
-//   fgeo   double [22][nf]       n(3), S, Gauss-point offsets from the left centroid
-//                                [3][3], offsets from the right centroid [3][3]
+//   fgeo   double [8][nf][2]     16 values per face as pair rows (value v in pair v/2,
+//                                lane v%2): n(3), S, Gauss-point offsets from the left
+//                                centroid [3][3], left minus right centroid (3; the
+//                                right offsets are the left ones plus it, zero at a wall)
 //   C      double [25][nc][2]    reconstruction: per variable (c0, g(3), H(6)) of
 //                                P(y) = c0 + g.y + H_xx y_x^2 + ... + H_yz y_y y_z,
 //                                y = x - centroid, stored as five coefficient pairs
@@ -47,7 +49,7 @@ namespace hgks {
 constexpr int SLOTS = 16;
 constexpr int NCOEF = 10;          // per variable: c0, g(3), H(6)
 constexpr int CGEO = 9;
-constexpr int FGEO = 22;
+constexpr int FGEO = 16;
 constexpr int CELL_TILE = 256;     // cells per workgroup (weno, update, dt)
 constexpr int FACE_TILE = 64;      // faces per workgroup (flux: 3 waves, one per Gauss point)
 
@@ -90,7 +92,7 @@ struct HostMesh {
     hvec<double> cgeo;              // [9][nc]
     hvec<int32_t> cface;            // [4][nc]
     hvec<int32_t> fcell;            // [2][nf]
-    hvec<double> fgeo;              // [22][nf]
+    hvec<double> fgeo;              // [8][nf][2]
     // faces grouped by colour (coloured accumulation); colour_offsets[c]..[c+1]
     std::vector<int32_t> colour_offsets;
     // diagnostics

@@ -1110,24 +1110,48 @@ __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t
     }
 }
 
+// Face geometry: 16 values per face in pair rows [8][nf] (value v in pair v/2, lane
+// v%2): the unit normal (3), the area, the offsets of the three Gauss points from the
+// left centroid (3 x 3), and the left centroid minus the right one (periodic image
+// applied).  A point's offset from the right centroid is its left offset plus that
+// difference; it is zero at a wall face, whose ghost side is evaluated at the wall
+// cell's own offsets.
+__device__ __forceinline__ void load_fgeo(const ProbDesc &P, uint32_t f, double v[16]) {
+    const d2 *g = reinterpret_cast<const d2 *>(P.fgeo);
+    const size_t nf = (size_t)P.nf;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const d2 pr = ldg<d2>(g + k * nf, f * 16u);
+        v[2 * k] = pr.x;
+        v[2 * k + 1] = pr.y;
+    }
+}
+__device__ __forceinline__ double fgeo_area(const ProbDesc &P, uint32_t f) {
+    return ldg<double>(P.fgeo + (size_t)2 * P.nf, f * 16u + 8u);      // value 3: pair 1, lane 1
+}
+// Gauss point p: offsets from the left and the right centroid
+template <class T>
+__device__ __forceinline__ void fgeo_point(const double v[16], int p, T yl[3], T yr[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        yl[a] = (T)v[4 + 3 * p + a];
+        yr[a] = (T)(v[4 + 3 * p + a] + v[13 + a]);
+    }
+}
+
 // The tau = 0 flux of face f with the positivity fallback, one Gauss point at a
 // time from reloaded inputs (only faces that need it come here).
 template <class T>
 __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage, uint32_t f, uint32_t l,
                                                              uint32_t r, bool wall, double out[10]) {
-    const uint32_t nf = (uint32_t)P.nf;
-    const double *fg = P.fgeo;
-    const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
-                    (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
-    const double w = ldg<double>(fg + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
+    double fv[16];
+    load_fgeo(P, f, fv);
+    const T n[3] = {(T)fv[0], (T)fv[1], (T)fv[2]};
+    const double w = fv[3] * (1.0 / 3.0);
 #pragma unroll 1
     for (int p = 0; p < 3; ++p) {
         T yl[3], yr[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            yl[a] = (T)ldg<double>(fg + (size_t)(4 + 3 * p + a) * nf, f * 8u);
-            yr[a] = (T)ldg<double>(fg + (size_t)(13 + 3 * p + a) * nf, f * 8u);
-        }
+        fgeo_point(fv, p, yl, yr);
         T qL[5], qR[5], gs[5][3];
         recon_point<T, false>(P, stage, l, yl, qL, gs);
         recon_point<T, true>(P, stage, r, yr, qR, gs);
@@ -1167,7 +1191,7 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
 // SIMD: left alone the FP64 one takes a few accumulation registers beyond 256 and
 // runs one wave (a few bytes of scratch per lane cost less than that).
 template <bool MIXED, bool COLOURED, bool WALLS, bool DF_ONLY = false>
-__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(WALLS && !COLOURED ? 2 : 1))) void
+__global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(COLOURED ? 1 : (MIXED ? 3 : 2)))) void
 k_flux_t0(const ProbDesc *__restrict__ probs,
                                                        const Tile *__restrict__ tiles, int stage) {
     static_assert(!(DF_ONLY && COLOURED), "the coloured mode accumulates both");
@@ -1183,18 +1207,13 @@ k_flux_t0(const ProbDesc *__restrict__ probs,
     const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
     const bool wall = WALLS && rr < 0;           // the ghost side is l's record mirrored
     const uint32_t r = rr < 0 ? l : (uint32_t)rr;
-    const double *fg = P.fgeo;
-    const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
-                    (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
-    const double S = ldg<double>(fg + (size_t)3 * nf, f * 8u);
+    double fv[16];
+    load_fgeo(P, f, fv);
+    const T n[3] = {(T)fv[0], (T)fv[1], (T)fv[2]};
+    const double S = fv[3];
     T yl[3][3], yr[3][3];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            yl[p][a] = (T)ldg<double>(fg + (size_t)(4 + 3 * p + a) * nf, f * 8u);
-            yr[p][a] = (T)ldg<double>(fg + (size_t)(13 + 3 * p + a) * nf, f * 8u);
-        }
+    for (int p = 0; p < 3; ++p) fgeo_point(fv, p, yl[p], yr[p]);
     T qL[3][5], qR[3][5], gs[3][5][3];
     recon_gp3<T, false>(P, stage, l, yl, qL, gs);
     // at a wall face the ghost side adds l's gradient reflected in the wall (branch-free:
@@ -1275,16 +1294,11 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) 
 template <bool MIXED, bool WALLS>
 __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
                                                 uint32_t r, bool wall, double Fo[5], double dFo[5]) {
-    const uint32_t nf = (uint32_t)P.nf;
-    const double *fg = P.fgeo;
-    const double nd[3] = {ldg<double>(fg, f * 8u), ldg<double>(fg + nf, f * 8u),
-                          ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+    double fv[16];
+    load_fgeo(P, f, fv);
+    const double nd[3] = {fv[0], fv[1], fv[2]};
     double yld[3], yrd[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        yld[a] = ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
-        yrd[a] = ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
-    }
+    fgeo_point(fv, (int)g, yld, yrd);
     double qL[5], gL[5][3], qR[5], gR[5][3];
     recon_point<double, false, MIXED>(P, stage, l, yld, qL, gL);
     recon_point<double, false, MIXED>(P, stage, r, yrd, qR, gR);
@@ -1311,16 +1325,11 @@ __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, ui
 template <bool WALLS>
 __device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
                                                   uint32_t r, bool wall, double Fo[5], double dFo[5]) {
-    const uint32_t nf = (uint32_t)P.nf;
-    const double *fg = P.fgeo;
-    const float n[3] = {(float)ldg<double>(fg, f * 8u), (float)ldg<double>(fg + nf, f * 8u),
-                        (float)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
+    double fv[16];
+    load_fgeo(P, f, fv);
+    const float n[3] = {(float)fv[0], (float)fv[1], (float)fv[2]};
     float yl[3], yr[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        yl[a] = (float)ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
-        yr[a] = (float)ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
-    }
+    fgeo_point(fv, (int)g, yl, yr);
     float qL[5], gL[5][3], qR[5], gR[5][3];
     recon_point<float, false>(P, stage, l, yl, qL, gL);
     recon_point<float, false>(P, stage, r, yr, qR, gR);
@@ -1363,16 +1372,12 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
         const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
         wall = WALLS && rr < 0;                  // the ghost side is l's record mirrored
         r = rr < 0 ? l : (uint32_t)rr;
-        const double *fg = P.fgeo;
-        const T n[3] = {(T)ldg<double>(fg, f * 8u), (T)ldg<double>(fg + nf, f * 8u),
-                        (T)ldg<double>(fg + (size_t)2 * nf, f * 8u)};
-        const double S = ldg<double>(fg + (size_t)3 * nf, f * 8u);
+        double fv[16];
+        load_fgeo(P, f, fv);
+        const T n[3] = {(T)fv[0], (T)fv[1], (T)fv[2]};
+        const double S = fv[3];
         T yl[3], yr[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            yl[a] = (T)ldg<double>(fg + (size_t)(4 + 3 * g + a) * nf, f * 8u);
-            yr[a] = (T)ldg<double>(fg + (size_t)(13 + 3 * g + a) * nf, f * 8u);
-        }
+        fgeo_point(fv, (int)g, yl, yr);
         double Fo[5], dFo[5];
         if constexpr (TAU0) {
             T qL[5], qR[5], gs[5][3], F[5], dF[5];
@@ -1455,7 +1460,7 @@ __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ pro
             done = point_flux_full32<WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
         else
             point_flux_full<false, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
-        const double w = ldg<double>(P.fgeo + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
+        const double w = fgeo_area(P, f) * (1.0 / 3.0);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             out[k] = done ? w * Fo[k] : __builtin_nan("");   // NaN: the face goes to the fix-up pass
@@ -1499,7 +1504,7 @@ __global__ __launch_bounds__(64) void k_flux_fix_full(const ProbDesc *__restrict
         const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
         const bool wall = WALLS && rr < 0;
         const uint32_t r = rr < 0 ? l : (uint32_t)rr;
-        const double w = ldg<double>(P.fgeo + (size_t)3 * nf, f * 8u) * (1.0 / 3.0);
+        const double w = fgeo_area(P, f) * (1.0 / 3.0);
         double out[10];
 #pragma unroll 1
         for (uint32_t g = 0; g < 3u; ++g) {

@@ -134,6 +134,156 @@ bool pinv_normal(int m, int n, const double *A, double *P) {
     return true;
 }
 
+// Proper edge colouring of a graph with n vertices, edges (eu[e], ev[e]) and largest
+// degree at most 4 (faces of tetrahedra): colour[e] in [0, k), no two edges of one
+// colour at a vertex.  A bipartite graph gets k = 4 colours: an edge takes a colour
+// free at both ends, or else the alternating path of the two colours free at either
+// end is swapped first (it cannot return to the edge in a bipartite graph).  Any
+// other graph gets at most 5 by the fan-rotation method of Misra and Gries.  Returns
+// the number of colours used, or -1 if the result fails the final check.
+int colour_edges(int32_t n, const std::vector<int32_t> &eu, const std::vector<int32_t> &ev,
+                 std::vector<int8_t> &colour) {
+    const int64_t m = (int64_t)eu.size();
+    constexpr int MAXC = 5;
+    std::vector<std::array<int32_t, 4>> inc(n);          // incident edges of each vertex
+    std::vector<int8_t> deg(n, 0);
+    for (int64_t e = 0; e < m; ++e) {
+        for (int32_t x : {eu[e], ev[e]}) {
+            if (deg[x] >= 4) return -1;
+            inc[x][deg[x]++] = (int32_t)e;
+        }
+    }
+    // two-colour the vertices: bipartite or not
+    std::vector<int8_t> side(n, -1);
+    bool bip = true;
+    {
+        std::vector<int32_t> stack;
+        for (int32_t s0 = 0; s0 < n && bip; ++s0) {
+            if (side[s0] >= 0) continue;
+            side[s0] = 0;
+            stack.push_back(s0);
+            while (!stack.empty() && bip) {
+                const int32_t x = stack.back();
+                stack.pop_back();
+                for (int k = 0; k < deg[x]; ++k) {
+                    const int64_t e = inc[x][k];
+                    const int32_t y = eu[e] == x ? ev[e] : eu[e];
+                    if (side[y] < 0) {
+                        side[y] = (int8_t)(1 - side[x]);
+                        stack.push_back(y);
+                    } else if (side[y] == side[x]) {
+                        bip = false;
+                    }
+                }
+            }
+        }
+    }
+    const int K = bip ? 4 : 5;
+    std::vector<std::array<int32_t, MAXC>> at(n);         // at[x][c]: edge of colour c at x, or -1
+    for (auto &a : at) a.fill(-1);
+    for (int64_t e = 0; e < m; ++e) colour[e] = -1;
+    auto other = [&](int64_t e, int32_t x) { return eu[e] == x ? ev[e] : eu[e]; };
+    auto free_at = [&](int32_t x, int c) { return at[x][c] < 0; };
+    auto first_free = [&](int32_t x) {
+        for (int c = 0; c < K; ++c)
+            if (at[x][c] < 0) return c;
+        return -1;
+    };
+    auto set = [&](int64_t e, int c) {
+        colour[e] = (int8_t)c;
+        at[eu[e]][c] = (int32_t)e;
+        at[ev[e]][c] = (int32_t)e;
+    };
+    auto unset = [&](int64_t e) {
+        const int c = colour[e];
+        if (c < 0) return;
+        if (at[eu[e]][c] == e) at[eu[e]][c] = -1;
+        if (at[ev[e]][c] == e) at[ev[e]][c] = -1;
+        colour[e] = -1;
+    };
+    // swap colours a and b along the maximal path that leaves x on its a-edge
+    std::vector<int64_t> path;
+    auto swap_path = [&](int32_t x, int a, int b) {
+        path.clear();
+        int c = a, d = b;
+        int32_t y = x;
+        while (at[y][c] >= 0) {
+            const int64_t e = at[y][c];
+            path.push_back(e);
+            y = other(e, y);
+            std::swap(c, d);
+        }
+        for (int64_t e : path) unset(e);
+        for (size_t k = 0; k < path.size(); ++k) set(path[k], k % 2 == 0 ? b : a);
+    };
+    for (int64_t e = 0; e < m; ++e) {
+        const int32_t u = eu[e], v = ev[e];
+        if (bip) {
+            const int a = first_free(u), b = first_free(v);
+            if (a < 0 || b < 0) return -1;
+            if (free_at(v, a)) {
+                set(e, a);
+                continue;
+            }
+            swap_path(v, a, b);          // v's a-edge becomes b: a is free at v, still at u
+            if (!free_at(u, a) || !free_at(v, a)) return -1;
+            set(e, a);
+            continue;
+        }
+        // Misra-Gries: a maximal fan of u starting at v
+        std::vector<int32_t> fan{v};
+        while (true) {
+            const int32_t last = fan.back();
+            int32_t next = -1;
+            for (int k = 0; k < deg[u] && next < 0; ++k) {
+                const int64_t f = inc[u][k];
+                if (colour[f] < 0) continue;
+                const int32_t w = other(f, u);
+                if (std::find(fan.begin(), fan.end(), w) != fan.end()) continue;
+                if (free_at(last, colour[f])) next = w;
+            }
+            if (next < 0) break;
+            fan.push_back(next);
+        }
+        const int c = first_free(u), d = first_free(fan.back());
+        if (c < 0 || d < 0) return -1;
+        if (c != d) swap_path(u, d, c);  // the cd-path from u, starting on its d-edge
+        // the first fan vertex w at which d is free; the fan up to w stays a fan
+        size_t wi = 0;
+        while (wi < fan.size() && !free_at(fan[wi], d)) ++wi;
+        if (wi == fan.size()) return -1;
+        auto edge_to = [&](int32_t w) {
+            for (int k = 0; k < deg[u]; ++k)
+                if (other(inc[u][k], u) == w) return (int64_t)inc[u][k];
+            return (int64_t)-1;
+        };
+        // rotate: (u, fan[i]) takes the colour of (u, fan[i+1]); (u, w) takes d
+        for (size_t i = 0; i < wi; ++i) {
+            const int64_t fi = edge_to(fan[i]), fj = edge_to(fan[i + 1]);
+            const int cj = colour[fj];
+            unset(fj);
+            unset(fi);
+            set(fi, cj);
+        }
+        const int64_t fw = edge_to(fan[wi]);
+        unset(fw);
+        if (!free_at(u, d) || !free_at(fan[wi], d)) return -1;
+        set(fw, d);
+    }
+    // check: every edge coloured, no colour twice at a vertex
+    int used = 0;
+    for (int32_t x = 0; x < n; ++x) {
+        int mask = 0;
+        for (int k = 0; k < deg[x]; ++k) {
+            const int c = colour[inc[x][k]];
+            if (c < 0 || c >= K || (mask >> c) & 1) return -1;
+            mask |= 1 << c;
+            used = std::max(used, c + 1);
+        }
+    }
+    return used;
+}
+
 uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
     v &= 0x1fffff;
     v = (v | v << 32) & 0x1f00000000ffffULL;
@@ -557,20 +707,23 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                           [](const FaceRec &x, const FaceRec &y) { return x.r < y.r || (x.r == y.r && x.pl < y.pl); });
         });
     }
-    // colour classes: no two faces of a class share a cell (greedy over the face order)
+    // colour classes for the coloured accumulation: no two faces of a class share a
+    // cell.  Faces are the edges of the cell graph (a wall face an edge to a ghost of
+    // its own), whose largest degree is 4; colour_edges uses 4 classes when the graph
+    // is bipartite (Koenig's theorem) and at most 5 otherwise (Vizing's theorem).
     std::vector<int8_t> colour(nf, 0);
     int ncol = 1;
-    {
-        std::vector<uint32_t> used(nc, 0);
+    if (prm.accumulation == HGKS_ACC_COLOURED) {
+        std::vector<int32_t> eu(nf), ev(nf);
+        int32_t ghost = (int32_t)nc;
         for (int64_t f = 0; f < nf; ++f) {
-            const int32_t l = faces[f].l, r = faces[f].r;
-            uint32_t m = used[l] | (r >= 0 ? used[r] : 0u);
-            int k = 0;
-            while (m & (1u << k)) ++k;
-            colour[f] = (int8_t)k;
-            used[l] |= 1u << k;
-            if (r >= 0) used[r] |= 1u << k;
-            ncol = std::max(ncol, k + 1);
+            eu[f] = faces[f].l;
+            ev[f] = faces[f].r >= 0 ? faces[f].r : ghost++;
+        }
+        ncol = colour_edges(ghost, eu, ev, colour);
+        if (ncol < 0) {
+            err = "internal error: face colouring";
+            return HGKS_E_BAD_MESH;
         }
     }
     std::vector<int64_t> forder(nf);
@@ -635,20 +788,22 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                 cr = cen[ro] + shift;
                 if (!(dot(nrm, cr - fc) > 0.0)) bad = 5;   // both cells on one side: overlapping / folded
             }
-            double *g = &out.fgeo[0];
-            g[0 * (size_t)nf + k] = nrm.x;
-            g[1 * (size_t)nf + k] = nrm.y;
-            g[2 * (size_t)nf + k] = nrm.z;
-            g[3 * (size_t)nf + k] = 0.5 * len;
+            // value v of face k sits in pair row v/2, lane v%2
+            auto put = [&](int v, double x) { out.fgeo[((size_t)(v / 2) * nf + k) * 2 + (v & 1)] = x; };
+            put(0, nrm.x);
+            put(1, nrm.y);
+            put(2, nrm.z);
+            put(3, 0.5 * len);
             for (int q = 0; q < 3; ++q) {
                 // 3-point degree-2 rule: barycentric permutations of (2/3, 1/6, 1/6)
                 V3 xg = (2.0 / 3.0) * tri[q] + (1.0 / 6.0) * (tri[(q + 1) % 3] + tri[(q + 2) % 3]);
-                V3 yl = xg - cen[lo], yr = xg - cr;
-                for (int a = 0; a < 3; ++a) {
-                    g[(size_t)(4 + 3 * q + a) * nf + k] = comp(yl, a);
-                    g[(size_t)(13 + 3 * q + a) * nf + k] = comp(yr, a);
-                }
+                V3 yl = xg - cen[lo];
+                for (int a = 0; a < 3; ++a) put(4 + 3 * q + a, comp(yl, a));
             }
+            // left minus right centroid: a point's offset from the right centroid is its
+            // left offset plus this (zero at a wall: cr is the wall cell's own centroid)
+            V3 dlr = cen[lo] - cr;
+            for (int a = 0; a < 3; ++a) put(13 + a, comp(dlr, a));
         }
     });
     if (bad == 5) {
@@ -669,8 +824,8 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             for (int p = 0; p < 4; ++p) {
                 const int32_t code = out.cface[(size_t)p * nc + c];
                 const int64_t k = code >> 1;
-                const double sS = (code & 1 ? -1.0 : 1.0) * out.fgeo[3 * (size_t)nf + k];
-                for (int a = 0; a < 3; ++a) acc[a] += out.fgeo[(size_t)a * nf + k] * sS;
+                const double sS = (code & 1 ? -1.0 : 1.0) * out.fgeo[((size_t)1 * nf + k) * 2 + 1];
+                for (int a = 0; a < 3; ++a) acc[a] += out.fgeo[((size_t)(a / 2) * nf + k) * 2 + (a & 1)] * sS;
             }
             for (int a = 0; a < 3; ++a) lmax = std::max(lmax, std::fabs(acc[a]));
         }

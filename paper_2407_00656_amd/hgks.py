@@ -98,12 +98,19 @@ def _f64(a, shape=None):
     return a.reshape(shape) if shape is not None else a
 
 
+OWN_STREAM = "own"
+
+
 def _stream_handle(stream):
+    """None: the device's null stream; "own": a stream the context (pool) creates and
+    destroys (HGKS_OWN_STREAM); an int: a hipStream_t handle."""
     if stream is None:
         return None
+    if stream == OWN_STREAM:
+        return 1
     if isinstance(stream, int):
         return stream
-    return int(stream.cuda_stream)      # a torch.cuda.Stream
+    raise TypeError(f"stream must be None, 'own' or a hipStream_t handle, got {stream!r}")
 
 
 class Solver:

@@ -3,8 +3,9 @@
 Requests arrive over wall-clock time (Poisson), each carrying its payload: the
 mesh (nodes and cells) and the initial state, which the client generated
 beforehand (`make_payloads`, outside the timed run).  An arrived request is
-prepared on a host worker thread: its mesh is uploaded (the host precompute runs
-there, overlapping the GPU) and its initial state is set.  A
+prepared on a host worker thread: its mesh is uploaded on a stream of its own
+(the host precompute runs there, and the copies overlap the pool's steps on the
+device) and its initial state is set.  A
 prepared request is admitted into the pool once its device footprint fits the
 HBM budget.  Every tick advances all admitted requests together by K steps,
 with one launch per phase covering every slot's tiles
@@ -58,7 +59,8 @@ def make_payloads(requests, npts: int = 3, workers: int = 8) -> dict:
 def _prepare(job: Job, payload):
     r = job.req
     mesh, q0 = payload
-    s = hgks.Solver(hgks.params(precision=r.precision))
+    # each request uploads on a stream of its own, so its copies overlap the pool's steps
+    s = hgks.Solver(hgks.params(precision=r.precision), stream=hgks.OWN_STREAM)
     s.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period)
     s.init_state(q0)
     job.mesh, job.q0, job.solver = mesh, q0, s
@@ -72,7 +74,7 @@ def run(requests, hbm_budget: int, max_steps_per_tick: int = 20, workers: int = 
     if payloads is None:
         payloads = make_payloads(requests, npts)
     jobs = sorted((Job(r) for r in requests), key=lambda j: j.req.arrival)
-    pool = hgks.Pool(hbm_budget=hbm_budget)
+    pool = hgks.Pool(hbm_budget=hbm_budget, stream=hgks.OWN_STREAM)
     exe = ThreadPoolExecutor(max_workers=workers)
     lock = threading.Lock()
     prepared = []                   # jobs ready for admission (arrival order)
@@ -91,63 +93,73 @@ def run(requests, hbm_budget: int, max_steps_per_tick: int = 20, workers: int = 
         with lock:
             prepared.append(job)
 
-    while len(finished) < len(jobs):
-        now = time.perf_counter() - t0
-        while nxt < len(jobs) and jobs[nxt].req.arrival <= now:
-            j = jobs[nxt]
-            j.t_arrive = j.req.arrival
-            f = exe.submit(_prepare, j, payloads[j.req.rid])
-            f.add_done_callback(on_ready)
-            futures.append(f)
-            nxt += 1
-        # admit prepared jobs in arrival order while they fit
-        with lock:
-            prepared.sort(key=lambda j: j.req.arrival)
-            waiting = []
-            for j in prepared:
-                used, _ = pool.used()
-                if hbm_budget and used + j.solver.footprint() > hbm_budget:
-                    if not active and j.solver.footprint() > hbm_budget:
-                        raise ValueError(f"request {j.req.rid} needs {j.solver.footprint()} B, over the budget")
-                    waiting.append(j)
-                    continue
-                j.slot = pool.add(j.solver)
-                j.t_admit = time.perf_counter() - t0
-                active[j.slot] = j
-            prepared[:] = waiting
-        if not active:
-            for f in futures:
-                if f.done() and f.exception() is not None:
-                    raise f.exception()
-            time.sleep(0.002)
-            continue
-        k = min(max_steps_per_tick, min(j.req.steps - j.done for j in active.values()))
-        slots = sorted(active)
-        tb = time.perf_counter()
-        pool.step(slots, k)
-        next(iter(active.values())).solver.sync()      # waits for the pool's stream
-        busy_s += time.perf_counter() - tb
-        ticks += 1
-        for s_ in slots:
-            j = active[s_]
-            j.done += k
-            cell_updates += k * j.mesh.n_cells
-        for s_ in slots:
-            j = active[s_]
-            if j.done >= j.req.steps:
-                j.q, j.t_sim = j.solver.get_state()
-                pool.remove(s_)
-                del active[s_]
-                j.t_finish = time.perf_counter() - t0
-                j.solver.close()
-                j.solver = None
-                finished.append(j)
-                if log:
-                    log(f"done rid={j.req.rid} n={j.req.n} prec={j.req.precision} "
-                        f"latency={j.t_finish - j.t_arrive:.3f}s")
-    makespan = time.perf_counter() - t0
-    exe.shutdown()
-    pool.close()
+    try:
+        while len(finished) < len(jobs):
+            now = time.perf_counter() - t0
+            while nxt < len(jobs) and jobs[nxt].req.arrival <= now:
+                j = jobs[nxt]
+                j.t_arrive = j.req.arrival
+                f = exe.submit(_prepare, j, payloads[j.req.rid])
+                f.add_done_callback(on_ready)
+                futures.append(f)
+                nxt += 1
+            # admit prepared jobs in arrival order while they fit
+            with lock:
+                prepared.sort(key=lambda j: j.req.arrival)
+                waiting = []
+                for j in prepared:
+                    used, _ = pool.used()
+                    if hbm_budget and used + j.solver.footprint() > hbm_budget:
+                        if not active and j.solver.footprint() > hbm_budget:
+                            raise ValueError(f"request {j.req.rid} needs {j.solver.footprint()} B, over the budget")
+                        waiting.append(j)
+                        continue
+                    j.slot = pool.add(j.solver)
+                    j.t_admit = time.perf_counter() - t0
+                    active[j.slot] = j
+                prepared[:] = waiting
+            if not active:
+                for f in futures:
+                    if f.done() and f.exception() is not None:
+                        raise f.exception()
+                time.sleep(0.002)
+                continue
+            k = min(max_steps_per_tick, min(j.req.steps - j.done for j in active.values()))
+            slots = sorted(active)
+            tb = time.perf_counter()
+            pool.step(slots, k)
+            next(iter(active.values())).solver.sync()      # waits for the pool's stream
+            busy_s += time.perf_counter() - tb
+            ticks += 1
+            for s_ in slots:
+                j = active[s_]
+                j.done += k
+                cell_updates += k * j.mesh.n_cells
+            for s_ in slots:
+                j = active[s_]
+                if j.done >= j.req.steps:
+                    j.q, j.t_sim = j.solver.get_state()
+                    pool.remove(s_)
+                    del active[s_]
+                    j.t_finish = time.perf_counter() - t0
+                    j.solver.close()
+                    j.solver = None
+                    finished.append(j)
+                    if log:
+                        log(f"done rid={j.req.rid} n={j.req.n} prec={j.req.precision} "
+                            f"latency={j.t_finish - j.t_arrive:.3f}s")
+        makespan = time.perf_counter() - t0
+    finally:
+        # on any exit the pool lets go of its slots before a solver can be freed
+        exe.shutdown(wait=True)
+        for s_ in list(active):
+            pool.remove(s_)
+        pool.close()
+        for f in futures:
+            if f.done() and f.exception() is None:
+                j = f.result()
+                if j.solver is not None and j not in finished:
+                    j.solver.close()
     lat = np.array([j.t_finish - j.t_arrive for j in finished])
     return {
         "requests": len(finished),

@@ -18,6 +18,7 @@ forms also report their relative L1 difference from FP64.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import sys
 import time
@@ -51,7 +52,9 @@ def run(mesh, q0, precision, t_end, chunk=20, log=print, profile=True):
             s.step(chunk)                     # no host synchronisation inside a chunk
             steps += chunk
         elif rest > dt:
-            dt = s.step(1, want_dt=True)
+            # the last stretch in equal fixed steps, each at most 0.99 of the last CFL
+            # step, so that no step overshoots t_end even if the CFL step would grow
+            s.step(1, dt_fixed=rest / math.ceil(rest / (0.99 * dt)))
             steps += 1
         else:
             s.step(1, dt_fixed=rest)          # land on t_end (rest <= the CFL step)

@@ -24,6 +24,20 @@ def rel_l1(q, q_ref, vol):
     return np.sum(np.abs(q - q_ref) * vol[:, None], axis=0) / np.sum(np.abs(q_ref) * vol[:, None], axis=0)
 
 
+def rel_l1_scaled(q, q_ref, vol, gamma=1.4):
+    """Volume-weighted L1 of the difference per variable, relative to the L1 of the
+    reference for rho and rho E, and for each momentum component to the L1 of a
+    momentum scale per cell, max(|rho U|, rho c), so that a component that is zero or
+    small in the flow is not measured against itself."""
+    q_ref = np.asarray(q_ref)
+    rho = q_ref[:, 0]
+    m = q_ref[:, 1:4]
+    p = (gamma - 1) * (q_ref[:, 4] - 0.5 * np.sum(m * m, axis=1) / rho)
+    ms = np.maximum(np.sqrt(np.sum(m * m, axis=1)), rho * np.sqrt(gamma * np.abs(p) / rho))
+    den = np.array([np.sum(np.abs(rho) * vol), *(3 * [np.sum(ms * vol)]), np.sum(np.abs(q_ref[:, 4]) * vol)])
+    return np.sum(np.abs(np.asarray(q) - q_ref) * vol[:, None], axis=0) / den
+
+
 def advection_case(n, seed=None, **kw):
     mesh = W.kuhn_box(n, seed=W.SEED_ADVECTION if seed is None else seed)
     case = W.AdvectionCase(**kw)

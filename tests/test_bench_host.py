@@ -27,6 +27,6 @@ def test_weno_algorithmic_bytes(mixed, pinv32, per_cell):
 
 def test_flux_and_update_algorithmic_bytes():
     nc, nf = 1000, 2000
-    # the mean of 264 (first stage) and 224 (second stage, dF only) per face
-    assert bench.algorithmic_bytes("flux", nc, nf, False) == nf * 244 + nc * 400
+    # the mean of 216 (first stage) and 176 (second stage, dF only) per face
+    assert bench.algorithmic_bytes("flux", nc, nf, False) == nf * 196 + nc * 400
     assert bench.algorithmic_bytes("update", nc, nf, False) == nc * 292

@@ -63,10 +63,20 @@ def test_renumbering_is_off_when_asked():
     assert np.array_equal(r["perm"], np.arange(m.n_cells))
 
 
-def test_colouring_classes_share_no_cell():
-    m = W.kuhn_box(6)
+@pytest.mark.parametrize("n,periodic,colours", [(6, (True, True, True), 4), (8, (True, True, True), 4),
+                                                 (5, (True, True, True), 5), (7, (True, True, True), 5),
+                                                 ((6, 6, 4), (False, True, True), 4),
+                                                 ((5, 6, 7), (False, False, True), 5)])
+def test_colouring_uses_koenig_and_vizing_bounds(n, periodic, colours):
+    """Face colour classes (no two faces of a class share a cell; the library checks
+    every class before it returns): the cell graph of a Kuhn box has degree 4, and is
+    bipartite when every periodic axis has an even cube count, so Koenig's theorem
+    gives 4 classes there; otherwise the fan method gives at most 5 (Vizing)."""
+    m = W.kuhn_box(n, periodic=periodic)
     r = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period, hgks.params(accumulation=hgks.ACC_COLOURED))
-    assert 4 <= r["stats"]["n_colours"] <= 7
+    assert r["stats"]["n_colours"] == colours
+    plain = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period)
+    assert plain["stats"]["n_colours"] == 1          # the gather accumulation needs no classes
 
 
 def test_bad_meshes_are_rejected():

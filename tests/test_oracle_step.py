@@ -99,9 +99,35 @@ def test_paper_table_norms_are_consistently_scaled():
 
 
 @pytest.mark.slow
-def test_design_order_of_accuracy():
-    """Smooth advection at a common final time with dt ~ h: the observed order rises
-    towards 3 (the paper's tet orders are 2.92-3.00, Sec. 5.1)."""
+def test_design_order_on_regular_kuhn_meshes():
+    """The design order 3 (Sec. 5.1, accuracy table for tetrahedral meshes: 2.92-3.00):
+    smooth advection on the six-tetrahedra split of N^3 cubes without jitter, N = 16,
+    24, 32, at a common final time T = 0.05 with dt = T / (0.75 N) (CFL about 0.23);
+    the L1 density error against the exact cell averages gives orders in [2.85, 3.15]
+    for both refinements (measured 2.97 and 2.89).  A dropped term in the reconstruction,
+    the flux time expansion or the S2O4 update shows up here as order 2 or lower."""
+    case = W.AdvectionCase()
+    T = 0.05
+    res = []
+    for n in (16, 24, 32):
+        m = W.kuhn_box(n, jitter=0.0)
+        om = O.Mesh.from_workload(m)
+        vol = om.cells()[0]
+        steps = int(round(0.75 * n))
+        qT, _ = om.step(case.conservative(m), steps, T / steps)
+        e = W.error_norms(vol, qT[:, 0], case.density_average(m, T))
+        res.append((n, e["L1"]))
+    orders = [math.log(a[1] / b[1]) / math.log(b[0] / a[0]) for a, b in zip(res, res[1:])]
+    assert all(2.85 <= o <= 3.15 for o in orders), orders
+
+
+@pytest.mark.slow
+def test_order_of_accuracy_on_jittered_meshes():
+    """The same on the jittered meshes of the workload (nodes moved by up to 10% of h),
+    at N = 8, 12, 16 and T = 0.1: the errors fall at better than second order and the
+    observed order rises (2.74 then 2.87).  On the jittered N = 16/24/32 meshes at
+    T = 0.05 it is 2.84 and 2.72 (2.86 and 2.84 with linear weights): random node
+    displacements keep the order below 3 at these resolutions, weights or not."""
     case = W.AdvectionCase()
     T = 0.1
     res = []
