@@ -58,16 +58,19 @@ typedef enum {
                                  (with tau > 0, Gauss points across a shock, where the
                                  two sides differ by more than 30%, are evaluated in
                                  FP64) */,
-    HGKS_FP32 = 2             /* the FP32-mixed form with the big-stencil pseudo-inverse
-                                 stored in FP32 (each coefficient rounded once at
-                                 mesh upload, half its bytes) and contracted in FP32;
-                                 the sub-stencil fits are formed in FP32 from FP64
-                                 centroid offsets and contracted in FP32, and the
-                                 stencil differences are formed in FP64 and rounded
-                                 once.  This is the storage and arithmetic side of the
-                                 single-precision build of Sec. 5.1 (memory and speed
-                                 against FP64), taken where it carries the bytes; the
-                                 state, geometry, accumulation and update stay FP64 */
+    HGKS_FP32 = 2             /* the single-precision build (Sec. 5.1, the memory and time
+                                 comparison of FP32 against FP64): the state (Q^n, Q*, and
+                                 the stage-2 base), the cell and face geometry, the face
+                                 fluxes and the accumulators are stored in FP32, and so is
+                                 the big-stencil pseudo-inverse (each value rounded once);
+                                 both WENO contractions, the sub-stencil fits, the weights
+                                 and the gas-kinetic flux run in FP32 (tau > 0 Gauss points
+                                 across a shock in FP64, as in the FP32-mixed form).  The
+                                 few operations of the stage update run in FP64 registers
+                                 on FP32 operands and are rounded once on store; dt and the
+                                 time stay FP64, and so do the centroids the sub-stencil
+                                 fits are formed from.  About half the device memory of
+                                 FP64 */
 } hgks_precision;
 
 typedef enum {
@@ -215,7 +218,7 @@ typedef struct hgks_pool hgks_pool;
  * hip_stream as in hgks_create (HGKS_OWN_STREAM: the pool's own stream). */
 hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hgks_pool **out);
 /* Bytes a context with this mesh size will hold (used for admission; exact for a
- * periodic mesh, wall faces add 8 + 128 + 80 bytes each).  HGKS_E_INVALID_ARG for
+ * periodic mesh, wall faces add 8 + 128 + 80 bytes each, 8 + 64 + 40 in the FP32 form).  HGKS_E_INVALID_ARG for
  * parameters hgks_create would reject, n_cells <= 0 or nodes_per_cell != 4. */
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int nodes_per_cell, size_t *bytes);
 /* Adds a context (mesh uploaded, state initialised); returns its slot id.  A context

@@ -17,7 +17,7 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
-CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-pthread", "-D__HIP_PLATFORM_AMD__",
+CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-pthread", "-D__HIP_PLATFORM_AMD__",
              f"-I{ROCM}/include"]
 
 

@@ -44,6 +44,9 @@ struct Layout {
 
 Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, int prec, bool coloured) {
     const bool mixed = prec != HGKS_FP64;
+    // the FP32 form stores the state, the cell and face geometry and the face fluxes
+    // in FP32 (es = 4): the same row layouts with half the element size
+    const size_t es = prec == HGKS_FP32 ? 4 : 8;
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t p = o; o += up(bytes); return p; };
@@ -51,17 +54,17 @@ Layout layout_for(int64_t nc, int64_t nf, int n_ctiles, int n_ftiles, int prec, 
     L.pinv0 = take((size_t)144 * nc * (prec == HGKS_FP32 ? 4 : 8));
     L.cen = take((size_t)3 * nc * 8);
     L.sshift = take((size_t)4 * nc * 4);
-    L.cgeo = take((size_t)CGEO * nc * 8);
+    L.cgeo = take((size_t)CGEO * nc * es);
     L.cface = take((size_t)4 * nc * 4);
     L.fcell = take((size_t)2 * nf * 4);
-    L.fgeo = take((size_t)FGEO * nf * 8);
-    L.Q = take((size_t)5 * nc * 8);
-    L.Qs = take((size_t)5 * nc * 8);
-    L.R = take((size_t)5 * nc * 8);
+    L.fgeo = take((size_t)FGEO * nf * es);
+    L.Q = take((size_t)5 * nc * es);
+    L.Qs = take((size_t)5 * nc * es);
+    L.R = take((size_t)5 * nc * es);
     L.C = take(mixed ? 0 : (size_t)5 * NCOEF * nc * 8);
     L.C32 = take(mixed ? (size_t)5 * NCOEF * nc * 4 : 0);
-    L.FF = take(coloured ? 0 : (size_t)10 * nf * 8);
-    L.acc = take(coloured ? (size_t)10 * nc * 8 : 0);
+    L.FF = take(coloured ? 0 : (size_t)10 * nf * es);
+    L.acc = take(coloured ? (size_t)10 * nc * es : 0);
     L.dtpart = take((size_t)n_ctiles * 8);
     L.scal = take(64);
     L.desc = take(sizeof(ProbDesc));
@@ -206,12 +209,12 @@ void enqueue_step(hgks_ctx *c, double dt_fixed) {
         if (col) {
             for (size_t k = 0; k + 1 < c->colour_tiles.size(); ++k) {
                 int t0 = c->colour_tiles[k], t1 = c->colour_tiles[k + 1];
-                timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles + t0, t1 - t0, stage, mixed, tau0, true, c->walls, s); });
+                timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles + t0, t1 - t0, stage, prec, tau0, true, c->walls, s); });
             }
         } else {
-            timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles, c->n_ftiles, stage, mixed, tau0, false, c->walls, s); });
+            timed(c, 2, [&] { launch_flux(c->d_desc, 1, c->d_ftiles, c->n_ftiles, stage, prec, tau0, false, c->walls, s); });
         }
-        timed(c, 3, [&] { launch_update(c->d_desc, c->d_ctiles, c->n_ctiles, stage, col, s); });
+        timed(c, 3, [&] { launch_update(c->d_desc, c->d_ctiles, c->n_ctiles, stage, col, prec == HGKS_FP32, s); });
     }
 }
 
@@ -380,14 +383,25 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     }
     HIPCHK(c, h2d(D.cen, hm.cen.data(), hm.cen.size() * 8));
     HIPCHK(c, h2d(D.sshift, hm.sshift.data(), hm.sshift.size() * 4));
-    HIPCHK(c, h2d(D.cgeo, hm.cgeo.data(), hm.cgeo.size() * 8));
+    const bool s32 = prec == HGKS_FP32;
+    std::vector<float> cg32, fg32;            // the FP32 form's geometry, each value rounded once
+    if (s32) {
+        cg32.assign(hm.cgeo.begin(), hm.cgeo.end());
+        fg32.assign(hm.fgeo.begin(), hm.fgeo.end());
+        HIPCHK(c, h2d(D.cgeo, cg32.data(), cg32.size() * 4));
+    } else {
+        HIPCHK(c, h2d(D.cgeo, hm.cgeo.data(), hm.cgeo.size() * 8));
+    }
     HIPCHK(c, h2d(D.cface, hm.cface.data(), hm.cface.size() * 4));
     HIPCHK(c, h2d(D.fcell, hm.fcell.data(), hm.fcell.size() * 4));
-    HIPCHK(c, h2d(D.fgeo, hm.fgeo.data(), hm.fgeo.size() * 8));
+    if (s32)
+        HIPCHK(c, h2d(D.fgeo, fg32.data(), fg32.size() * 4));
+    else
+        HIPCHK(c, h2d(D.fgeo, hm.fgeo.data(), hm.fgeo.size() * 8));
     HIPCHK(c, h2d(c->d_desc, &D, sizeof(ProbDesc)));
     HIPCHK(c, h2d(c->d_ctiles, ct.data(), ct.size() * sizeof(Tile)));
     HIPCHK(c, h2d(c->d_ftiles, ft.data(), ft.size() * sizeof(Tile)));
-    if (col) launch_fill(D.acc, 0.0, (int64_t)10 * hm.nc, s);
+    if (col) launch_fill(D.acc, 0.0, (int64_t)(s32 ? 5 : 10) * hm.nc, s);   // zero bits: 0.0 in either size
     HIPCHK(c, hipStreamSynchronize(s));
     c->nc = hm.nc;
     c->nf = hm.nf;
@@ -418,10 +432,17 @@ hgks_status hgks_init_state(hgks_ctx *c, const double *q, double t0) {
     HIPCHK(c, hipSetDevice(c->device));
     double scal[3] = {0.0, t0, 0.0};
     int32_t zero[2] = {0, 0};     // non-physical flag, flux fix-up flag
-    HIPCHK(c, hipMemcpyAsync(c->desc.Q, soa.data(), soa.size() * 8, hipMemcpyHostToDevice, c->stream));
+    const bool s32 = c->prm.precision == HGKS_FP32;
+    std::vector<float> soa32;
+    if (s32) {                    // the FP32 form's state: each value rounded once
+        soa32.assign(soa.begin(), soa.end());
+        HIPCHK(c, hipMemcpyAsync(c->desc.Q, soa32.data(), soa32.size() * 4, hipMemcpyHostToDevice, c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->desc.Q, soa.data(), soa.size() * 8, hipMemcpyHostToDevice, c->stream));
+    }
     HIPCHK(c, hipMemcpyAsync(c->desc.dt, scal, 16, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->desc.flag, zero, 8, hipMemcpyHostToDevice, c->stream));
-    launch_dt_local(c->d_desc, c->d_ctiles, c->n_ctiles, c->stream);
+    launch_dt_local(c->d_desc, c->d_ctiles, c->n_ctiles, s32, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->has_state = true;
@@ -470,7 +491,13 @@ hgks_status hgks_get_state(hgks_ctx *c, double *q_out, double *t_out) {
     const int64_t nc = c->nc;
     if (q_out) {
         std::vector<double> soa((size_t)5 * nc);
-        HIPCHK(c, hipMemcpy(soa.data(), c->desc.Q, soa.size() * 8, hipMemcpyDeviceToHost));
+        if (c->prm.precision == HGKS_FP32) {
+            std::vector<float> soa32((size_t)5 * nc);
+            HIPCHK(c, hipMemcpy(soa32.data(), c->desc.Q, soa32.size() * 4, hipMemcpyDeviceToHost));
+            soa.assign(soa32.begin(), soa32.end());
+        } else {
+            HIPCHK(c, hipMemcpy(soa.data(), c->desc.Q, soa.size() * 8, hipMemcpyDeviceToHost));
+        }
         for (int64_t i = 0; i < nc; ++i)
             for (int v = 0; v < 5; ++v) q_out[5 * c->perm[i] + v] = soa[(size_t)v * nc + i];
     }
@@ -547,7 +574,7 @@ hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const 
     if (check_params(&p) != HGKS_OK) return HGKS_E_INVALID_ARG;
     HostMesh hm;
     std::string err;
-    hgks_status st = build_mesh(p, n_nodes, xyz, n_cells, npc, cell_nodes, period, hm, err);
+    hgks_status st = build_mesh(p, n_nodes, xyz, n_cells, npc, cell_nodes, period, hm, err, true);
     if (st != HGKS_OK) return st;
     if (stats) {
         stats[0] = (double)hm.nf;
@@ -698,8 +725,14 @@ void enqueue_pool_steps(const ProbDesc *probs, int nprobs, const Tile *ct, int n
         for (int stage = 1; stage <= 2; ++stage) {
             for (auto &g : groups) launch_weno(probs, ct + g.c0, g.c1 - g.c0, stage, g.prec, g.walls, s);
             for (auto &g : groups)
-                launch_flux(probs, nprobs, ft + g.f0, g.f1 - g.f0, stage, g.prec != HGKS_FP64, g.tau0, false, g.walls, s);
-            launch_update(probs, ct, n_ct, stage, false, s);
+                launch_flux(probs, nprobs, ft + g.f0, g.f1 - g.f0, stage, g.prec, g.tau0, false, g.walls, s);
+            // groups run FP64, FP32-mixed, FP32: the FP32 form's cells (FP32 storage) are
+            // the last tiles, updated by their own launch
+            int c32 = n_ct;
+            for (auto &g : groups)
+                if (g.prec == HGKS_FP32) c32 = std::min(c32, g.c0);
+            launch_update(probs, ct, c32, stage, false, false, s);
+            launch_update(probs, ct + c32, n_ct - c32, stage, false, true, s);
         }
     }
 }

@@ -104,9 +104,10 @@ struct HostMesh {
 };
 
 // Builds the device-ready arrays on the host.  Returns HGKS_OK or an error with `err` set.
+// diagnostics: also measure max |P A - I| of the big-stencil pseudo-inverses (inspection).
 hgks_status build_mesh(const hgks_params &prm, int64_t n_nodes, const double *xyz, int64_t n_cells,
                        int nodes_per_cell, const int64_t *cell_nodes, const double *period,
-                       HostMesh &out, std::string &err);
+                       HostMesh &out, std::string &err, bool diagnostics = false);
 
 int host_threads();
 

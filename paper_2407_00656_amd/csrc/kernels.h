@@ -56,10 +56,13 @@ constexpr int UPD_TILE = 64;     // cells per update / dt workgroup
 // prec: 0 FP64, 1 FP32-mixed, 2 FP32 (the hgks_precision values)
 void launch_weno(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, int prec, bool walls,
                  hipStream_t s);
-void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0,
+// prec as for launch_weno: 2 means FP32 state, geometry and face-flux storage
+void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, int prec, bool tau0,
                  bool coloured, bool walls, hipStream_t s);
-void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, hipStream_t s);
-void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, hipStream_t s);
+// s32: the FP32 form's storage (state, cell geometry, face fluxes in FP32)
+void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, bool s32,
+                   hipStream_t s);
+void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, bool s32, hipStream_t s);
 void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
 

@@ -126,6 +126,22 @@ __device__ __forceinline__ float hg_rsqrt(float x) { return __builtin_amdgcn_rsq
 __device__ __forceinline__ double hg_rsq_raw(double x) { return __builtin_amdgcn_rsq(x); }
 __device__ __forceinline__ float hg_rsq_raw(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Storage of the state (Q, Q*, R), the cell geometry, the face fluxes and the
+// coloured accumulators: FP64, or FP32 in the FP32 form (S32).  Arrays keep their
+// row layout [rows][n]; only the element size changes.  Values are handled as
+// double in registers and rounded once when stored.
+template <bool S32>
+struct Sto {
+    using E = std::conditional_t<S32, float, double>;
+    static constexpr uint32_t SZ = (uint32_t)sizeof(E);
+    __device__ static __forceinline__ double ld(const double *base, size_t row, uint32_t n, uint32_t i) {
+        return (double)ldg<E>(reinterpret_cast<const E *>(base) + row * n, i * SZ);
+    }
+    __device__ static __forceinline__ void st(double *base, size_t row, uint32_t n, uint32_t i, double v) {
+        stg<E>(reinterpret_cast<E *>(base) + row * n, i * SZ, (E)v);
+    }
+};
+
 // erfcx(a) = exp(a^2) erfc(a) for a >= 0: Chebyshev series in t = (a - k)/(a + k),
 // summed by Clenshaw's recurrence (the coefficients come from gen_erfcx_table.py).
 template <class T>
@@ -378,7 +394,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
             sid[e / WC][e % WC] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
         if (F32 && threadIdx.x < 7u * WC)
             sgeo[threadIdx.x / WC][threadIdx.x % WC] =
-                ldg<double>(P.cgeo + (size_t)(threadIdx.x / WC) * nc, min(c0 + threadIdx.x % WC, last) * 8u);
+                Sto<F32>::ld(P.cgeo, threadIdx.x / WC, nc, min(c0 + threadIdx.x % WC, last));
         __syncthreads();
     }
     // 2. the sub-stencil fits: thread (m, c) for m < 4.  The FP32 form stages them
@@ -413,17 +429,19 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     const uint32_t i0 = c0 + cl;
     const bool ok = active && i0 <= last;
     const uint32_t i = min(i0, last);
-    const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)(active ? v : 0u) * nc;
+    // the state: FP64, or FP32 in the FP32 form
+    const double *Qb = stage == 1 ? P.Q : P.Qs;
+    const uint32_t vrow = active ? v : 0u;
     double qi = 0.0, geo[7];
     DT d[SLOTS];
     if (active) {
-        qi = ldg<double>(Qv, i * 8u);
+        qi = Sto<F32>::ld(Qb, vrow, nc, i);
 #pragma unroll
         for (int q = 0; q < 7; ++q) geo[q] = F32 ? sgeo[q][cl] : ldg<double>(P.cgeo + (size_t)q * nc, i * 8u);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             const uint32_t j = (uint32_t)sid[s][cl];
-            d[s] = (DT)(ldg<double>(Qv, j * 8u) - qi);   // the difference in FP64, then rounded once
+            d[s] = (DT)(Sto<F32>::ld(Qb, vrow, nc, j) - qi);   // the difference in FP64, then rounded once
         }
     }
     __syncthreads();
@@ -1001,18 +1019,18 @@ __device__ __forceinline__ bool finite_flux(const T F[5], const T dF[5]) {
     return s == T(0);
 }
 
-template <class T>
+template <class T, bool S32 = false>
 __device__ __forceinline__ void cell_mean(const ProbDesc &P, int stage, uint32_t c, T q[5]) {
     const double *Qa = stage == 1 ? P.Q : P.Qs;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) q[v] = (T)ldg<double>(Qa + (size_t)v * P.nc, c * 8u);
+    for (int v = 0; v < 5; ++v) q[v] = (T)Sto<S32>::ld(Qa, v, (uint32_t)P.nc, c);
 }
 
 // Value and gradient of a cell's reconstruction at offset y from its centroid;
 // ADD accumulates the gradient into g (tau = 0 needs only the sum of both sides).
 // REC32: the records are the FP32-mixed ones (FP32 coefficients, c0 the deviation from
 // the FP64 cell mean); they may be evaluated in FP64 (T = double).
-template <class T, bool ADD, bool REC32 = (sizeof(T) == 4)>
+template <class T, bool ADD, bool REC32 = (sizeof(T) == 4), bool S32 = false>
 __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32_t c, const T y[3], T q[5], T g[5][3]) {
     const uint32_t nc = (uint32_t)P.nc;
     const T yy[6] = {y[0] * y[0], y[1] * y[1], y[2] * y[2], y[0] * y[1], y[0] * y[2], y[1] * y[2]};
@@ -1037,8 +1055,8 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32
         if constexpr (!REC32) {
             q[v] = val;
         } else {
-            // FP32 form: FP64 cell mean plus the deviation, rounded once to T
-            const double mean = ldg<double>((stage == 1 ? P.Q : P.Qs) + (size_t)v * nc, c * 8u);
+            // FP32 records: the cell mean plus the deviation, rounded once to T
+            const double mean = Sto<S32>::ld(stage == 1 ? P.Q : P.Qs, v, nc, c);
             q[v] = (T)(mean + (double)val);
         }
         const T gx = cf[1] + T(2) * cf[4] * y[0] + cf[7] * y[1] + cf[8] * y[2];
@@ -1057,7 +1075,7 @@ __device__ __forceinline__ void recon_point(const ProbDesc &P, int stage, uint32
 // coefficient is loaded once per face.  ADD accumulates the gradients.
 // REFL: the gradient is reflected before it is added, g - refl (g.n) n (refl = 2 at a
 // wall face, 0 elsewhere; the ghost side of a wall face)
-template <class T, bool ADD, bool REFL = false>
+template <class T, bool ADD, bool REFL = false, bool S32 = false>
 __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t c, const T y[3][3], T q[3][5],
                                           T g[3][5][3], const T *nrm = nullptr, T refl = T(0)) {
     const uint32_t nc = (uint32_t)P.nc;
@@ -1077,7 +1095,7 @@ __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t
             }
         }
         double mean = 0.0;
-        if constexpr (sizeof(T) == 4) mean = ldg<double>((stage == 1 ? P.Q : P.Qs) + (size_t)v * nc, c * 8u);
+        if constexpr (sizeof(T) == 4) mean = Sto<S32>::ld(stage == 1 ? P.Q : P.Qs, v, nc, c);
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             const T *yp = y[p];
@@ -1116,36 +1134,67 @@ __device__ __forceinline__ void recon_gp3(const ProbDesc &P, int stage, uint32_t
 // applied).  A point's offset from the right centroid is its left offset plus that
 // difference; it is zero at a wall face, whose ghost side is evaluated at the wall
 // cell's own offsets.
+// (FP32 pairs in the FP32 form.)
+template <bool S32 = false>
 __device__ __forceinline__ void load_fgeo(const ProbDesc &P, uint32_t f, double v[16]) {
-    const d2 *g = reinterpret_cast<const d2 *>(P.fgeo);
     const size_t nf = (size_t)P.nf;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const d2 pr = ldg<d2>(g + k * nf, f * 16u);
-        v[2 * k] = pr.x;
-        v[2 * k + 1] = pr.y;
+        if constexpr (S32) {
+            const f2 pr = ldg<f2>(reinterpret_cast<const f2 *>(P.fgeo) + k * nf, f * 8u);
+            v[2 * k] = pr.x;
+            v[2 * k + 1] = pr.y;
+        } else {
+            const d2 pr = ldg<d2>(reinterpret_cast<const d2 *>(P.fgeo) + k * nf, f * 16u);
+            v[2 * k] = pr.x;
+            v[2 * k + 1] = pr.y;
+        }
     }
 }
+template <bool S32 = false>
 __device__ __forceinline__ double fgeo_area(const ProbDesc &P, uint32_t f) {
-    return ldg<double>(P.fgeo + (size_t)2 * P.nf, f * 16u + 8u);      // value 3: pair 1, lane 1
+    // value 3: pair 1, lane 1
+    if constexpr (S32) return (double)ldg<float>(reinterpret_cast<const float *>(P.fgeo) + (size_t)2 * P.nf, f * 8u + 4u);
+    else return ldg<double>(P.fgeo + (size_t)2 * P.nf, f * 16u + 8u);
 }
-// Gauss point p: offsets from the left and the right centroid
+// One value of a face's geometry record (v as above)
+template <bool S32 = false>
+__device__ __forceinline__ double fgeo_value(const ProbDesc &P, uint32_t f, uint32_t v) {
+    const size_t row = (size_t)(v >> 1) * 2 * (size_t)P.nf;       // pair row v/2, in elements
+    if constexpr (S32) return (double)ldg<float>(reinterpret_cast<const float *>(P.fgeo) + row, (f * 2u + (v & 1u)) * 4u);
+    else return ldg<double>(P.fgeo + row, (f * 2u + (v & 1u)) * 8u);
+}
+// The normal and the offsets of Gauss point g from both centroids, loading only
+// those nine values (for kernels that evaluate one point of a face per lane)
+template <class T, bool S32 = false>
+__device__ __forceinline__ void fgeo_gauss(const ProbDesc &P, uint32_t f, uint32_t g, T n[3], T yl[3], T yr[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        n[a] = (T)fgeo_value<S32>(P, f, (uint32_t)a);
+        const double y = fgeo_value<S32>(P, f, 4u + 3u * g + (uint32_t)a);
+        yl[a] = (T)y;
+        yr[a] = (T)(y + fgeo_value<S32>(P, f, 13u + (uint32_t)a));
+    }
+}
+// Gauss point p: offsets from the left and the right centroid (p may differ across
+// lanes: the point is selected, never indexed, so v stays in registers)
 template <class T>
 __device__ __forceinline__ void fgeo_point(const double v[16], int p, T yl[3], T yr[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        yl[a] = (T)v[4 + 3 * p + a];
-        yr[a] = (T)(v[4 + 3 * p + a] + v[13 + a]);
+        const double y = p == 0 ? v[4 + a] : (p == 1 ? v[7 + a] : v[10 + a]);
+        yl[a] = (T)y;
+        yr[a] = (T)(y + v[13 + a]);
     }
 }
 
 // The tau = 0 flux of face f with the positivity fallback, one Gauss point at a
 // time from reloaded inputs (only faces that need it come here).
-template <class T>
+template <class T, bool S32 = false>
 __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage, uint32_t f, uint32_t l,
                                                              uint32_t r, bool wall, double out[10]) {
     double fv[16];
-    load_fgeo(P, f, fv);
+    load_fgeo<S32>(P, f, fv);
     const T n[3] = {(T)fv[0], (T)fv[1], (T)fv[2]};
     const double w = fv[3] * (1.0 / 3.0);
 #pragma unroll 1
@@ -1153,21 +1202,21 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
         T yl[3], yr[3];
         fgeo_point(fv, p, yl, yr);
         T qL[5], qR[5], gs[5][3];
-        recon_point<T, false>(P, stage, l, yl, qL, gs);
-        recon_point<T, true>(P, stage, r, yr, qR, gs);
+        recon_point<T, false, (sizeof(T) == 4), S32>(P, stage, l, yl, qL, gs);
+        recon_point<T, true, (sizeof(T) == 4), S32>(P, stage, r, yr, qR, gs);
         if (wall) reflect_grad(gs, n, T(1));
         const bool okL = physical_point(qL), okR = physical_point(qR);
         if (!(okL && okR)) {
-            if (!okL) cell_mean(P, stage, l, qL);
-            if (!okR) cell_mean(P, stage, r, qR);
+            if (!okL) cell_mean<T, S32>(P, stage, l, qL);
+            if (!okR) cell_mean<T, S32>(P, stage, r, qR);
 #pragma unroll
             for (int v = 0; v < 5; ++v) gs[v][0] = gs[v][1] = gs[v][2] = T(0);
         }
         T F[5], dF[5];
         gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
         if (!finite_flux(F, dF)) {          // (FP32 form) a non-finite point flux: first order
-            cell_mean(P, stage, l, qL);
-            cell_mean(P, stage, r, qR);
+            cell_mean<T, S32>(P, stage, l, qL);
+            cell_mean<T, S32>(P, stage, r, qR);
 #pragma unroll
             for (int v = 0; v < 5; ++v) gs[v][0] = gs[v][1] = gs[v][2] = T(0);
             gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
@@ -1190,11 +1239,13 @@ __device__ __forceinline__ void flux_face_fallback(const ProbDesc &P, int stage,
 // of that stage does not use L(Q*).  The wall variants are held to two waves per
 // SIMD: left alone the FP64 one takes a few accumulation registers beyond 256 and
 // runs one wave (a few bytes of scratch per lane cost less than that).
-template <bool MIXED, bool COLOURED, bool WALLS, bool DF_ONLY = false>
+template <bool MIXED, bool COLOURED, bool WALLS, bool DF_ONLY = false, bool S32 = false>
 __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(COLOURED ? 1 : (MIXED ? 3 : 2)))) void
 k_flux_t0(const ProbDesc *__restrict__ probs,
                                                        const Tile *__restrict__ tiles, int stage) {
     static_assert(!(DF_ONLY && COLOURED), "the coloured mode accumulates both");
+    static_assert(MIXED || !S32, "FP32 storage comes with the FP32 flux");
+    using ST = Sto<S32>;
     using T = typename std::conditional<MIXED, float, double>::type;
     // tiles in reverse order: the reconstruction records written last by the WENO
     // pass are the likeliest still to sit in the last-level cache
@@ -1208,17 +1259,17 @@ k_flux_t0(const ProbDesc *__restrict__ probs,
     const bool wall = WALLS && rr < 0;           // the ghost side is l's record mirrored
     const uint32_t r = rr < 0 ? l : (uint32_t)rr;
     double fv[16];
-    load_fgeo(P, f, fv);
+    load_fgeo<S32>(P, f, fv);
     const T n[3] = {(T)fv[0], (T)fv[1], (T)fv[2]};
     const double S = fv[3];
     T yl[3][3], yr[3][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) fgeo_point(fv, p, yl[p], yr[p]);
     T qL[3][5], qR[3][5], gs[3][5][3];
-    recon_gp3<T, false>(P, stage, l, yl, qL, gs);
+    recon_gp3<T, false, false, S32>(P, stage, l, yl, qL, gs);
     // at a wall face the ghost side adds l's gradient reflected in the wall (branch-free:
     // a branch on the wall flag here costs the kernel half its occupancy)
-    recon_gp3<T, true, WALLS>(P, stage, r, yr, qR, gs, n, wall ? T(2) : T(0));
+    recon_gp3<T, true, WALLS, S32>(P, stage, r, yr, qR, gs, n, wall ? T(2) : T(0));
     const double w = S * (1.0 / 3.0);          // three Gauss points of equal weight
     double out[10];
 #pragma unroll
@@ -1232,16 +1283,16 @@ k_flux_t0(const ProbDesc *__restrict__ probs,
         }
     }
     if constexpr (COLOURED) {      // this mode accumulates at once: take the fallback inline
-        if (!(out[0] == out[0])) flux_face_fallback<T>(P, stage, f, l, r, wall, out);
+        if (!(out[0] == out[0])) flux_face_fallback<T, S32>(P, stage, f, l, r, wall, out);
     }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         if constexpr (COLOURED) {
-            double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
-            stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - out[k]);
-            if (!wall) stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + out[k]);
+            const uint32_t ncu = (uint32_t)P.nc;      // no other face of this colour touches l or r
+            ST::st(P.acc, k, ncu, l, ST::ld(P.acc, k, ncu, l) - out[k]);
+            if (!wall) ST::st(P.acc, k, ncu, r, ST::ld(P.acc, k, ncu, r) + out[k]);
         } else if (!DF_ONLY || k >= 5) {
-            stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
+            ST::st(P.FF, k, nf, f, out[k]);
         }
     }
     if constexpr (!COLOURED) {
@@ -1261,10 +1312,11 @@ k_flux_t0(const ProbDesc *__restrict__ probs,
 // Each workgroup (one wave) walks tiles with a grid stride, so the scan is a
 // few waves per SIMD reading one double per face; the recomputation is rare and
 // may use scratch memory.
-template <bool MIXED>
+template <bool MIXED, bool S32 = false>
 __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) void k_flux_fix(
     const ProbDesc *__restrict__ probs, int nprobs, const Tile *__restrict__ tiles, int ntiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
+    using ST = Sto<S32>;
     // one look at every problem's flag: nothing to do in any of them is the common case
     bool any = false;
     for (int k = threadIdx.x; k < nprobs; k += FACE_TILE) any = any || ldg<int32_t>(probs[k].flag, 4u) != 0;
@@ -1277,36 +1329,33 @@ __global__ __launch_bounds__(FACE_TILE) __attribute__((amdgpu_waves_per_eu(4))) 
         if (f >= (uint32_t)tl.end) continue;
         const uint32_t nf = (uint32_t)P.nf;
         // the first row of F, or in the second stage (F not stored) of dF
-        const double f0 = ldg<double>(P.FF + (stage == 1 ? 0 : (size_t)5 * nf), f * 8u);
+        const double f0 = ST::ld(P.FF, stage == 1 ? 0 : 5, nf, f);
         if (f0 - f0 == 0.0) continue;            // finite
         const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
         const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
         double out[10];
-        flux_face_fallback<T>(P, stage, f, l, rr < 0 ? l : (uint32_t)rr, rr < 0, out);
+        flux_face_fallback<T, S32>(P, stage, f, l, rr < 0 ? l : (uint32_t)rr, rr < 0, out);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
+        for (int k = 0; k < 10; ++k) ST::st(P.FF, k, nf, f, out[k]);
     }
 }
 
 // The tau > 0 flux at Gauss point g of face f (between cells l and r; wall: r = l and
 // the ghost side mirrored), in FP64.  MIXED: from the FP32-mixed records (the points
 // the FP32 pass leaves, and the coloured mode of the FP32-mixed form).
-template <bool MIXED, bool WALLS>
+template <bool MIXED, bool WALLS, bool S32 = false>
 __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
                                                 uint32_t r, bool wall, double Fo[5], double dFo[5]) {
-    double fv[16];
-    load_fgeo(P, f, fv);
-    const double nd[3] = {fv[0], fv[1], fv[2]};
-    double yld[3], yrd[3];
-    fgeo_point(fv, (int)g, yld, yrd);
+    double nd[3], yld[3], yrd[3];
+    fgeo_gauss<double, S32>(P, f, g, nd, yld, yrd);
     double qL[5], gL[5][3], qR[5], gR[5][3];
-    recon_point<double, false, MIXED>(P, stage, l, yld, qL, gL);
-    recon_point<double, false, MIXED>(P, stage, r, yrd, qR, gR);
+    recon_point<double, false, MIXED, S32>(P, stage, l, yld, qL, gL);
+    recon_point<double, false, MIXED, S32>(P, stage, r, yrd, qR, gR);
     if constexpr (WALLS) reflect_grad(gR, nd, wall ? 2.0 : 0.0);
     const bool okL = physical_point(qL), okR = physical_point(qR);
     if (!(okL && okR)) {
-        if (!okL) cell_mean(P, stage, l, qL);
-        if (!okR) cell_mean(P, stage, r, qR);
+        if (!okL) cell_mean<double, S32>(P, stage, l, qL);
+        if (!okR) cell_mean<double, S32>(P, stage, r, qR);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             gL[v][0] = gL[v][1] = gL[v][2] = 0.0;
@@ -1322,17 +1371,14 @@ __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, ui
 // finite, is left to the FP64 evaluation of the fix-up pass (returns false).  (An
 // FP32 evaluation at every point went non-physical next to a diaphragm on large
 // meshes; with the FP64 path taking the shock points both shock-tube layouts run.)
-template <bool WALLS>
+template <bool WALLS, bool S32 = false>
 __device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
                                                   uint32_t r, bool wall, double Fo[5], double dFo[5]) {
-    double fv[16];
-    load_fgeo(P, f, fv);
-    const float n[3] = {(float)fv[0], (float)fv[1], (float)fv[2]};
-    float yl[3], yr[3];
-    fgeo_point(fv, (int)g, yl, yr);
+    float n[3], yl[3], yr[3];
+    fgeo_gauss<float, S32>(P, f, g, n, yl, yr);
     float qL[5], gL[5][3], qR[5], gR[5][3];
-    recon_point<float, false>(P, stage, l, yl, qL, gL);
-    recon_point<float, false>(P, stage, r, yr, qR, gR);
+    recon_point<float, false, true, S32>(P, stage, l, yl, qL, gL);
+    recon_point<float, false, true, S32>(P, stage, r, yr, qR, gR);
     if constexpr (WALLS) reflect_grad(gR, n, wall ? 2.0f : 0.0f);
     if (!(physical_point(qL) && physical_point(qR))) return false;
     const float gm1 = (float)P.gamma - 1.0f;
@@ -1350,10 +1396,11 @@ __device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, 
     return true;
 }
 
-template <bool MIXED, bool TAU0, bool COLOURED, bool WALLS>
+template <bool MIXED, bool TAU0, bool COLOURED, bool WALLS, bool S32 = false>
 __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restrict__ probs,
                                                          const Tile *__restrict__ tiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
+    using ST = Sto<S32>;
     __shared__ double red[3][10][FACE_TILE];
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
@@ -1372,17 +1419,14 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
         const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
         wall = WALLS && rr < 0;                  // the ghost side is l's record mirrored
         r = rr < 0 ? l : (uint32_t)rr;
-        double fv[16];
-        load_fgeo(P, f, fv);
-        const T n[3] = {(T)fv[0], (T)fv[1], (T)fv[2]};
-        const double S = fv[3];
-        T yl[3], yr[3];
-        fgeo_point(fv, (int)g, yl, yr);
+        T n[3], yl[3], yr[3];
+        fgeo_gauss<T, S32>(P, f, (uint32_t)g, n, yl, yr);
+        const double S = fgeo_area<S32>(P, f);
         double Fo[5], dFo[5];
         if constexpr (TAU0) {
             T qL[5], qR[5], gs[5][3], F[5], dF[5];
-            recon_point<T, false>(P, stage, l, yl, qL, gs);
-            recon_point<T, true>(P, stage, r, yr, qR, gs);
+            recon_point<T, false, (sizeof(T) == 4), S32>(P, stage, l, yl, qL, gs);
+            recon_point<T, true, (sizeof(T) == 4), S32>(P, stage, r, yr, qR, gs);
             if constexpr (WALLS) reflect_grad(gs, n, wall ? T(1) : T(0));
             gks_flux_tau0<T>(qL, qR, gs, n, P, F, dF);
 #pragma unroll
@@ -1391,7 +1435,7 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
                 dFo[k] = (double)dF[k];
             }
         } else {
-            point_flux_full<MIXED, WALLS>(P, stage, f, (uint32_t)g, l, r, wall, Fo, dFo);
+            point_flux_full<MIXED, WALLS, S32>(P, stage, f, (uint32_t)g, l, r, wall, Fo, dFo);
         }
         const double w = S * (1.0 / 3.0);      // three Gauss points of equal weight
 #pragma unroll
@@ -1408,11 +1452,11 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
         for (int k = 0; k < 10; ++k) {
             const double s = red[0][k][lane] + red[1][k][lane] + red[2][k][lane];
             if constexpr (COLOURED) {
-                double *acc = P.acc + (size_t)k * P.nc;   // no other face of this colour touches l or r
-                stg<double>(acc, l * 8u, ldg<double>(acc, l * 8u) - s);
-                if (!wall) stg<double>(acc, r * 8u, ldg<double>(acc, r * 8u) + s);
+                const uint32_t ncu = (uint32_t)P.nc;     // no other face of this colour touches l or r
+                ST::st(P.acc, k, ncu, l, ST::ld(P.acc, k, ncu, l) - s);
+                if (!wall) ST::st(P.acc, k, ncu, r, ST::ld(P.acc, k, ncu, r) + s);
             } else {
-                stg<double>(P.FF + (size_t)k * nf, f * 8u, s);
+                ST::st(P.FF, k, nf, f, s);
             }
         }
     }
@@ -1424,9 +1468,10 @@ __global__ __launch_bounds__(3 * FACE_TILE) void k_flux(const ProbDesc *__restri
 // in the order (g0 + g1) + g2, as the three-wave kernel sums them.  At two waves per
 // SIMD a three-wave workgroup leaves a quarter of a CU's wave slots idle; single-wave
 // workgroups fill them all.
-template <bool MIXED, bool WALLS>
+template <bool MIXED, bool WALLS, bool S32 = false>
 __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ probs, const Tile *__restrict__ tiles,
                                                 int stage) {
+    using ST = Sto<S32>;
     constexpr uint32_t SPLIT = 3;                        // workgroups per tile
     // XCD x takes a contiguous run of (tile, part) units (the tile table is laid out
     // for one workgroup per tile: invert that layout, as the WENO kernel does)
@@ -1457,10 +1502,10 @@ __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ pro
         double Fo[5], dFo[5];
         bool done = true;
         if constexpr (MIXED)
-            done = point_flux_full32<WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
+            done = point_flux_full32<WALLS, S32>(P, stage, f, g, l, r, wall, Fo, dFo);
         else
             point_flux_full<false, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
-        const double w = fgeo_area(P, f) * (1.0 / 3.0);
+        const double w = fgeo_area<S32>(P, f) * (1.0 / 3.0);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             out[k] = done ? w * Fo[k] : __builtin_nan("");   // NaN: the face goes to the fix-up pass
@@ -1473,7 +1518,7 @@ __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ pro
         const double o1 = __shfl_down(out[k], 1u), o2 = __shfl_down(out[k], 2u);
         const double sum = (out[k] + o1) + o2;
         if (k == 0) s0 = sum;
-        if (ok && g == 0u) stg<double>(P.FF + (size_t)k * nf, f * 8u, sum);
+        if (ok && g == 0u) ST::st(P.FF, k, nf, f, sum);
     }
     if constexpr (MIXED) {
         // the fix-up pass has work: a face left to FP64 (flag cleared by the stage update)
@@ -1485,9 +1530,10 @@ __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ pro
 // Faces the FP32 tau > 0 pass left (their flux is NaN): the three Gauss points again,
 // in FP64 from the FP32 records, summed in the same order.  Grid-stride over the face
 // tiles, after one look at every problem's flag (nothing to do is the common case).
-template <bool WALLS>
+template <bool WALLS, bool S32 = false>
 __global__ __launch_bounds__(64) void k_flux_fix_full(const ProbDesc *__restrict__ probs, int nprobs,
                                                       const Tile *__restrict__ tiles, int ntiles, int stage) {
+    using ST = Sto<S32>;
     bool any = false;
     for (int k = threadIdx.x; k < nprobs; k += 64) any = any || ldg<int32_t>(probs[k].flag, 4u) != 0;
     if (__ballot(any) == 0) return;
@@ -1498,18 +1544,18 @@ __global__ __launch_bounds__(64) void k_flux_fix_full(const ProbDesc *__restrict
         const uint32_t f = tl.begin + threadIdx.x;
         if (f >= (uint32_t)tl.end) continue;
         const uint32_t nf = (uint32_t)P.nf;
-        const double f0 = ldg<double>(P.FF, f * 8u);
+        const double f0 = ST::ld(P.FF, 0, nf, f);
         if (f0 - f0 == 0.0) continue;                     // finite: done in FP32
         const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
         const int32_t rr = ldg<int32_t>(P.fcell + nf, f * 4u);
         const bool wall = WALLS && rr < 0;
         const uint32_t r = rr < 0 ? l : (uint32_t)rr;
-        const double w = fgeo_area(P, f) * (1.0 / 3.0);
+        const double w = fgeo_area<S32>(P, f) * (1.0 / 3.0);
         double out[10];
 #pragma unroll 1
         for (uint32_t g = 0; g < 3u; ++g) {
             double Fo[5], dFo[5];
-            point_flux_full<true, WALLS>(P, stage, f, g, l, r, wall, Fo, dFo);
+            point_flux_full<true, WALLS, S32>(P, stage, f, g, l, r, wall, Fo, dFo);
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 out[k] = g == 0u ? w * Fo[k] : out[k] + w * Fo[k];
@@ -1517,7 +1563,7 @@ __global__ __launch_bounds__(64) void k_flux_fix_full(const ProbDesc *__restrict
             }
         }
 #pragma unroll
-        for (int k = 0; k < 10; ++k) stg<double>(P.FF + (size_t)k * nf, f * 8u, out[k]);
+        for (int k = 0; k < 10; ++k) ST::st(P.FF, k, nf, f, out[k]);
     }
 }
 
@@ -1531,6 +1577,7 @@ __device__ __forceinline__ double wave_min(double x) {
 }
 
 // h / (|U| + c) of a cell, and whether its state is physical (rho > 0, p > 0, finite)
+template <bool S32 = false>
 __device__ __forceinline__ double cfl_bound(const ProbDesc &P, uint32_t i, const double q[5], bool &ok) {
     const double rho = q[0], ir = 1.0 / rho;
     const double u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
@@ -1538,12 +1585,13 @@ __device__ __forceinline__ double cfl_bound(const ProbDesc &P, uint32_t i, const
     ok = rho > 0.0 && p > 0.0 && isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
          isfinite(q[4]);
     const double c = sqrt(P.gamma * p * ir);
-    return ldg<double>(P.cgeo + (size_t)8 * P.nc, i * 8u) / (sqrt(u * u + v * v + w * w) + c);
+    return Sto<S32>::ld(P.cgeo, 8, (uint32_t)P.nc, i) / (sqrt(u * u + v * v + w * w) + c);
 }
 
-template <int STAGE, bool COLOURED>
+template <int STAGE, bool COLOURED, bool S32 = false>
 __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict__ probs,
                                                       const Tile *__restrict__ tiles) {
+    using ST = Sto<S32>;
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
     const uint32_t nc = (uint32_t)P.nc;
@@ -1554,9 +1602,8 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
         if constexpr (COLOURED) {
 #pragma unroll
             for (int k = 0; k < 10; ++k) {
-                double *acc = P.acc + (size_t)k * nc;
-                s[k] = ldg<double>(acc, i * 8u);
-                stg<double>(acc, i * 8u, 0.0);
+                s[k] = ST::ld(P.acc, k, nc, i);
+                ST::st(P.acc, k, nc, i, 0.0);
             }
         } else {
             const uint32_t nf = (uint32_t)P.nf;
@@ -1568,10 +1615,10 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
                 const uint32_t f = code >> 1;
                 const double sg = (code & 1u) ? 1.0 : -1.0;   // the normal points out of the left cell
 #pragma unroll
-                for (int k = 0; k < 10; ++k) s[k] = fma(sg, ldg<double>(P.FF + (size_t)k * nf, f * 8u), s[k]);
+                for (int k = 0; k < 10; ++k) s[k] = fma(sg, ST::ld(P.FF, k, nf, f), s[k]);
             }
         }
-        const double iv = ldg<double>(P.cgeo + (size_t)7 * nc, i * 8u);
+        const double iv = ST::ld(P.cgeo, 7, nc, i);
         const double dt = P.dt[0];
         double qn[5];
         bool ok;
@@ -1580,22 +1627,23 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
             const double h2 = 0.5 * dt, h8 = 0.125 * dt * dt, h6 = dt * dt * (1.0 / 6.0);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                const double q = ldg<double>(P.Q + (size_t)v * nc, i * 8u);
+                const double q = ST::ld(P.Q, v, nc, i);
                 const double L = s[v] * iv, dL = s[5 + v] * iv;
                 qn[v] = q + h2 * L + h8 * dL;
-                stg<double>(P.Qs + (size_t)v * nc, i * 8u, qn[v]);
-                stg<double>(P.R + (size_t)v * nc, i * 8u, q + dt * L + h6 * dL);
+                ST::st(P.Qs, v, nc, i, qn[v]);
+                ST::st(P.R, v, nc, i, q + dt * L + h6 * dL);
             }
-            cfl_bound(P, i, qn, ok);
+            cfl_bound<S32>(P, i, qn, ok);
         } else {
             // Q^{n+1} = R + dt^2/3 dL(Q*)
             const double h3 = dt * dt * (1.0 / 3.0);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-                qn[v] = ldg<double>(P.R + (size_t)v * nc, i * 8u) + h3 * (s[5 + v] * iv);
-                stg<double>(P.Q + (size_t)v * nc, i * 8u, qn[v]);
+                qn[v] = ST::ld(P.R, v, nc, i) + h3 * (s[5 + v] * iv);
+                ST::st(P.Q, v, nc, i, qn[v]);
+                qn[v] = (double)(typename ST::E)qn[v];        // the CFL bound of the stored state
             }
-            bound = cfl_bound(P, i, qn, ok);
+            bound = cfl_bound<S32>(P, i, qn, ok);
         }
         if (!ok) P.flag[0] = 1;
     }
@@ -1606,6 +1654,7 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
     }
 }
 
+template <bool S32 = false>
 __global__ __launch_bounds__(UPD_TILE) void k_dt_local(const ProbDesc *__restrict__ probs,
                                                         const Tile *__restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
@@ -1615,9 +1664,9 @@ __global__ __launch_bounds__(UPD_TILE) void k_dt_local(const ProbDesc *__restric
     if (i < (uint32_t)tl.end) {
         double q[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[v] = ldg<double>(P.Q + (size_t)v * P.nc, i * 8u);
+        for (int v = 0; v < 5; ++v) q[v] = Sto<S32>::ld(P.Q, v, (uint32_t)P.nc, i);
         bool ok;
-        bound = cfl_bound(P, i, q, ok);
+        bound = cfl_bound<S32>(P, i, q, ok);
         if (!ok) P.flag[0] = 1;
     }
     bound = wave_min(bound);
@@ -1684,66 +1733,85 @@ static int device_cus() {
     return cached[dev];
 }
 
-void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, bool mixed, bool tau0,
+void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntiles, int stage, int prec, bool tau0,
                  bool coloured, bool walls, hipStream_t s) {
     if (ntiles <= 0) return;
+    // prec 0: FP64; 1: FP32 flux on FP64 storage; 2: FP32 flux on FP32 storage
+    const bool mixed = prec != 0;
     if (tau0) {
         dim3 g(ntiles), b(FACE_TILE);
-#define HGKS_FLUX0(M, CO, D)                                                                                \
+#define HGKS_FLUX0(M, CO, D, S)                                                                             \
     do {                                                                                                    \
-        if (walls) hipLaunchKernelGGL((k_flux_t0<M, CO, true, D>), g, b, 0, s, probs, tiles, stage);        \
-        else hipLaunchKernelGGL((k_flux_t0<M, CO, false, D>), g, b, 0, s, probs, tiles, stage);             \
+        if (walls) hipLaunchKernelGGL((k_flux_t0<M, CO, true, D, S>), g, b, 0, s, probs, tiles, stage);     \
+        else hipLaunchKernelGGL((k_flux_t0<M, CO, false, D, S>), g, b, 0, s, probs, tiles, stage);          \
     } while (0)
-        if (coloured) { if (mixed) HGKS_FLUX0(true, true, false); else HGKS_FLUX0(false, true, false); }
-        else if (stage == 1) { if (mixed) HGKS_FLUX0(true, false, false); else HGKS_FLUX0(false, false, false); }
-        else { if (mixed) HGKS_FLUX0(true, false, true); else HGKS_FLUX0(false, false, true); }
+#define HGKS_FLUX0P(CO, D)                                                                                  \
+    do {                                                                                                    \
+        if (prec == 2) HGKS_FLUX0(true, CO, D, true);                                                       \
+        else if (prec == 1) HGKS_FLUX0(true, CO, D, false);                                                 \
+        else HGKS_FLUX0(false, CO, D, false);                                                               \
+    } while (0)
+        if (coloured) HGKS_FLUX0P(true, false);
+        else if (stage == 1) HGKS_FLUX0P(false, false);
+        else HGKS_FLUX0P(false, true);
+#undef HGKS_FLUX0P
 #undef HGKS_FLUX0
         if (!coloured) {
             const dim3 gf(std::min(ntiles, 8 * device_cus()));
-            if (mixed) hipLaunchKernelGGL((k_flux_fix<true>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
-            else hipLaunchKernelGGL((k_flux_fix<false>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
+            if (prec == 2) hipLaunchKernelGGL((k_flux_fix<true, true>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
+            else if (prec == 1) hipLaunchKernelGGL((k_flux_fix<true, false>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
+            else hipLaunchKernelGGL((k_flux_fix<false, false>), gf, b, 0, s, probs, nprobs, tiles, ntiles, stage);
         }
         return;
     }
     if (!coloured) {          // tiles of 3 * GP_FACES faces, three single-wave workgroups each
         dim3 g(ntiles * 3), b(64);
-        if (mixed) { if (walls) hipLaunchKernelGGL((k_flux_gp<true, true>), g, b, 0, s, probs, tiles, stage);
-                     else hipLaunchKernelGGL((k_flux_gp<true, false>), g, b, 0, s, probs, tiles, stage); }
-        else { if (walls) hipLaunchKernelGGL((k_flux_gp<false, true>), g, b, 0, s, probs, tiles, stage);
-               else hipLaunchKernelGGL((k_flux_gp<false, false>), g, b, 0, s, probs, tiles, stage); }
+#define HGKS_GP(M, W, S) hipLaunchKernelGGL((k_flux_gp<M, W, S>), g, b, 0, s, probs, tiles, stage)
+        if (prec == 2) { if (walls) HGKS_GP(true, true, true); else HGKS_GP(true, false, true); }
+        else if (prec == 1) { if (walls) HGKS_GP(true, true, false); else HGKS_GP(true, false, false); }
+        else { if (walls) HGKS_GP(false, true, false); else HGKS_GP(false, false, false); }
+#undef HGKS_GP
         if (mixed) {            // faces left to FP64 by the FP32 pass
             const dim3 gf(std::min(ntiles, 8 * device_cus())), bf(64);
-            if (walls) hipLaunchKernelGGL((k_flux_fix_full<true>), gf, bf, 0, s, probs, nprobs, tiles, ntiles, stage);
-            else hipLaunchKernelGGL((k_flux_fix_full<false>), gf, bf, 0, s, probs, nprobs, tiles, ntiles, stage);
+#define HGKS_FIX(W, S) hipLaunchKernelGGL((k_flux_fix_full<W, S>), gf, bf, 0, s, probs, nprobs, tiles, ntiles, stage)
+            if (prec == 2) { if (walls) HGKS_FIX(true, true); else HGKS_FIX(false, true); }
+            else { if (walls) HGKS_FIX(true, false); else HGKS_FIX(false, false); }
+#undef HGKS_FIX
         }
         return;
     }
+    // tau > 0 with colour classes: one wave per Gauss point, summed through LDS
     dim3 g(ntiles), b(3 * FACE_TILE);
-#define HGKS_FLUX(M, CO)                                                                                    \
+#define HGKS_FLUX(M, S)                                                                                     \
     do {                                                                                                    \
-        if (walls) hipLaunchKernelGGL((k_flux<M, false, CO, true>), g, b, 0, s, probs, tiles, stage);       \
-        else hipLaunchKernelGGL((k_flux<M, false, CO, false>), g, b, 0, s, probs, tiles, stage);            \
+        if (walls) hipLaunchKernelGGL((k_flux<M, false, true, true, S>), g, b, 0, s, probs, tiles, stage);  \
+        else hipLaunchKernelGGL((k_flux<M, false, true, false, S>), g, b, 0, s, probs, tiles, stage);       \
     } while (0)
-    if (coloured) { if (mixed) HGKS_FLUX(true, true); else HGKS_FLUX(false, true); }
-    else { if (mixed) HGKS_FLUX(true, false); else HGKS_FLUX(false, false); }
+    if (prec == 2) HGKS_FLUX(true, true);
+    else if (prec == 1) HGKS_FLUX(true, false);
+    else HGKS_FLUX(false, false);
 #undef HGKS_FLUX
 }
 
-void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, hipStream_t s) {
+void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, bool s32,
+                   hipStream_t s) {
     if (ntiles <= 0) return;
     dim3 g(ntiles), b(UPD_TILE);
+#define HGKS_UPD(ST, CO, S) hipLaunchKernelGGL((k_update<ST, CO, S>), g, b, 0, s, probs, tiles)
     if (stage == 1) {
-        if (coloured) hipLaunchKernelGGL((k_update<1, true>), g, b, 0, s, probs, tiles);
-        else hipLaunchKernelGGL((k_update<1, false>), g, b, 0, s, probs, tiles);
+        if (s32) { if (coloured) HGKS_UPD(1, true, true); else HGKS_UPD(1, false, true); }
+        else { if (coloured) HGKS_UPD(1, true, false); else HGKS_UPD(1, false, false); }
     } else {
-        if (coloured) hipLaunchKernelGGL((k_update<2, true>), g, b, 0, s, probs, tiles);
-        else hipLaunchKernelGGL((k_update<2, false>), g, b, 0, s, probs, tiles);
+        if (s32) { if (coloured) HGKS_UPD(2, true, true); else HGKS_UPD(2, false, true); }
+        else { if (coloured) HGKS_UPD(2, true, false); else HGKS_UPD(2, false, false); }
     }
+#undef HGKS_UPD
 }
 
-void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, hipStream_t s) {
+void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, bool s32, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_dt_local, dim3(ntiles), dim3(UPD_TILE), 0, s, probs, tiles);
+    if (s32) hipLaunchKernelGGL(k_dt_local<true>, dim3(ntiles), dim3(UPD_TILE), 0, s, probs, tiles);
+    else hipLaunchKernelGGL(k_dt_local<false>, dim3(ntiles), dim3(UPD_TILE), 0, s, probs, tiles);
 }
 
 void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s) {

@@ -297,7 +297,8 @@ uint64_t spread3(uint64_t v) {  // 21 bits -> every third bit
 }  // namespace
 
 hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, int64_t nc, int npc,
-                       const int64_t *cn, const double *period_in, HostMesh &out, std::string &err) {
+                       const int64_t *cn, const double *period_in, HostMesh &out, std::string &err,
+                       bool diagnostics) {
     if (nn <= 0 || nc <= 0 || !xyz || !cn) {
         err = "empty mesh";
         return HGKS_E_INVALID_ARG;
@@ -598,7 +599,8 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                 bad = 4;
                 continue;
             }
-            // residual |P A - I|
+            // residual |P A - I| (a diagnostic of hgks_inspect_mesh, skipped at upload)
+            if (diagnostics)
             for (int r = 0; r < 9; ++r)
                 for (int c = 0; c < 9; ++c) {
                     double s = 0.0;

@@ -47,7 +47,16 @@ def test_config1_errors_against_exact_solution():
         f"(normalised by |D| = 8: L1 {e['L1'] / 8:.4e})")
     assert 0.15 < t < 0.25
     assert 2.3 < e["L1"] / e["L2"] < 2.7          # a sine-shaped error (reading of the norms)
-    assert e["Linf"] < 0.02 and e["L1"] < 0.05    # against an amplitude of 0.2 at N = 8
+    # N = 8 resolves the wave with under five cells per wavelength along the diagonal:
+    # the error is about a tenth of the amplitude 0.2 at its worst (measured Linf 0.022)
+    assert e["Linf"] < 0.05 and e["L1"] < 0.15
+    # and it is the oracle's error, run over the same 20 steps
+    from oracle import oracle as O
+    q_orc, _ = O.Mesh.from_workload(mesh).step(q0, 20)
+    e_orc = W.error_norms(vol, q_orc[:, 0], case.density_average(mesh, t))
+    say(f"config 1 oracle: L1 {e_orc['L1']:.4e} L2 {e_orc['L2']:.4e} Linf {e_orc['Linf']:.4e}")
+    for k in ("L1", "L2", "Linf"):
+        assert abs(e[k] - e_orc[k]) <= 1e-10 * e_orc[k], k
     for prec in (hgks.FP32_MIXED, hgks.FP32):
         q32, _ = _run(mesh, q0, prec, 20)
         d = rel_l1_scaled(q32, q, vol)

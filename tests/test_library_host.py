@@ -117,11 +117,14 @@ def test_oracle_sampled_step_equals_full_step():
 def test_footprint_by_precision():
     """Device footprint per precision (host arithmetic only, no device call): the
     FP32-mixed form stores the reconstruction in FP32 (200 of 400 B a cell), and the
-    FP32 form also the big-stencil pseudo-inverse (576 of 1152 B a cell)."""
+    FP32 form also the big-stencil pseudo-inverse (576 of 1152 B a cell), the state
+    (60 of 120), the cell geometry (36 of 72), and per face the geometry (64 of 128)
+    and the flux sums (40 of 80): 880 B a cell less (two faces a cell)."""
     nc = 6 * 40 ** 3
     f = {p: hgks.pool_footprint(hgks.params(precision=p), nc) for p in (hgks.FP64, hgks.FP32_MIXED, hgks.FP32)}
     slack = 4096          # per-array alignment
     assert abs((f[hgks.FP64] - f[hgks.FP32_MIXED]) - 200 * nc) <= slack
-    assert abs((f[hgks.FP32_MIXED] - f[hgks.FP32]) - 576 * nc) <= slack
+    assert abs((f[hgks.FP32_MIXED] - f[hgks.FP32]) - 880 * nc) <= slack
+    assert f[hgks.FP32] < 0.53 * f[hgks.FP64]          # about half the memory of FP64
     with pytest.raises(hgks.HGKSError):
         hgks.pool_footprint(hgks.params(precision=3), nc)
