@@ -42,19 +42,22 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector
 #          9x16 (1152) + 1/h and second moments (56) + own centroid (24) + slot image
 #          codes (16) + reconstruction written (400)                           = 1752
 #          (the sub-stencil fits are formed on the device from the centroids;
-#          FP32-mixed writes 200, and the FP32 form also reads a 576 B pseudo-inverse)
+#          FP32-mixed writes 200)
 #   flux   per face: cells (8) + normal, area, Gauss offsets and the centroid difference
 #          (128) + flux written (80) = 216 in the first stage and 176 in the second (dF
 #          only), plus per cell the reconstruction read once (400)
 #   update per cell: face ids (16) + its faces' fluxes (2 faces' worth, 160) + 1/|V|
 #          and h (16) + state traffic (stage 1: 3 x 40, stage 2: 2 x 40)       ~ 292
-def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool = False) -> float:
+# The FP32 form (fp32=True) stores state, cell and face geometry and face fluxes in
+# 4-byte words and streams a 576 B pseudo-inverse; ids, centroids and codes are as above.
+def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, fp32: bool = False) -> float:
+    es = 4 if fp32 else 8
     if kernel == "weno":
-        return nc * (64 + 40 + (576 if pinv32 else 1152) + 56 + 24 + 16 + (200 if mixed else 400))
-    if kernel == "flux":   # 216 B a face in the first stage, 176 in the second (F not stored)
-        return nf * 196 + nc * ((200 + 40) if mixed else 400)
+        return nc * (64 + 5 * es + (576 if fp32 else 1152) + 7 * es + 24 + 16 + (200 if mixed else 400))
+    if kernel == "flux":   # first stage F and dF/dt, second stage dF/dt only
+        return nf * (8 + 16 * es + 7.5 * es) + nc * ((200 + 5 * es) if mixed else 400)
     if kernel == "update":
-        return nc * (16 + 160 + 16 + 100)
+        return nc * (16 + 20 * es + 2 * es + 12.5 * es)
     return 0.0
 
 
@@ -67,14 +70,14 @@ def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, pinv32: bool =
 TABLE_BOUND_BYTES_PER_CELL_UPDATE = 4340.0
 
 
-def reduced_weno(r, nc: int, nf: int, pinv32: bool):
+def reduced_weno(r, nc: int, nf: int, fp32: bool):
     """Average WENO launch time of a reduced-precision run, and its algorithmic rate."""
     ms, cnt = r["prof"]["weno"]
     if not cnt:
         return None
     avg_s = ms / 1e3 / cnt
     return {"us": round(1e6 * avg_s, 2),
-            "alg_GBps": round(algorithmic_bytes("weno", nc, nf, True, pinv32) / avg_s / 1e9, 1)}
+            "alg_GBps": round(algorithmic_bytes("weno", nc, nf, True, fp32) / avg_s / 1e9, 1)}
 
 
 def kernel_source_hash() -> str:

@@ -18,11 +18,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-@pytest.mark.parametrize("mixed,pinv32,per_cell", [(False, False, 1752), (True, False, 1552), (True, True, 976)])
-def test_weno_algorithmic_bytes(mixed, pinv32, per_cell):
-    """Per-cell WENO bytes of the three precision forms: ids 64, state 40, pseudo-inverse
-    1152 (576 in FP32), geometry 56, centroid 24, image codes 16, record 400 (200)."""
-    assert bench.algorithmic_bytes("weno", 1000, 2000, mixed, pinv32) == 1000 * per_cell
+@pytest.mark.parametrize("mixed,fp32,per_cell", [(False, False, 1752), (True, False, 1552), (True, True, 928)])
+def test_weno_algorithmic_bytes(mixed, fp32, per_cell):
+    """Per-cell WENO bytes of the three precision forms: ids 64, state 40 (20 in FP32),
+    pseudo-inverse 1152 (576), geometry 56 (28), centroid 24, image codes 16, record 400
+    (200 in both reduced forms)."""
+    assert bench.algorithmic_bytes("weno", 1000, 2000, mixed, fp32) == 1000 * per_cell
 
 
 def test_flux_and_update_algorithmic_bytes():
@@ -30,3 +31,6 @@ def test_flux_and_update_algorithmic_bytes():
     # the mean of 216 (first stage) and 176 (second stage, dF only) per face
     assert bench.algorithmic_bytes("flux", nc, nf, False) == nf * 196 + nc * 400
     assert bench.algorithmic_bytes("update", nc, nf, False) == nc * 292
+    # the FP32 form: 4-byte geometry, fluxes and state, 4-byte ids as before
+    assert bench.algorithmic_bytes("flux", nc, nf, True, True) == nf * 102 + nc * 220
+    assert bench.algorithmic_bytes("update", nc, nf, True, True) == nc * 154
