@@ -1,7 +1,7 @@
 /*
  * hgks_oracle.c -- plain FP64 CPU reference of one explicit
  * HGKS step (third-order unstructured WENO, Gauss-point gas-kinetic flux,
- * two-stage fourth-order update) on tetrahedral meshes.
+ * two-stage fourth-order update) on tetrahedral and hexahedral meshes.
  *
  * TEST INFRASTRUCTURE ONLY.  It is linked by the test-suite, the smoke check and
  * the CPU-baseline leg of the benchmark, never by the product path, and it
@@ -9,35 +9,53 @@
  * every step follows the paper (arXiv 2407.00656, Sec. 2) in the paper's order:
  *
  *   geometry ............ Sec. 3.1 (areas, volumes, local frames)
- *   stencils ............ Sec. 3.1 item 4 / Algorithm 1, Sec. 2.3 (tet sub-stencils)
+ *   stencils ............ Sec. 3.1 item 4 / Algorithm 1, Sec. 2.3 (tet and hex
+ *                         sub-stencils)
  *   WENO ................ Sec. 2.3, Eqs. (polys) and (weno), WENO-Z weights,
- *                         smoothness indicators beta_m
+ *                         smoothness indicators beta_m, gamma_0 = 1 - M gamma
  *   gas-kinetic flux .... Sec. 2.1, Eqs. (flux-G), (flux), compatibility
  *                         condition for Q0, slope relations <a>, <a.u + A> = 0
  *   time fit ............ Sec. 2.2, Eq. (expansion-1) and its 2x2 system
  *   S2O4 update ......... Sec. 2.2
+ *   viscous flow ........ Sec. 5.2 (mu = mu_inf (T/T_inf)^0.7, no-slip adiabatic
+ *                         wall, far field by Riemann invariants)
  *
  * Readings where the paper is silent (all are parameters or documented choices):
- *   - 3-point degree-2 Gauss rule on each triangular face (weights 1/3);
+ *   - 3-point degree-2 Gauss rule on each triangular face (weights 1/3); on a
+ *     hexahedron's bilinear face the 2x2 Gauss-Legendre rule in the face's
+ *     bilinear parameters, each point with its own unit normal and weight
+ *     |x_s x x_t| / 4 (the weights sum to the face's area up to the rule's
+ *     error, and the weighted normals to its exact vector area);
+ *   - cell integrals: the 4-point degree-2 rule on a tetrahedron; the 3x3x3
+ *     Gauss-Legendre rule over the trilinear map of a hexahedron (exact for the
+ *     monomials of degree <= 2 times the map's Jacobian);
  *   - WENO-Z with exponent 1 and the epsilon given in the parameters;
  *   - unweighted least squares in cell-scaled centroid coordinates, solved by
  *     normal equations + Cholesky;
  *   - the slopes of the equilibrium state use dQ0 = (dQ_l + dQ_r)/2;
- *   - tau = 0 (smooth flow, Sec. 5.1) or tau = eps*dt + C*|pl-pr|/(pl+pr)*dt;
+ *   - tau = 0 (smooth flow, Sec. 5.1), tau = eps*dt + C*|pl-pr|/(pl+pr)*dt, or
+ *     (viscous) tau = mu(T0)/p0 + C*|pl-pr|/(pl+pr)*dt with T = p/rho;
+ *   - Prandtl number: BGK has Pr = 1; for Pr != 1 (viscous mode only) the energy
+ *     flux takes (1/Pr - 1) times the heat flux of the interface distribution,
+ *     measured in the frame of the interface equilibrium velocity U0;
  *   - dt = CFL * min_i h_i / (|U_i| + c_i), h_i = 6|Omega_i| / sum_p S_ip;
  *   - positivity fallback at Gauss points (where a reconstructed side is
  *     non-physical the point is first order: zero gradients, cell averages for
  *     the non-physical sides), which acts only at discontinuities.
  *
- * Conventions: cells are 0-based; face p of a tetrahedron is the one opposite
- * its node p (Sec. 3.1 item 1); the neighbour across face p is "i_{p+1}" of
+ * Conventions: cells are 0-based.  Face p of a tetrahedron is the one opposite
+ * its node p (Sec. 3.1 item 1).  A hexahedron lists nodes 0-3 around one face and
+ * nodes 4-7 above them (node k+4 joined to node k); its faces, in the paper's
+ * numbering 1..6 (Sec. 2.3, where faces 1 and 6 are opposite and 2..5 go around)
+ * are, 0-based: 0 = (0,1,2,3), 1 = (0,1,5,4), 2 = (1,2,6,5), 3 = (2,3,7,6),
+ * 4 = (3,0,4,7), 5 = (4,5,6,7).  The neighbour across face p is "i_{p+1}" of
  * Sec. 2.3.  Meshes may be periodic: period[a] > 0 identifies x_a with
  * x_a + period[a]; each cell is unwrapped around its first node.
  *
  * Boundaries (Algorithm 1 gives a boundary face a ghost neighbour "according to
- * the boundary condition"; the reading here is the transmissive wall): an axis
- * with period 0 ends in two planar walls at the extreme node coordinates.  The
- * ghost across a wall face is the mirror image of the wall cell in the wall
+ * the boundary condition").  Without a boundary-face list, an axis with period 0
+ * ends in two planar transmissive walls at the extreme node coordinates.  The
+ * ghost across such a wall face is the mirror image of the wall cell in the wall
  * plane and holds the wall cell's state.  A ghost's face neighbours are the
  * mirror images of the wall cell's neighbours (so a two-layer stencil near a
  * wall contains mirror images of interior cells, and near an edge images under
@@ -46,6 +64,17 @@
  * s = -1 for mirrors.  Because a ghost's stencil and data are the mirror image of
  * the wall cell's, so is its reconstruction: at a wall Gauss point its value is
  * the wall cell's and its gradient the wall cell's reflected in the wall.
+ *
+ * With a boundary-face list (no periodic axis), each listed face is a no-slip
+ * adiabatic wall or a far-field face.  Its ghost is the cell's mirror image in
+ * the face's mean plane, has no neighbours of its own, and holds the ghost state
+ * of the cell's average: at a wall (rho, -rho U, rho E), i.e. zero velocity and
+ * the cell's temperature on the face; at the far field the Riemann-invariant
+ * state of the cell and the free stream.  At a Gauss point of such a face the
+ * right side is the same ghost map applied to the left reconstruction: at a wall
+ * the value with its momentum negated and the gradient reflected in the plane
+ * (momentum rows negated), at the far field the Riemann-invariant state of the
+ * left point value with a zero gradient.
  */
 #include <math.h>
 #include <stdint.h>
@@ -61,18 +90,32 @@
 #define ORC_E_MESH 2
 #define ORC_E_NONPHYS 6
 
-#define MAXSTEN 32
+#define MAXSTEN 40
 #define MAXSUB 8
+#define MAXM 8              /* sub-stencils per cell: 4 (tet), 8 (hex) */
+#define MAXFC 6             /* faces per cell */
+#define MAXGP 4             /* Gauss points per face */
+#define MAXCQ 27            /* cell quadrature points */
 
 typedef struct {
     double gamma;
     double cfl;
-    int tau_mode;          /* 0: tau = 0;  1: tau = tau_eps*dt + tau_C*|pl-pr|/(pl+pr)*dt */
+    int tau_mode;          /* 0: tau = 0;  1: tau = tau_eps*dt + tau_C*|pl-pr|/(pl+pr)*dt;
+                              2: tau = mu(T0)/p0 + tau_C*|pl-pr|/(pl+pr)*dt (viscous) */
     double tau_eps;
     double tau_C;
     double weno_eps;
-    double gamma_lin;      /* linear weight of each sub-stencil; gamma_0 = 1 - 4*gamma_lin */
+    double gamma_lin;      /* linear weight of each sub-stencil; gamma_0 = 1 - M*gamma_lin */
+    double mu_ref;         /* viscous mode: mu = mu_ref * (T / T_ref)^mu_exp, T = p / rho */
+    double T_ref;
+    double mu_exp;
+    double prandtl;
+    double farfield[5];    /* free stream (rho, U, V, W, p) of far-field faces */
 } orc_params;
+
+/* boundary kinds of listed boundary faces */
+#define ORC_BC_WALL 1      /* no-slip adiabatic wall */
+#define ORC_BC_FAR 2       /* far field (Riemann invariants) */
 
 /* placement of a stencil member: x -> s*x + o on each axis */
 typedef struct { double s[3], o[3]; } xform;
@@ -80,30 +123,39 @@ static const xform XID = {{1.0, 1.0, 1.0}, {0.0, 0.0, 0.0}};
 
 typedef struct {
     int64_t nc, nn, nf;
+    int npc, nfc, ngp, msub;       /* nodes per cell, faces per cell, Gauss points per face, sub-stencils */
     double period[3];
     double lo[3], hi[3];            /* node extent per axis (the walls of non-periodic axes) */
-    double (*vert)[4][3];          /* unwrapped vertices of each cell */
+    double (*vert)[8][3];          /* unwrapped vertices of each cell */
     double *vol;
     double (*cen)[3];
     double *h;                      /* |Omega|^(1/3): length scale of the local coordinates */
     double *hdt;                    /* 6|Omega| / sum of face areas */
     /* faces */
-    int64_t (*fcell)[2];            /* left, right (-1: a wall face, the right side is the ghost) */
+    int64_t (*fcell)[2];            /* left, right (-1: a boundary face, the right side is the ghost) */
+    int *fkind;                     /* 0 interior or transmissive wall, ORC_BC_WALL, ORC_BC_FAR */
     double (*fshift)[3];            /* right cell's image in the left cell's frame = right + fshift */
-    double (*fnrm)[3];
-    double *farea;
-    double (*fgp)[3][3];            /* Gauss points, left cell's frame */
-    int64_t (*cface)[4];            /* face opposite local node p */
-    /* neighbours i_1..i_4 */
-    int64_t (*nb)[4];               /* the cell itself across a wall face */
-    xform (*nbx)[4];                /* placement of that neighbour (a mirror across a wall face) */
-    /* big stencil and the four sub-stencils (members other than the cell itself) */
+    double (*fnrm)[3];              /* mean unit normal (vector area / area), left -> right */
+    double *farea;                  /* sum of the Gauss weights */
+    double (*fgp)[MAXGP][3];        /* Gauss points, left cell's frame */
+    double (*fpn)[MAXGP][3];        /* unit normal at each Gauss point */
+    double (*fpw)[MAXGP];           /* weight of each Gauss point (area units) */
+    int64_t (*cface)[MAXFC];        /* local face p of each cell */
+    /* neighbours i_1..i_nfc; an id >= nc is ghost (id - nc) of a listed boundary face */
+    int64_t (*nb)[MAXFC];           /* the cell itself across a transmissive wall face */
+    xform (*nbx)[MAXFC];            /* placement of that neighbour (a mirror across a wall face) */
+    /* ghosts of listed boundary faces */
+    int64_t ng;
+    int64_t *gcell, *gface;
+    int *gkind;
+    double (*gpt)[3], (*gnrm)[3];   /* mirror plane: a point and the unit normal */
+    /* big stencil and the sub-stencils (members other than the cell itself) */
     int *nsten;
     int64_t (*sten)[MAXSTEN];
     xform (*stx)[MAXSTEN];
-    int (*nsub)[4];
-    int64_t (*sub)[4][MAXSUB];
-    xform (*subx)[4][MAXSUB];
+    int (*nsub)[MAXM];
+    int64_t (*sub)[MAXM][MAXSUB];
+    xform (*subx)[MAXM][MAXSUB];
 } orc_mesh;
 
 /* ------------------------------------------------------------------------- */
@@ -168,6 +220,91 @@ static void tet_monomial_means(const double v[4][3], const double *c, double h, 
         double xi[3] = {(pts[q][0] - c[0]) / h, (pts[q][1] - c[1]) / h, (pts[q][2] - c[2]) / h};
         for (int d = 0; d < 9; ++d) out[d] += 0.25 * mono(DEXP[d], xi);
     }
+}
+
+/* Hexahedron: reference coordinates of node k on [0,1]^3 (nodes 0-3 at zeta = 0
+ * going around, node k+4 above node k), and the six faces in cyclic node order. */
+static const int HXI[8][3] = {{0,0,0},{1,0,0},{1,1,0},{0,1,0},{0,0,1},{1,0,1},{1,1,1},{0,1,1}};
+static const int HEXF[6][4] = {{0,1,2,3},{0,1,5,4},{1,2,6,5},{2,3,7,6},{3,0,4,7},{4,5,6,7}};
+/* hex sub-stencils (Sec. 2.3): the face neighbours of each, 0-based faces */
+static const int HEXSUB[8][3] = {{0,1,2},{0,2,3},{0,3,4},{0,4,1},{5,1,2},{5,2,3},{5,3,4},{5,4,1}};
+/* tet sub-stencils: S_1 = {i1,i2,i3} + N(i1), S_2 = {i1,i2,i4} + N(i2),
+ * S_3 = {i2,i3,i4} + N(i3), S_4 = {i3,i1,i4} + N(i4) */
+static const int TETSUB[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
+
+/* Gauss-Legendre rules on [0, 1] */
+static const double GL2X[2] = {0.21132486540518711775, 0.78867513459481288225};
+static const double GL3X[3] = {0.11270166537925831148, 0.5, 0.88729833462074168852};
+static const double GL3W[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+/* Trilinear map of a hexahedron at reference point r: position x and det dx/dr. */
+static double hex_map(const double v[8][3], const double r[3], double x[3]) {
+    double J[3][3] = {{0}};
+    for (int a = 0; a < 3; ++a) x[a] = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        double f[3], df[3];
+        for (int d = 0; d < 3; ++d) {
+            f[d] = HXI[k][d] ? r[d] : 1.0 - r[d];
+            df[d] = HXI[k][d] ? 1.0 : -1.0;
+        }
+        const double N = f[0] * f[1] * f[2];
+        const double dN[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+        for (int a = 0; a < 3; ++a) {
+            x[a] += N * v[k][a];
+            for (int d = 0; d < 3; ++d) J[a][d] += dN[d] * v[k][a];
+        }
+    }
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* Quadrature of a cell: points and weights (weights sum to the volume).
+ * Tet: the degree-2 four-point rule; hex: 3x3x3 Gauss-Legendre over the trilinear
+ * map.  jmin/jmax (nullable) receive the extreme Jacobians (hex). */
+static int cell_quadrature(int npc, const double v[8][3], double pts[MAXCQ][3], double wts[MAXCQ], double *jmin,
+                           double *jmax) {
+    if (npc == 4) {
+        tet_points(v, pts);
+        double e1[3], e2[3], e3[3], cr[3];
+        sub3(v[1], v[0], e1);
+        sub3(v[2], v[0], e2);
+        sub3(v[3], v[0], e3);
+        cross3(e2, e3, cr);
+        const double vol = fabs(dot3(e1, cr)) / 6.0;
+        for (int q = 0; q < 4; ++q) wts[q] = 0.25 * vol;
+        if (jmin) *jmin = vol;
+        if (jmax) *jmax = vol;
+        return 4;
+    }
+    int n = 0;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) {
+                const double r[3] = {GL3X[a], GL3X[b], GL3X[c]};
+                const double J = hex_map(v, r, pts[n]);
+                lo = fmin(lo, J); hi = fmax(hi, J);
+                wts[n] = GL3W[a] * GL3W[b] * GL3W[c] * fabs(J);
+                ++n;
+            }
+    if (jmin) *jmin = lo;
+    if (jmax) *jmax = hi;
+    return n;
+}
+
+/* Mean of the 9 scaled monomials over a cell with vertices v (any frame). */
+static void cell_monomial_means(int npc, const double v[8][3], const double *c, double h, double out[9]) {
+    if (npc == 4) { tet_monomial_means(v, c, h, out); return; }
+    double pts[MAXCQ][3], wts[MAXCQ];
+    const int n = cell_quadrature(npc, v, pts, wts, NULL, NULL);
+    double V = 0.0;
+    for (int d = 0; d < 9; ++d) out[d] = 0.0;
+    for (int q = 0; q < n; ++q) {
+        double xi[3] = {(pts[q][0] - c[0]) / h, (pts[q][1] - c[1]) / h, (pts[q][2] - c[2]) / h};
+        V += wts[q];
+        for (int d = 0; d < 9; ++d) out[d] += wts[q] * mono(DEXP[d], xi);
+    }
+    for (int d = 0; d < 9; ++d) out[d] /= V;
 }
 
 /* Least squares min ||A x - B|| via the normal equations and Cholesky.
@@ -245,22 +382,36 @@ static int gauss_solve(int n, const double *Ain, const double *bin, double *x) {
 /* mesh: connectivity (Sec. 3.1) and geometry                                */
 /* ------------------------------------------------------------------------- */
 
-typedef struct { int64_t key[3]; int64_t cell; int p; } face_rec;
+typedef struct { int64_t key[4]; int64_t cell; int p; } face_rec;
+
+static int cmp_key(const int64_t *x, const int64_t *y) {
+    for (int k = 0; k < 4; ++k) {
+        if (x[k] < y[k]) return -1;
+        if (x[k] > y[k]) return 1;
+    }
+    return 0;
+}
 
 static int cmp_face(const void *a, const void *b) {
     const face_rec *x = (const face_rec *)a, *y = (const face_rec *)b;
-    for (int k = 0; k < 3; ++k) {
-        if (x->key[k] < y->key[k]) return -1;
-        if (x->key[k] > y->key[k]) return 1;
-    }
+    int c = cmp_key(x->key, y->key);
+    if (c) return c;
     if (x->cell != y->cell) return x->cell < y->cell ? -1 : 1;
     return x->p - y->p;
 }
 
-static void sort3(int64_t *k) {
-    for (int a = 0; a < 3; ++a)
-        for (int b = a + 1; b < 3; ++b)
-            if (k[b] < k[a]) { int64_t t = k[a]; k[a] = k[b]; k[b] = t; }
+/* sorted node ids of a face; a triangle's fourth key is -1 */
+static void face_key(const int64_t *nodes, int nk, int64_t key[4]) {
+    for (int k = 0; k < 4; ++k) key[k] = k < nk ? nodes[k] : -1;
+    for (int a = 0; a < nk; ++a)
+        for (int b = a + 1; b < nk; ++b)
+            if (key[b] < key[a]) { int64_t t = key[a]; key[a] = key[b]; key[b] = t; }
+}
+
+/* local node q of face p (nk nodes, cyclic order) */
+static int face_node(int npc, int p, int k) {
+    if (npc == 8) return HEXF[p][k];
+    return k + (k >= p ? 1 : 0);        /* the three nodes other than p */
 }
 
 void orc_mesh_free(orc_mesh *m);
@@ -279,13 +430,69 @@ static xform compose(const xform *A, const xform *B) {
     return r;
 }
 
-orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t *cell_nodes,
-                       const double *period, char *err, int errlen) {
-    if (nn <= 0 || nc <= 0 || !xyz || !cell_nodes) { set_err(err, errlen, "empty mesh"); return NULL; }
+/* Gauss points, their unit normals and weights of a face given its nodes in cyclic
+ * order (left cell's frame).  Returns the number of points. */
+static int face_points(int nk, const double fv[4][3], double gp[MAXGP][3], double gn[MAXGP][3], double gw[MAXGP]) {
+    if (nk == 3) {
+        double e1[3], e2[3], nrm[3];
+        sub3(fv[1], fv[0], e1);
+        sub3(fv[2], fv[0], e2);
+        cross3(e1, e2, nrm);
+        const double len = sqrt(dot3(nrm, nrm));
+        /* 3-point degree-2 rule: barycentric permutations of (2/3, 1/6, 1/6) */
+        for (int g = 0; g < 3; ++g) {
+            for (int a = 0; a < 3; ++a) {
+                double s_ = 0.0;
+                for (int v = 0; v < 3; ++v) s_ += (v == g ? 2.0 / 3.0 : 1.0 / 6.0) * fv[v][a];
+                gp[g][a] = s_;
+                gn[g][a] = nrm[a] / len;
+            }
+            gw[g] = 0.5 * len / 3.0;
+        }
+        return 3;
+    }
+    /* bilinear patch x(s,t) = (1-s)(1-t) a + s(1-t) b + s t c + (1-s) t d */
+    int g = 0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j, ++g) {
+            const double s_ = GL2X[i], t = GL2X[j];
+            double xs[3], xt[3], nrm[3];
+            for (int a = 0; a < 3; ++a) {
+                gp[g][a] = (1 - s_) * (1 - t) * fv[0][a] + s_ * (1 - t) * fv[1][a] + s_ * t * fv[2][a] + (1 - s_) * t * fv[3][a];
+                xs[a] = (1 - t) * (fv[1][a] - fv[0][a]) + t * (fv[2][a] - fv[3][a]);
+                xt[a] = (1 - s_) * (fv[3][a] - fv[0][a]) + s_ * (fv[2][a] - fv[1][a]);
+            }
+            cross3(xs, xt, nrm);
+            const double len = sqrt(dot3(nrm, nrm));
+            for (int a = 0; a < 3; ++a) gn[g][a] = nrm[a] / len;
+            gw[g] = 0.25 * len;
+        }
+    return 4;
+}
+
+/*
+ * Builds the oracle mesh.  npc = 4 (tetrahedra) or 8 (hexahedra).  nbf boundary
+ * faces (bface_nodes [nbf][3 or 4], any order) with kinds ORC_BC_WALL / ORC_BC_FAR;
+ * a mesh with listed boundary faces has no periodic axis, and every face that
+ * belongs to one cell must then be listed.
+ */
+orc_mesh *orc_mesh_new2(int64_t nn, const double *xyz, int64_t nc, int npc, const int64_t *cell_nodes,
+                        const double *period, int64_t nbf, const int64_t *bface_nodes, const int *bface_kind,
+                        char *err, int errlen) {
+    if (nn <= 0 || nc <= 0 || !xyz || !cell_nodes || (npc != 4 && npc != 8)) { set_err(err, errlen, "empty mesh or bad cell type"); return NULL; }
+    const int nfc = npc == 4 ? 4 : 6, nk = npc == 4 ? 3 : 4;
+    if (nbf > 0) {
+        if (!bface_nodes || !bface_kind) { set_err(err, errlen, "boundary faces without nodes or kinds"); return NULL; }
+        for (int a = 0; a < 3; ++a)
+            if (period && period[a] > 0.0) { set_err(err, errlen, "listed boundary faces need a mesh without periodic axes"); return NULL; }
+        for (int64_t k = 0; k < nbf; ++k)
+            if (bface_kind[k] != ORC_BC_WALL && bface_kind[k] != ORC_BC_FAR) { set_err(err, errlen, "unknown boundary kind"); return NULL; }
+    }
     orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
     m->nc = nc; m->nn = nn;
+    m->npc = npc; m->nfc = nfc; m->ngp = npc == 4 ? 3 : 4; m->msub = npc == 4 ? 4 : 8;
     for (int a = 0; a < 3; ++a) m->period[a] = period ? period[a] : 0.0;
-    m->vert = malloc(sizeof(*m->vert) * nc);
+    m->vert = calloc((size_t)nc, sizeof(*m->vert));
     m->vol = malloc(sizeof(double) * nc);
     m->cen = malloc(sizeof(*m->cen) * nc);
     m->h = malloc(sizeof(double) * nc);
@@ -299,108 +506,184 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
 
     /* unwrap every cell around its first node; volume, centroid */
     for (int64_t c = 0; c < nc; ++c) {
-        for (int q = 0; q < 4; ++q) {
-            int64_t nid = cell_nodes[c * 4 + q];
+        for (int q = 0; q < npc; ++q) {
+            int64_t nid = cell_nodes[c * npc + q];
             if (nid < 0 || nid >= nn) { set_err(err, errlen, "node id out of range"); orc_mesh_free(m); return NULL; }
         }
-        const double *x0 = xyz + 3 * cell_nodes[c * 4];
-        for (int q = 0; q < 4; ++q) {
-            const double *xq = xyz + 3 * cell_nodes[c * 4 + q];
+        const double *x0 = xyz + 3 * cell_nodes[c * npc];
+        for (int q = 0; q < npc; ++q) {
+            const double *xq = xyz + 3 * cell_nodes[c * npc + q];
             for (int a = 0; a < 3; ++a) {
                 double d = xq[a] - x0[a];
                 if (m->period[a] > 0.0) d -= m->period[a] * nearbyint(d / m->period[a]);
                 m->vert[c][q][a] = x0[a] + d;
             }
         }
-        double e1[3], e2[3], e3[3], cr[3];
-        sub3(m->vert[c][1], m->vert[c][0], e1);
-        sub3(m->vert[c][2], m->vert[c][0], e2);
-        sub3(m->vert[c][3], m->vert[c][0], e3);
-        cross3(e2, e3, cr);
-        double v = fabs(dot3(e1, cr)) / 6.0;
         double ext = 0.0;
-        for (int a = 0; a < 3; ++a) ext = fmax(ext, fabs(e1[a]) + fabs(e2[a]) + fabs(e3[a]));
-        if (!(v > 1e-12 * ext * ext * ext)) { set_err(err, errlen, "degenerate tetrahedron"); orc_mesh_free(m); return NULL; }
-        m->vol[c] = v;
-        m->h[c] = cbrt(v);
-        for (int a = 0; a < 3; ++a)
-            m->cen[c][a] = 0.25 * (m->vert[c][0][a] + m->vert[c][1][a] + m->vert[c][2][a] + m->vert[c][3][a]);
+        for (int q = 1; q < npc; ++q)
+            for (int a = 0; a < 3; ++a) ext = fmax(ext, fabs(m->vert[c][q][a] - m->vert[c][0][a]));
+        if (npc == 4) {
+            double e1[3], e2[3], e3[3], cr[3];
+            sub3(m->vert[c][1], m->vert[c][0], e1);
+            sub3(m->vert[c][2], m->vert[c][0], e2);
+            sub3(m->vert[c][3], m->vert[c][0], e3);
+            cross3(e2, e3, cr);
+            double v = fabs(dot3(e1, cr)) / 6.0;
+            ext = 0.0;
+            for (int a = 0; a < 3; ++a) ext = fmax(ext, fabs(e1[a]) + fabs(e2[a]) + fabs(e3[a]));
+            if (!(v > 1e-12 * ext * ext * ext)) { set_err(err, errlen, "degenerate tetrahedron"); orc_mesh_free(m); return NULL; }
+            m->vol[c] = v;
+            for (int a = 0; a < 3; ++a)
+                m->cen[c][a] = 0.25 * (m->vert[c][0][a] + m->vert[c][1][a] + m->vert[c][2][a] + m->vert[c][3][a]);
+        } else {
+            double pts[MAXCQ][3], wts[MAXCQ], jlo, jhi;
+            const int n = cell_quadrature(npc, m->vert[c], pts, wts, &jlo, &jhi);
+            /* the trilinear map must not fold: one Jacobian sign at every point */
+            if (!(jlo * jhi > 0.0) || !(fmin(fabs(jlo), fabs(jhi)) > 1e-12 * ext * ext * ext)) {
+                set_err(err, errlen, "degenerate or folded hexahedron"); orc_mesh_free(m); return NULL;
+            }
+            double V = 0.0, cx[3] = {0, 0, 0};
+            for (int q = 0; q < n; ++q) {
+                V += wts[q];
+                for (int a = 0; a < 3; ++a) cx[a] += wts[q] * pts[q][a];
+            }
+            m->vol[c] = V;
+            for (int a = 0; a < 3; ++a) m->cen[c][a] = cx[a] / V;
+        }
+        m->h[c] = cbrt(m->vol[c]);
     }
 
-    /* faces: match the node triples of all cell faces (CellFace / FaceCell) */
-    face_rec *fr = malloc(sizeof(face_rec) * nc * 4);
+    /* listed boundary faces, sorted by key for lookup */
+    int64_t (*bkey)[4] = NULL;
+    int *bkind = NULL;
+    int64_t *border = NULL;
+    if (nbf > 0) {
+        bkey = malloc(sizeof(*bkey) * nbf);
+        bkind = malloc(sizeof(int) * nbf);
+        face_rec *br = malloc(sizeof(face_rec) * nbf);
+        for (int64_t k = 0; k < nbf; ++k) {
+            face_key(bface_nodes + k * nk, nk, br[k].key);
+            br[k].cell = k; br[k].p = 0;
+        }
+        qsort(br, (size_t)nbf, sizeof(face_rec), cmp_face);
+        border = malloc(sizeof(int64_t) * nbf);
+        for (int64_t k = 0; k < nbf; ++k) { memcpy(bkey[k], br[k].key, sizeof(bkey[k])); bkind[k] = bface_kind[br[k].cell]; border[k] = br[k].cell; }
+        free(br);
+    }
+
+    /* faces: match the node sets of all cell faces (CellFace / FaceCell) */
+    face_rec *fr = malloc(sizeof(face_rec) * nc * nfc);
     for (int64_t c = 0; c < nc; ++c)
-        for (int p = 0; p < 4; ++p) {
-            face_rec *r = &fr[c * 4 + p];
-            int k = 0;
-            for (int q = 0; q < 4; ++q) if (q != p) r->key[k++] = cell_nodes[c * 4 + q];
-            sort3(r->key);
+        for (int p = 0; p < nfc; ++p) {
+            face_rec *r = &fr[c * nfc + p];
+            int64_t nodes[4];
+            for (int k = 0; k < nk; ++k) nodes[k] = cell_nodes[c * npc + face_node(npc, p, k)];
+            face_key(nodes, nk, r->key);
             r->cell = c; r->p = p;
         }
-    qsort(fr, (size_t)(nc * 4), sizeof(face_rec), cmp_face);
+    const int64_t nrec = nc * nfc;
+    qsort(fr, (size_t)nrec, sizeof(face_rec), cmp_face);
     int64_t nf = 0;
-    for (int64_t k = 0; k < nc * 4;) {
+    for (int64_t k = 0; k < nrec;) {
         int64_t j = k + 1;
-        while (j < nc * 4 && memcmp(fr[j].key, fr[k].key, sizeof(fr[k].key)) == 0) ++j;
-        if (j - k > 2) { set_err(err, errlen, "non-conforming face"); free(fr); orc_mesh_free(m); return NULL; }
+        while (j < nrec && cmp_key(fr[j].key, fr[k].key) == 0) ++j;
+        if (j - k > 2) { set_err(err, errlen, "non-conforming face"); free(fr); free(bkey); free(bkind); free(border); orc_mesh_free(m); return NULL; }
         ++nf; k = j;
     }
     m->nf = nf;
     m->fcell = malloc(sizeof(*m->fcell) * nf);
+    m->fkind = calloc((size_t)nf, sizeof(int));
     m->fshift = malloc(sizeof(*m->fshift) * nf);
     m->fnrm = malloc(sizeof(*m->fnrm) * nf);
     m->farea = malloc(sizeof(double) * nf);
-    m->fgp = malloc(sizeof(*m->fgp) * nf);
+    m->fgp = calloc((size_t)nf, sizeof(*m->fgp));
+    m->fpn = calloc((size_t)nf, sizeof(*m->fpn));
+    m->fpw = calloc((size_t)nf, sizeof(*m->fpw));
+    m->gcell = malloc(sizeof(int64_t) * (nbf > 0 ? nbf : 1));
+    m->gface = malloc(sizeof(int64_t) * (nbf > 0 ? nbf : 1));
+    m->gkind = malloc(sizeof(int) * (nbf > 0 ? nbf : 1));
+    m->gpt = malloc(sizeof(*m->gpt) * (nbf > 0 ? nbf : 1));
+    m->gnrm = malloc(sizeof(*m->gnrm) * (nbf > 0 ? nbf : 1));
+    m->ng = 0;
+    unsigned char *bused = nbf > 0 ? calloc((size_t)nbf, 1) : NULL;
     double *asum = calloc((size_t)nc, sizeof(double));
     int64_t f = 0;
-    for (int64_t k = 0; k < nc * 4; ++f) {
-        const int wall = k + 1 >= nc * 4 || memcmp(fr[k + 1].key, fr[k].key, sizeof(fr[k].key)) != 0;
-        const face_rec *A = &fr[k], *B = wall ? NULL : &fr[k + 1];     /* A->cell <= B->cell */
-        k += wall ? 1 : 2;
+    const char *fail = NULL;
+    for (int64_t k = 0; k < nrec && !fail; ++f) {
+        const int single = k + 1 >= nrec || cmp_key(fr[k + 1].key, fr[k].key) != 0;
+        const face_rec *A = &fr[k], *B = single ? NULL : &fr[k + 1];     /* A->cell <= B->cell */
+        k += single ? 1 : 2;
         int64_t l = A->cell;
         int pl = A->p;
         m->fcell[f][0] = l;
         m->cface[l][pl] = f;
-        /* face vertices in the left frame */
-        double tri[3][3];
-        int t = 0;
-        for (int q = 0; q < 4; ++q) if (q != pl) { memcpy(tri[t], m->vert[l][q], sizeof(tri[t])); ++t; }
-        double e1[3], e2[3], nrm[3];
-        sub3(tri[1], tri[0], e1);
-        sub3(tri[2], tri[0], e2);
-        cross3(e1, e2, nrm);
-        double len = sqrt(dot3(nrm, nrm));
-        m->farea[f] = 0.5 * len;
-        for (int a = 0; a < 3; ++a) nrm[a] /= len;
-        double fc[3], d[3];
-        for (int a = 0; a < 3; ++a) fc[a] = (tri[0][a] + tri[1][a] + tri[2][a]) / 3.0;
+        /* face vertices in the left frame, cyclic order */
+        double fv[4][3];
+        for (int q = 0; q < nk; ++q) memcpy(fv[q], m->vert[l][face_node(npc, pl, q)], sizeof(fv[q]));
+        double gw[MAXGP];
+        const int ng = face_points(nk, fv, m->fgp[f], m->fpn[f], gw);
+        /* orient out of the left cell: the weighted normals give the vector area */
+        double va[3] = {0, 0, 0}, fc[3] = {0, 0, 0}, area = 0.0;
+        for (int g = 0; g < ng; ++g) {
+            area += gw[g];
+            for (int a = 0; a < 3; ++a) { va[a] += gw[g] * m->fpn[f][g][a]; fc[a] += m->fgp[f][g][a] / ng; }
+        }
+        double d[3];
         sub3(fc, m->cen[l], d);
-        if (dot3(nrm, d) < 0.0) for (int a = 0; a < 3; ++a) nrm[a] = -nrm[a];
-        memcpy(m->fnrm[f], nrm, sizeof(nrm));
-        /* 3-point degree-2 rule: barycentric permutations of (2/3, 1/6, 1/6) */
-        for (int g = 0; g < 3; ++g)
-            for (int a = 0; a < 3; ++a) {
-                double s_ = 0.0;
-                for (int v = 0; v < 3; ++v) s_ += (v == g ? 2.0 / 3.0 : 1.0 / 6.0) * tri[v][a];
-                m->fgp[f][g][a] = s_;
-            }
+        const double sg = dot3(va, d) < 0.0 ? -1.0 : 1.0;
+        const double vlen = sqrt(dot3(va, va));
+        for (int a = 0; a < 3; ++a) m->fnrm[f][a] = npc == 4 ? sg * m->fpn[f][0][a] : sg * va[a] / vlen;
+        for (int g = 0; g < ng; ++g) {
+            for (int a = 0; a < 3; ++a) m->fpn[f][g][a] *= sg;
+            m->fpw[f][g] = gw[g];
+        }
+        m->farea[f] = area;
+        if (npc == 4) {   /* the triangle's area, as 0.5 |e1 x e2| */
+            double e1[3], e2[3], nrm[3];
+            sub3(fv[1], fv[0], e1);
+            sub3(fv[2], fv[0], e2);
+            cross3(e1, e2, nrm);
+            m->farea[f] = 0.5 * sqrt(dot3(nrm, nrm));
+        }
         asum[l] += m->farea[f];
-        if (wall) {
-            /* a wall of a non-periodic axis: all three nodes on the lowest or highest coordinate */
+        if (single) {
+            m->fcell[f][1] = -1;
+            for (int a = 0; a < 3; ++a) m->fshift[f][a] = 0.0;
+            if (nbf > 0) {
+                /* a listed boundary face: a ghost of the given kind */
+                int64_t lo_ = 0, hi_ = nbf - 1, at = -1;
+                while (lo_ <= hi_) {
+                    int64_t mid = (lo_ + hi_) / 2;
+                    int c = cmp_key(bkey[mid], A->key);
+                    if (c == 0) { at = mid; break; }
+                    if (c < 0) lo_ = mid + 1; else hi_ = mid - 1;
+                }
+                if (at < 0) { fail = "a face of one cell is not in the boundary-face list"; break; }
+                bused[at] = 1;
+                const int64_t g = m->ng++;
+                m->fkind[f] = bkind[at];
+                m->gcell[g] = l; m->gface[g] = f; m->gkind[g] = bkind[at];
+                memcpy(m->gnrm[g], m->fnrm[f], sizeof(m->gnrm[g]));
+                for (int a = 0; a < 3; ++a) m->gpt[g][a] = fc[a];
+                m->nb[l][pl] = nc + g;
+                m->nbx[l][pl] = XID;
+                continue;
+            }
+            /* a wall of a non-periodic axis: all nodes on the lowest or highest coordinate */
             int axis = -1;
             double w = 0.0;
             for (int a = 0; a < 3 && axis < 0; ++a) {
                 if (m->period[a] > 0.0) continue;
-                const double x0 = xyz[3 * A->key[0] + a], x1 = xyz[3 * A->key[1] + a], x2 = xyz[3 * A->key[2] + a];
-                if (x0 == x1 && x1 == x2 && (x0 == m->lo[a] || x0 == m->hi[a])) { axis = a; w = x0; }
+                const double x0 = xyz[3 * A->key[0] + a];
+                int on = x0 == m->lo[a] || x0 == m->hi[a];
+                for (int q = 1; q < nk; ++q) on = on && xyz[3 * A->key[q] + a] == x0;
+                if (on) { axis = a; w = x0; }
             }
             if (axis < 0) {
-                set_err(err, errlen, "boundary face off the walls (an unmatched face must lie on the lowest or highest "
-                                     "coordinate of a non-periodic axis)");
-                free(fr); free(asum); orc_mesh_free(m); return NULL;
+                fail = "boundary face off the walls (an unmatched face must lie on the lowest or highest "
+                       "coordinate of a non-periodic axis)";
+                break;
             }
-            m->fcell[f][1] = -1;
-            for (int a = 0; a < 3; ++a) m->fshift[f][a] = 0.0;
             m->nb[l][pl] = l;
             m->nbx[l][pl] = XID;
             m->nbx[l][pl].s[axis] = -1.0;
@@ -411,10 +694,10 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
         int pr = B->p;
         m->fcell[f][1] = r;
         m->cface[r][pr] = f;
-        /* the right cell's image shift in the left frame */
-        int64_t n0 = cell_nodes[l * 4 + (pl == 0 ? 1 : 0)];
+        /* the right cell's image shift in the left frame, from a shared node */
+        int64_t n0 = cell_nodes[l * npc + face_node(npc, pl, 0)];
         int ql = -1, qr = -1;
-        for (int q = 0; q < 4; ++q) { if (cell_nodes[l * 4 + q] == n0) ql = q; if (cell_nodes[r * 4 + q] == n0) qr = q; }
+        for (int q = 0; q < npc; ++q) { if (cell_nodes[l * npc + q] == n0) ql = q; if (cell_nodes[r * npc + q] == n0) qr = q; }
         sub3(m->vert[l][ql], m->vert[r][qr], m->fshift[f]);
         asum[r] += m->farea[f];
         m->nb[l][pl] = r;
@@ -423,30 +706,34 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
         m->nbx[r][pr] = XID;
         for (int a = 0; a < 3; ++a) { m->nbx[l][pl].o[a] = m->fshift[f][a]; m->nbx[r][pr].o[a] = -m->fshift[f][a]; }
     }
-    free(fr);
+    if (!fail)
+        for (int64_t k = 0; k < nbf; ++k)
+            if (!bused[k]) { fail = "a listed boundary face is not a face of exactly one cell"; break; }
+    free(fr); free(bkey); free(bkind); free(border); free(bused);
+    if (fail) { set_err(err, errlen, fail); free(asum); orc_mesh_free(m); return NULL; }
     for (int64_t c = 0; c < nc; ++c) m->hdt[c] = 6.0 * m->vol[c] / asum[c];
     free(asum);
 
-    /* two-layer stencil (Algorithm 1, self excluded) and the tet sub-stencils (Sec. 2.3) */
+    /* two-layer stencil (Algorithm 1, self excluded) and the sub-stencils (Sec. 2.3).
+     * A ghost of a listed boundary face is a member but has no neighbours. */
     m->nsten = malloc(sizeof(int) * nc);
     m->sten = malloc(sizeof(*m->sten) * nc);
     m->stx = malloc(sizeof(*m->stx) * nc);
-    m->nsub = malloc(sizeof(*m->nsub) * nc);
+    m->nsub = calloc((size_t)nc, sizeof(*m->nsub));
     m->sub = malloc(sizeof(*m->sub) * nc);
     m->subx = malloc(sizeof(*m->subx) * nc);
-    /* S_1 = {i1,i2,i3} + N(i1), S_2 = {i1,i2,i4} + N(i2), S_3 = {i2,i3,i4} + N(i3), S_4 = {i3,i1,i4} + N(i4) */
-    static const int SUBFIRST[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {2, 0, 3}};
     for (int64_t i = 0; i < nc; ++i) {
         /* a neighbour's neighbours are placed by composing the two placements */
         int n = 0;
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < nfc; ++p) {
             int dup = same_member(m->nb[i][p], &m->nbx[i][p], i, &XID);
             for (int k = 0; k < n; ++k) dup |= same_member(m->sten[i][k], &m->stx[i][k], m->nb[i][p], &m->nbx[i][p]);
             if (!dup) { m->sten[i][n] = m->nb[i][p]; m->stx[i][n] = m->nbx[i][p]; ++n; }
         }
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < nfc; ++p) {
             int64_t j = m->nb[i][p];
-            for (int q = 0; q < 4; ++q) {
+            if (j >= nc) continue;                           /* a ghost: no neighbours */
+            for (int q = 0; q < nfc; ++q) {
                 int64_t c = m->nb[j][q];
                 xform x = compose(&m->nbx[i][p], &m->nbx[j][q]);
                 int dup = same_member(c, &x, i, &XID);
@@ -458,21 +745,23 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
             }
         }
         m->nsten[i] = n;
-        for (int s_ = 0; s_ < 4; ++s_) {
+        for (int s_ = 0; s_ < m->msub; ++s_) {
             int k = 0;
             for (int t = 0; t < 3; ++t) {
-                int p = SUBFIRST[s_][t];
+                int p = npc == 4 ? TETSUB[s_][t] : HEXSUB[s_][t];
                 int dup = 0;
                 for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], &m->subx[i][s_][u], m->nb[i][p], &m->nbx[i][p]);
                 if (!dup) { m->sub[i][s_][k] = m->nb[i][p]; m->subx[i][s_][k] = m->nbx[i][p]; ++k; }
             }
-            int64_t j = m->nb[i][s_];
-            for (int q = 0; q < 4; ++q) {
-                int64_t c = m->nb[j][q];
-                xform x = compose(&m->nbx[i][s_], &m->nbx[j][q]);
-                int dup = same_member(c, &x, i, &XID);
-                for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], &m->subx[i][s_][u], c, &x);
-                if (!dup) { m->sub[i][s_][k] = c; m->subx[i][s_][k] = x; ++k; }
+            if (npc == 4 && m->nb[i][s_] < nc) {             /* tet: add N(i_m) */
+                int64_t j = m->nb[i][s_];
+                for (int q = 0; q < 4; ++q) {
+                    int64_t c = m->nb[j][q];
+                    xform x = compose(&m->nbx[i][s_], &m->nbx[j][q]);
+                    int dup = same_member(c, &x, i, &XID);
+                    for (int u = 0; u < k; ++u) dup |= same_member(m->sub[i][s_][u], &m->subx[i][s_][u], c, &x);
+                    if (!dup) { m->sub[i][s_][k] = c; m->subx[i][s_][k] = x; ++k; }
+                }
             }
             m->nsub[i][s_] = k;
         }
@@ -480,17 +769,30 @@ orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t 
     return m;
 }
 
+orc_mesh *orc_mesh_new(int64_t nn, const double *xyz, int64_t nc, const int64_t *cell_nodes,
+                       const double *period, char *err, int errlen) {
+    return orc_mesh_new2(nn, xyz, nc, 4, cell_nodes, period, 0, NULL, NULL, err, errlen);
+}
+
 void orc_mesh_free(orc_mesh *m) {
     if (!m) return;
     free(m->vert); free(m->vol); free(m->cen); free(m->h); free(m->hdt);
-    free(m->fcell); free(m->fshift); free(m->fnrm); free(m->farea); free(m->fgp);
+    free(m->fcell); free(m->fkind); free(m->fshift); free(m->fnrm); free(m->farea); free(m->fgp);
+    free(m->fpn); free(m->fpw);
     free(m->cface); free(m->nb); free(m->nbx);
+    free(m->gcell); free(m->gface); free(m->gkind); free(m->gpt); free(m->gnrm);
     free(m->nsten); free(m->sten); free(m->stx); free(m->nsub); free(m->sub); free(m->subx);
     free(m);
 }
 
 /* accessors for tests */
 int64_t orc_mesh_nfaces(const orc_mesh *m) { return m->nf; }
+/* info [6]: nodes per cell, faces per cell, Gauss points per face, sub-stencils, ghosts, max stencil size */
+void orc_mesh_info(const orc_mesh *m, int64_t *info) {
+    int64_t mx = 0;
+    for (int64_t i = 0; i < m->nc; ++i) if (m->nsten[i] > mx) mx = m->nsten[i];
+    info[0] = m->npc; info[1] = m->nfc; info[2] = m->ngp; info[3] = m->msub; info[4] = m->ng; info[5] = mx;
+}
 void orc_mesh_cells(const orc_mesh *m, double *vol, double *cen, double *hdt) {
     for (int64_t c = 0; c < m->nc; ++c) {
         if (vol) vol[c] = m->vol[c];
@@ -498,30 +800,43 @@ void orc_mesh_cells(const orc_mesh *m, double *vol, double *cen, double *hdt) {
         if (hdt) hdt[c] = m->hdt[c];
     }
 }
+/* gp [nf][ngp][3] */
 void orc_mesh_faces(const orc_mesh *m, int64_t *lr, double *nrm, double *area, double *shift, double *gp) {
     for (int64_t f = 0; f < m->nf; ++f) {
         if (lr) { lr[2 * f] = m->fcell[f][0]; lr[2 * f + 1] = m->fcell[f][1]; }
         if (nrm) memcpy(nrm + 3 * f, m->fnrm[f], sizeof(double) * 3);
         if (area) area[f] = m->farea[f];
         if (shift) memcpy(shift + 3 * f, m->fshift[f], sizeof(double) * 3);
-        if (gp) memcpy(gp + 9 * f, m->fgp[f], sizeof(double) * 9);
+        if (gp) for (int g = 0; g < m->ngp; ++g) memcpy(gp + 3 * (m->ngp * f + g), m->fgp[f][g], sizeof(double) * 3);
     }
 }
-/* stencil of cell i: returns K; members[K], shifts[K][3]; sub-stencil sizes[4], members[4][MAXSUB] */
+/* per Gauss point unit normals pn [nf][ngp][3] and weights pw [nf][ngp]; kind [nf] */
+void orc_mesh_face_points(const orc_mesh *m, double *pn, double *pw, int *kind) {
+    for (int64_t f = 0; f < m->nf; ++f) {
+        for (int g = 0; g < m->ngp; ++g) {
+            if (pn) memcpy(pn + 3 * (m->ngp * f + g), m->fpn[f][g], sizeof(double) * 3);
+            if (pw) pw[m->ngp * f + g] = m->fpw[f][g];
+        }
+        if (kind) kind[f] = m->fkind[f];
+    }
+}
+/* stencil of cell i: returns K; members[K] (ids >= nc are ghosts), shifts[K][3];
+ * sub-stencil sizes[msub], members[msub][MAXSUB] */
 int orc_mesh_stencil(const orc_mesh *m, int64_t i, int64_t *members, double *shifts, int *nsub, int64_t *sub) {
     int n = m->nsten[i];
     for (int k = 0; k < n; ++k) {
         if (members) members[k] = m->sten[i][k];
         if (shifts) memcpy(shifts + 3 * k, m->stx[i][k].o, sizeof(double) * 3);   /* offsets (s = 1 unless mirrored) */
     }
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < m->msub; ++s) {
         if (nsub) nsub[s] = m->nsub[i][s];
         if (sub) for (int k = 0; k < MAXSUB; ++k) sub[s * MAXSUB + k] = k < m->nsub[i][s] ? m->sub[i][s][k] : -1;
     }
     return n;
 }
+/* nb [nc][nfc] */
 void orc_mesh_neighbors(const orc_mesh *m, int64_t *nb) {
-    for (int64_t c = 0; c < m->nc; ++c) for (int p = 0; p < 4; ++p) nb[4 * c + p] = m->nb[c][p];
+    for (int64_t c = 0; c < m->nc; ++c) for (int p = 0; p < m->nfc; ++p) nb[m->nfc * c + p] = m->nb[c][p];
 }
 
 /* ------------------------------------------------------------------------- */
