@@ -840,72 +840,155 @@ void orc_mesh_neighbors(const orc_mesh *m, int64_t *nb) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* ghosts of listed boundary faces (Sec. 5.2)                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { double rho, U, V, W, lam, p; } prim;
+
+static prim primitives(const double *q, double gamma) {
+    prim s;
+    s.rho = q[0];
+    s.U = q[1] / q[0]; s.V = q[2] / q[0]; s.W = q[3] / q[0];
+    s.p = (gamma - 1.0) * (q[4] - 0.5 * s.rho * (s.U * s.U + s.V * s.V + s.W * s.W));
+    s.lam = s.rho / (2.0 * s.p);
+    return s;
+}
+
+static void conservative(double rho, const double *U, double pr, double gamma, double *q) {
+    q[0] = rho;
+    for (int a = 0; a < 3; ++a) q[1 + a] = rho * U[a];
+    q[4] = pr / (gamma - 1.0) + 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+}
+
+/*
+ * Far-field state by Riemann invariants (characteristic boundary): with the outward
+ * normal n, interior state q and free stream (rho, U, p)_inf,
+ *   R+ = U.n + 2c/(gamma-1) from the interior, R- = U_inf.n - 2c_inf/(gamma-1) from
+ *   outside; the boundary normal velocity (R+ + R-)/2 and sound speed
+ *   (gamma-1)(R+ - R-)/4; entropy p/rho^gamma and tangential velocity from the
+ *   interior at an outflow, from the free stream at an inflow.  A supersonic outflow
+ *   takes the interior state, a supersonic inflow the free stream.
+ */
+static void farfield_state(const orc_params *p, const double *q, const double *n, double *out) {
+    const double g = p->gamma;
+    const prim si = primitives(q, g);
+    const double Ui[3] = {si.U, si.V, si.W};
+    const double *Uf = p->farfield + 1;
+    const double rf = p->farfield[0], pf = p->farfield[4];
+    const double ci = sqrt(g * si.p / si.rho), cf = sqrt(g * pf / rf);
+    const double vi = dot3(Ui, n), vf = dot3(Uf, n);
+    if (vi >= ci) { memcpy(out, q, sizeof(double) * 5); return; }
+    if (vi <= -ci) { conservative(rf, Uf, pf, g, out); return; }
+    const double Rp = vi + 2.0 * ci / (g - 1.0), Rm = vf - 2.0 * cf / (g - 1.0);
+    const double vb = 0.5 * (Rp + Rm), cb = 0.25 * (g - 1.0) * (Rp - Rm);
+    const int outflow = vb > 0.0;
+    const double ent = outflow ? si.p / pow(si.rho, g) : pf / pow(rf, g);
+    const double *Ut = outflow ? Ui : Uf;
+    const double vt = outflow ? vi : vf;
+    const double rb = pow(cb * cb / (g * ent), 1.0 / (g - 1.0));
+    const double pb = rb * cb * cb / g;
+    double Ub[3];
+    for (int a = 0; a < 3; ++a) Ub[a] = Ut[a] - vt * n[a] + vb * n[a];
+    conservative(rb, Ub, pb, g, out);
+}
+
+/* the state a boundary-face ghost holds for the adjacent state q */
+static void ghost_state(const orc_params *p, int kind, const double *q, const double *n, double *out) {
+    if (kind == ORC_BC_WALL) {                       /* zero velocity on the face, same temperature */
+        out[0] = q[0]; out[1] = -q[1]; out[2] = -q[2]; out[3] = -q[3]; out[4] = q[4];
+    } else {
+        farfield_state(p, q, n, out);
+    }
+}
+
+/* state of a stencil member (a cell or a ghost) */
+static void member_state(const orc_mesh *m, const orc_params *p, const double *Q, int64_t id, double *out) {
+    if (id < m->nc) { memcpy(out, Q + 5 * id, sizeof(double) * 5); return; }
+    const int64_t g = id - m->nc;
+    ghost_state(p, m->gkind[g], Q + 5 * m->gcell[g], m->gnrm[g], out);
+}
+
+/* ------------------------------------------------------------------------- */
 /* WENO reconstruction (Sec. 2.3)                                            */
 /* ------------------------------------------------------------------------- */
 
 typedef struct {
-    double a[5][9];        /* P0 coefficients, per variable */
-    double b[4][5][3];     /* P_m coefficients (linear), per sub-stencil and variable */
-    double beta[5][5];     /* [variable][m], m = 0..4 */
-    double wbar[5][5];     /* normalised non-linear weights [variable][m] */
-    double mean_i[9];      /* mean over the cell of xi^d */
+    double a[5][9];          /* P0 coefficients, per variable */
+    double b[MAXM][5][3];    /* P_m coefficients (linear), per sub-stencil and variable */
+    double beta[5][MAXM + 1];   /* [variable][m], m = 0..M */
+    double wbar[5][MAXM + 1];   /* normalised non-linear weights [variable][m] */
+    double mean_i[9];        /* mean over the cell of xi^d */
 } orc_weno;
 
-/* A member's vertices placed in the target cell's frame (periodic image or mirror). */
-static void member_vertices(const orc_mesh *m, int64_t k, const xform *x, double v[4][3]) {
-    for (int q = 0; q < 4; ++q) for (int a = 0; a < 3; ++a) v[q][a] = x->s[a] * m->vert[k][q][a] + x->o[a];
+/* A member's vertices placed in the target cell's frame: a periodic image or axis
+ * mirror of a cell, or a boundary ghost (the cell's mirror image in the face plane). */
+static void member_vertices(const orc_mesh *m, int64_t k, const xform *x, double v[8][3]) {
+    if (k >= m->nc) {
+        const int64_t g = k - m->nc;
+        const double *pt = m->gpt[g], *n = m->gnrm[g];
+        for (int q = 0; q < m->npc; ++q) {
+            const double *y = m->vert[m->gcell[g]][q];
+            const double d = (y[0] - pt[0]) * n[0] + (y[1] - pt[1]) * n[1] + (y[2] - pt[2]) * n[2];
+            for (int a = 0; a < 3; ++a) v[q][a] = y[a] - 2.0 * d * n[a];
+        }
+        return;
+    }
+    for (int q = 0; q < m->npc; ++q) for (int a = 0; a < 3; ++a) v[q][a] = x->s[a] * m->vert[k][q][a] + x->o[a];
 }
 
 static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i, orc_weno *w) {
     const double *ci = m->cen[i];
     const double hi = m->h[i];
-    tet_monomial_means(m->vert[i], ci, hi, w->mean_i);
+    const int M = m->msub;
+    cell_monomial_means(m->npc, m->vert[i], ci, hi, w->mean_i);
     /* quadratic P0 on the big stencil: constraints (1/|Omega_k|) int_{Omega_k} P0 = Q_k */
     int K = m->nsten[i];
     double A[MAXSTEN * 9], B[MAXSTEN * 5];
     for (int k = 0; k < K; ++k) {
-        double v[4][3], mk[9];
+        double v[8][3], mk[9], qk[5];
         member_vertices(m, m->sten[i][k], &m->stx[i][k], v);
-        tet_monomial_means(v, ci, hi, mk);
+        cell_monomial_means(m->npc, v, ci, hi, mk);
+        member_state(m, p, Q, m->sten[i][k], qk);
         for (int d = 0; d < 9; ++d) A[k * 9 + d] = mk[d] - w->mean_i[d];
-        for (int q = 0; q < 5; ++q) B[k * 5 + q] = Q[5 * m->sten[i][k] + q] - Q[5 * i + q];
+        for (int q = 0; q < 5; ++q) B[k * 5 + q] = qk[q] - Q[5 * i + q];
     }
     double X[9 * 5];
     if (lsq_normal(K, 9, A, 5, B, X)) return ORC_E_MESH;
     for (int d = 0; d < 9; ++d) for (int q = 0; q < 5; ++q) w->a[q][d] = X[d * 5 + q];
     /* linear P_m on the sub-stencils */
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < M; ++s) {
         int n = m->nsub[i][s];
         double As[MAXSUB * 3], Bs[MAXSUB * 5], Xs[3 * 5];
         for (int k = 0; k < n; ++k) {
-            double v[4][3], mk[9];
+            double v[8][3], mk[9], qk[5];
             member_vertices(m, m->sub[i][s][k], &m->subx[i][s][k], v);
-            tet_monomial_means(v, ci, hi, mk);
+            cell_monomial_means(m->npc, v, ci, hi, mk);
+            member_state(m, p, Q, m->sub[i][s][k], qk);
             for (int d = 0; d < 3; ++d) As[k * 3 + d] = mk[d] - w->mean_i[d];
-            for (int q = 0; q < 5; ++q) Bs[k * 5 + q] = Q[5 * m->sub[i][s][k] + q] - Q[5 * i + q];
+            for (int q = 0; q < 5; ++q) Bs[k * 5 + q] = qk[q] - Q[5 * i + q];
         }
         if (lsq_normal(n, 3, As, 5, Bs, Xs)) return ORC_E_MESH;
         for (int d = 0; d < 3; ++d) for (int q = 0; q < 5; ++q) w->b[s][q][d] = Xs[d * 5 + q];
     }
     /* smoothness indicators: beta_m = sum_{1<=|l|<=r_m} |Omega|^(2|l|/3-1) int (d^l P_m)^2 dV,
-     * evaluated in physical coordinates with the degree-2 rule (exact for these integrands) */
-    double pts[4][3];
-    tet_points(m->vert[i], pts);
+     * evaluated in physical coordinates with the cell rule (exact for these integrands) */
+    double pts[MAXCQ][3], wts[MAXCQ];
+    const int nq = cell_quadrature(m->npc, m->vert[i], pts, wts, NULL, NULL);
     const double V = m->vol[i];
     const double w1 = pow(V, 2.0 / 3.0 - 1.0), w2 = pow(V, 4.0 / 3.0 - 1.0);
     static const int L2IDX[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
     for (int q = 0; q < 5; ++q) {
-        for (int s = 0; s < 5; ++s) {
+        for (int s = 0; s <= M; ++s) {
             int nd = s == 0 ? 9 : 3;
             const double *c = s == 0 ? w->a[q] : w->b[s - 1][q];
             double beta = 0.0;
             for (int j = 0; j < 3; ++j) {               /* |l| = 1 */
                 double integral = 0.0;
-                for (int g = 0; g < 4; ++g) {
+                for (int g = 0; g < nq; ++g) {
                     double xi[3] = {(pts[g][0] - ci[0]) / hi, (pts[g][1] - ci[1]) / hi, (pts[g][2] - ci[2]) / hi};
                     double dp = 0.0;
                     for (int d = 0; d < nd; ++d) dp += c[d] * dmono(DEXP[d], j, xi) / hi;
-                    integral += 0.25 * V * dp * dp;
+                    integral += (m->npc == 4 ? 0.25 * V : wts[g]) * dp * dp;
                 }
                 beta += w1 * integral;
             }
@@ -919,15 +1002,15 @@ static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, in
             }
             w->beta[q][s] = beta;
         }
-        /* WENO-Z non-linear weights */
-        double g[5];
-        g[0] = 1.0 - 4.0 * p->gamma_lin;
-        for (int s = 1; s < 5; ++s) g[s] = p->gamma_lin;
+        /* WENO-Z non-linear weights, gamma_0 = 1 - M gamma */
+        double g[MAXM + 1];
+        g[0] = 1.0 - (double)M * p->gamma_lin;
+        for (int s = 1; s <= M; ++s) g[s] = p->gamma_lin;
         double tauZ = 0.0;
-        for (int s = 1; s < 5; ++s) tauZ += fabs(w->beta[q][0] - w->beta[q][s]) / 4.0;
-        double om[5], sum = 0.0;
-        for (int s = 0; s < 5; ++s) { om[s] = g[s] * (1.0 + tauZ / (w->beta[q][s] + p->weno_eps)); sum += om[s]; }
-        for (int s = 0; s < 5; ++s) w->wbar[q][s] = om[s] / sum;
+        for (int s = 1; s <= M; ++s) tauZ += fabs(w->beta[q][0] - w->beta[q][s]) / (double)M;
+        double om[MAXM + 1], sum = 0.0;
+        for (int s = 0; s <= M; ++s) { om[s] = g[s] * (1.0 + tauZ / (w->beta[q][s] + p->weno_eps)); sum += om[s]; }
+        for (int s = 0; s <= M; ++s) w->wbar[q][s] = om[s] / sum;
     }
     return ORC_OK;
 }
@@ -936,11 +1019,12 @@ static int weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, in
 static void weno_eval(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i, const orc_weno *w,
                       const double *x, double *val, double grad[5][3]) {
     const double hi = m->h[i];
+    const int M = m->msub;
     double xi[3] = {(x[0] - m->cen[i][0]) / hi, (x[1] - m->cen[i][1]) / hi, (x[2] - m->cen[i][2]) / hi};
-    const double g0 = 1.0 - 4.0 * p->gamma_lin, gm = p->gamma_lin;
+    const double g0 = 1.0 - (double)M * p->gamma_lin, gm = p->gamma_lin;
     for (int q = 0; q < 5; ++q) {
-        double P[5], dP[5][3];
-        for (int s = 0; s < 5; ++s) {
+        double P[MAXM + 1], dP[MAXM + 1][3];
+        for (int s = 0; s <= M; ++s) {
             int nd = s == 0 ? 9 : 3;
             const double *c = s == 0 ? w->a[q] : w->b[s - 1][q];
             double v = Q[5 * i + q];
@@ -953,11 +1037,11 @@ static void weno_eval(const orc_mesh *m, const orc_params *p, const double *Q, i
             }
         }
         double v = w->wbar[q][0] * P[0] / g0;
-        for (int s = 1; s < 5; ++s) v += -w->wbar[q][0] * gm / g0 * P[s] + w->wbar[q][s] * P[s];
+        for (int s = 1; s <= M; ++s) v += -w->wbar[q][0] * gm / g0 * P[s] + w->wbar[q][s] * P[s];
         val[q] = v;
         for (int j = 0; j < 3; ++j) {
             double t = w->wbar[q][0] * dP[0][j] / g0;
-            for (int s = 1; s < 5; ++s) t += -w->wbar[q][0] * gm / g0 * dP[s][j] + w->wbar[q][s] * dP[s][j];
+            for (int s = 1; s <= M; ++s) t += -w->wbar[q][0] * gm / g0 * dP[s][j] + w->wbar[q][s] * dP[s][j];
             grad[q][j] = t;
         }
     }
@@ -1092,17 +1176,6 @@ static void to_local(const double *q, const double *n, const double *t1, const d
     out[4] = q[4];
 }
 
-typedef struct { double rho, U, V, W, lam, p; } prim;
-
-static prim primitives(const double *q, double gamma) {
-    prim s;
-    s.rho = q[0];
-    s.U = q[1] / q[0]; s.V = q[2] / q[0]; s.W = q[3] / q[0];
-    s.p = (gamma - 1.0) * (q[4] - 0.5 * s.rho * (s.U * s.U + s.V * s.V + s.W * s.W));
-    s.lam = s.rho / (2.0 * s.p);
-    return s;
-}
-
 /*
  * F(t) fitted linearly over [0, dt] (Eq. expansion-1).  Inputs are the
  * reconstructed left/right states at the Gauss point and their gradients in
@@ -1178,6 +1251,12 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
     /* collision time */
     double tau = 0.0;
     if (p->tau_mode == 1) tau = p->tau_eps * dt + p->tau_C * fabs(sl.p - sr.p) / (sl.p + sr.p) * dt;
+    const double p0 = s0.rho / (2.0 * s0.lam);
+    if (p->tau_mode == 2) {
+        /* viscous: mu = mu_ref (T0/T_ref)^mu_exp with T = p/rho, tau = mu/p0 + the jump term */
+        const double mu = p->mu_ref * pow((p0 / s0.rho) / p->T_ref, p->mu_exp);
+        tau = mu / p0 + p->tau_C * fabs(sl.p - sr.p) / (sl.p + sr.p) * dt;
+    }
     /* moments of the three pieces of f (Eq. flux) that the time integrals weight:
      * the equilibrium part, and the left/right initial parts on their half spaces */
     double e0[3][5], el[3][5], er[3][5];       /* [0]: <u psi>, [1]: sum_j <u u_j (a_j.psi) psi>, [2]: <u (A.psi) psi> */
@@ -1196,8 +1275,29 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
             er[2][a] += Ar[b] * expect(&Mrn, &P_UPP[0][b][a]);
         }
     }
-    /* time-integrated flux I(delta) = int_0^delta F(t) dt, for delta = dt and dt/2 */
-    double I[2][5];
+    /* for the Prandtl correction: the same three pieces without the factor u, i.e.
+     * the conserved moments W = <psi f> of the interface distribution */
+    const int prandtl = p->tau_mode == 2 && p->prandtl != 1.0;
+    double w0[3][5], wl[3][5], wr[3][5];
+    if (prandtl)
+        for (int a = 0; a < 5; ++a) {
+            w0[0][a] = expect(&M0, &PSI[a]); wl[0][a] = expect(&Mlp, &PSI[a]); wr[0][a] = expect(&Mrn, &PSI[a]);
+            w0[1][a] = wl[1][a] = wr[1][a] = 0.0;
+            w0[2][a] = wl[2][a] = wr[2][a] = 0.0;
+            for (int b = 0; b < 5; ++b) {
+                for (int j = 0; j < 3; ++j) {
+                    w0[1][a] += a0[j][b] * expect(&M0, &P_UPP[j][b][a]);
+                    wl[1][a] += al[j][b] * expect(&Mlp, &P_UPP[j][b][a]);
+                    wr[1][a] += ar[j][b] * expect(&Mrn, &P_UPP[j][b][a]);
+                }
+                w0[2][a] += A0[b] * expect(&M0, &P_PP[b][a]);
+                wl[2][a] += Al[b] * expect(&Mlp, &P_PP[b][a]);
+                wr[2][a] += Ar[b] * expect(&Mrn, &P_PP[b][a]);
+            }
+        }
+    /* time-integrated flux I(delta) = int_0^delta F(t) dt, for delta = dt and dt/2
+     * (and IW, the same integral of W) */
+    double I[2][5], IW[2][5];
     for (int h = 0; h < 2; ++h) {
         double d = h == 0 ? dt : 0.5 * dt;
         double q0, q1, q2, q3, q4, q5;
@@ -1211,10 +1311,15 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
             q4 = -2.0 * tau * tau + tau * (d + 2.0 * tau) * E;
             q5 = -tau * tau * (1.0 - E);
         }
-        for (int a = 0; a < 5; ++a)
+        for (int a = 0; a < 5; ++a) {
             I[h][a] = s0.rho * (q0 * e0[0][a] + q1 * e0[1][a] + q2 * e0[2][a])
                     + sl.rho * (q3 * el[0][a] + q4 * el[1][a] + q5 * el[2][a])
                     + sr.rho * (q3 * er[0][a] + q4 * er[1][a] + q5 * er[2][a]);
+            IW[h][a] = !prandtl ? 0.0
+                     : s0.rho * (q0 * w0[0][a] + q1 * w0[1][a] + q2 * w0[2][a])
+                     + sl.rho * (q3 * wl[0][a] + q4 * wl[1][a] + q5 * wl[2][a])
+                     + sr.rho * (q3 * wr[0][a] + q4 * wr[1][a] + q5 * wr[2][a]);
+        }
     }
     /* solve  F dt + dF dt^2/2 = I(dt),  F dt/2 + dF dt^2/8 = I(dt/2)  (Cramer) */
     const double m11 = dt, m12 = 0.5 * dt * dt, m21 = 0.5 * dt, m22 = dt * dt / 8.0;
@@ -1223,6 +1328,24 @@ int orc_gks_flux(const orc_params *p, const double *ql, const double *gl /*[5][3
     for (int a = 0; a < 5; ++a) {
         Fl[a] = (I[0][a] * m22 - m12 * I[1][a]) / det;
         dFl[a] = (m11 * I[1][a] - I[0][a] * m21) / det;
+    }
+    if (prandtl) {
+        /* heat flux of f in the frame of U0: q = 1/2 <(u - U0)_n ((u - U0)^2 + xi^2) f>
+         *   = F_E - U0.F_m + |U0|^2/2 F_rho - U0_n (W_E - U0.W_m + |U0|^2/2 W_rho),
+         * fitted in time like F; the energy flux takes (1/Pr - 1) q */
+        const double U0[3] = {s0.U, s0.V, s0.W};
+        const double u2 = 0.5 * dot3(U0, U0);
+        double Wf[5], dWf[5];
+        for (int a = 0; a < 5; ++a) {
+            Wf[a] = (IW[0][a] * m22 - m12 * IW[1][a]) / det;
+            dWf[a] = (m11 * IW[1][a] - IW[0][a] * m21) / det;
+        }
+        const double qh = Fl[4] - (U0[0] * Fl[1] + U0[1] * Fl[2] + U0[2] * Fl[3]) + u2 * Fl[0]
+                        - U0[0] * (Wf[4] - (U0[0] * Wf[1] + U0[1] * Wf[2] + U0[2] * Wf[3]) + u2 * Wf[0]);
+        const double dqh = dFl[4] - (U0[0] * dFl[1] + U0[1] * dFl[2] + U0[2] * dFl[3]) + u2 * dFl[0]
+                         - U0[0] * (dWf[4] - (U0[0] * dWf[1] + U0[1] * dWf[2] + U0[2] * dWf[3]) + u2 * dWf[0]);
+        Fl[4] += (1.0 / p->prandtl - 1.0) * qh;
+        dFl[4] += (1.0 / p->prandtl - 1.0) * dqh;
     }
     /* rotate back to the global frame */
     F[0] = Fl[0]; dF[0] = dFl[0];
@@ -1278,34 +1401,61 @@ static void gauss_point_fallback(const orc_params *p, const double *ql_cell, con
     }
 }
 
-/* S * sum_G w_G (F, dF) of face f.  At a wall face the right side is the ghost:
- * the wall cell's reconstruction mirrored, i.e. the same value at the (in-wall)
- * Gauss point and the gradient reflected in the wall. */
+/* Right side of Gauss point g of face f: the right cell's reconstruction, or at a
+ * boundary face the ghost's.  At a transmissive wall the ghost is the wall cell's
+ * reconstruction mirrored (the same value at the in-wall point, the gradient
+ * reflected in the wall); at a no-slip wall the same with the momentum negated; at
+ * the far field the Riemann-invariant state of the left point value, no gradient.
+ * qr_cell receives the right cell's (or ghost's) cell average. */
+static void right_point(const orc_mesh *m, const orc_params *p, const double *Q, const orc_weno *W, int64_t f,
+                        int g, const double *vl, double gl[5][3], double *vr, double gr[5][3], double *qr_cell) {
+    const int64_t l = m->fcell[f][0], r = m->fcell[f][1];
+    if (r >= 0) {
+        double xr[3];
+        for (int a = 0; a < 3; ++a) xr[a] = m->fgp[f][g][a] - m->fshift[f][a];
+        weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
+        memcpy(qr_cell, Q + 5 * r, sizeof(double) * 5);
+        return;
+    }
+    const double *n = m->fnrm[f];
+    const int kind = m->fkind[f];
+    if (kind == ORC_BC_FAR) {
+        farfield_state(p, vl, m->fpn[f][g], vr);
+        for (int q = 0; q < 5; ++q) gr[q][0] = gr[q][1] = gr[q][2] = 0.0;
+        farfield_state(p, Q + 5 * l, n, qr_cell);
+        return;
+    }
+    const double sg = kind == ORC_BC_WALL ? -1.0 : 1.0;      /* momentum sign of the ghost */
+    for (int q = 0; q < 5; ++q) {
+        const double s_ = (q >= 1 && q <= 3) ? sg : 1.0;
+        const double gn = gl[q][0] * n[0] + gl[q][1] * n[1] + gl[q][2] * n[2];
+        vr[q] = s_ * vl[q];
+        for (int a = 0; a < 3; ++a) gr[q][a] = s_ * (gl[q][a] - 2.0 * gn * n[a]);
+        qr_cell[q] = s_ * Q[5 * l + q];
+    }
+}
+
+/* S * sum_G w_G (F, dF) of face f; with tets the three points share the face
+ * normal and weigh 1/3 each. */
 static int face_flux(const orc_mesh *m, const orc_params *p, const double *Q, const orc_weno *W, int64_t f,
                      double dt, double out[10]) {
-    const int64_t l = m->fcell[f][0], r = m->fcell[f][1];
-    const double *n = m->fnrm[f];
+    const int64_t l = m->fcell[f][0];
     double Ff[5] = {0}, dFf[5] = {0};
     int rc = ORC_OK;
-    for (int g = 0; g < 3; ++g) {
-        double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5];
-        for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
-        weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
-        if (r >= 0) {
-            weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
-        } else {
-            for (int q = 0; q < 5; ++q) {
-                const double gn = gl[q][0] * n[0] + gl[q][1] * n[1] + gl[q][2] * n[2];
-                vr[q] = vl[q];
-                for (int a = 0; a < 3; ++a) gr[q][a] = gl[q][a] - 2.0 * gn * n[a];
-            }
-        }
-        gauss_point_fallback(p, Q + 5 * l, Q + 5 * (r >= 0 ? r : l), vl, gl, vr, gr);
-        int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], n, dt, F, dF);
+    for (int g = 0; g < m->ngp; ++g) {
+        double vl[5], vr[5], gl[5][3], gr[5][3], F[5], dF[5], qr_cell[5];
+        weno_eval(m, p, Q, l, &W[l], m->fgp[f][g], vl, gl);
+        right_point(m, p, Q, W, f, g, vl, gl, vr, gr, qr_cell);
+        gauss_point_fallback(p, Q + 5 * l, qr_cell, vl, gl, vr, gr);
+        int r_ = orc_gks_flux(p, vl, &gl[0][0], vr, &gr[0][0], m->ngp == 3 ? m->fnrm[f] : m->fpn[f][g], dt, F, dF);
         if (r_ > rc) rc = r_;
-        for (int q = 0; q < 5; ++q) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
+        for (int q = 0; q < 5; ++q) {
+            if (m->ngp == 3) { Ff[q] += F[q] / 3.0; dFf[q] += dF[q] / 3.0; }
+            else { Ff[q] += m->fpw[f][g] * F[q]; dFf[q] += m->fpw[f][g] * dF[q]; }
+        }
     }
-    for (int q = 0; q < 5; ++q) { out[q] = Ff[q] * m->farea[f]; out[5 + q] = dFf[q] * m->farea[f]; }
+    const double S = m->ngp == 3 ? m->farea[f] : 1.0;
+    for (int q = 0; q < 5; ++q) { out[q] = Ff[q] * S; out[5 + q] = dFf[q] * S; }
     return rc;
 }
 
@@ -1329,7 +1479,7 @@ int orc_rhs(const orc_mesh *m, const orc_params *p, const double *Q, double dt, 
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m->nc; ++i) {
             double s[10] = {0};
-            for (int p_ = 0; p_ < 4; ++p_) {
+            for (int p_ = 0; p_ < m->nfc; ++p_) {
                 int64_t f = m->cface[i][p_];
                 double sign = m->fcell[f][0] == i ? -1.0 : 1.0;    /* the normal points out of the left cell */
                 for (int q = 0; q < 10; ++q) s[q] += sign * FF[f][q];
@@ -1424,17 +1574,27 @@ void orc_collision(const orc_params *p, const double *ql, const double *qr, doub
     for (int a = 0; a < 5; ++a) q0[a] = sl.rho * expect(&Mlp, &PSI[a]) + sr.rho * expect(&Mrn, &PSI[a]);
 }
 
-/* WENO of one cell: P0 coefficients a[5][9], P_m coefficients b[4][5][3], beta[5][5], wbar[5][5]. */
+/* WENO of one cell: P0 coefficients a[5][9], P_m coefficients b[M][5][3], beta[5][M+1],
+ * wbar[5][M+1] (M = 4 for tets, 8 for hexes). */
 int orc_weno_cell(const orc_mesh *m, const orc_params *p, const double *Q, int64_t i,
                   double *a, double *b, double *beta, double *wbar) {
     orc_weno w;
     int rc = weno_cell(m, p, Q, i, &w);
     if (rc) return rc;
+    const int M = m->msub;
     if (a) memcpy(a, w.a, sizeof(w.a));
-    if (b) memcpy(b, w.b, sizeof(w.b));
-    if (beta) memcpy(beta, w.beta, sizeof(w.beta));
-    if (wbar) memcpy(wbar, w.wbar, sizeof(w.wbar));
+    if (b) memcpy(b, w.b, sizeof(double) * 15 * M);
+    for (int q = 0; q < 5; ++q)
+        for (int s = 0; s <= M; ++s) {
+            if (beta) beta[q * (M + 1) + s] = w.beta[q][s];
+            if (wbar) wbar[q * (M + 1) + s] = w.wbar[q][s];
+        }
     return ORC_OK;
+}
+
+/* The state a boundary ghost of the given kind holds next to state q (outward normal n). */
+void orc_ghost_state(const orc_params *p, int kind, const double *q, const double *n, double *out) {
+    ghost_state(p, kind, q, n, out);
 }
 
 /* Reconstructed value and gradient of cell i at point x (cell i's frame). */
@@ -1473,21 +1633,11 @@ int orc_fallback_census(const orc_mesh *m, const orc_params *p, const double *Q,
     for (int64_t i = 0; i < m->nc && !rc; ++i) rc = weno_cell(m, p, Q, i, &W[i]);
     int64_t all = 0, one = 0, one_grad = 0;
     for (int64_t f = 0; f < m->nf && !rc; ++f) {
-        const int64_t l = m->fcell[f][0], r = m->fcell[f][1];
-        const double *n = m->fnrm[f];
-        for (int g = 0; g < 3; ++g) {
-            double xl[3], xr[3], vl[5], vr[5], gl[5][3], gr[5][3];
-            for (int a = 0; a < 3; ++a) { xl[a] = m->fgp[f][g][a]; xr[a] = xl[a] - m->fshift[f][a]; }
-            weno_eval(m, p, Q, l, &W[l], xl, vl, gl);
-            if (r >= 0) {
-                weno_eval(m, p, Q, r, &W[r], xr, vr, gr);
-            } else {
-                for (int q = 0; q < 5; ++q) {
-                    const double gn = gl[q][0] * n[0] + gl[q][1] * n[1] + gl[q][2] * n[2];
-                    vr[q] = vl[q];
-                    for (int a = 0; a < 3; ++a) gr[q][a] = gl[q][a] - 2.0 * gn * n[a];
-                }
-            }
+        const int64_t l = m->fcell[f][0];
+        for (int g = 0; g < m->ngp; ++g) {
+            double vl[5], vr[5], gl[5][3], gr[5][3], qr_cell[5];
+            weno_eval(m, p, Q, l, &W[l], m->fgp[f][g], vl, gl);
+            right_point(m, p, Q, W, f, g, vl, gl, vr, gr, qr_cell);
             const int okl = physical_point(p, vl), okr = physical_point(p, vr);
             if (okl && okr) continue;
             ++all;
@@ -1510,7 +1660,7 @@ int orc_fallback_census(const orc_mesh *m, const orc_params *p, const double *Q,
 
 /* mean over cell i of the scaled monomials, as used by the least-squares rows */
 void orc_cell_monomial_means(const orc_mesh *m, int64_t i, const double *target_c, double target_h, double *out) {
-    tet_monomial_means(m->vert[i], target_c, target_h, out);
+    cell_monomial_means(m->npc, m->vert[i], target_c, target_h, out);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1522,7 +1672,10 @@ static void mark_stencils(const orc_mesh *m, const unsigned char *in, unsigned c
     for (int64_t i = 0; i < m->nc; ++i) {
         if (!in[i]) continue;
         out[i] = 1;
-        for (int k = 0; k < m->nsten[i]; ++k) out[m->sten[i][k]] = 1;
+        for (int k = 0; k < m->nsten[i]; ++k) {
+            const int64_t id = m->sten[i][k];
+            out[id < m->nc ? id : m->gcell[id - m->nc]] = 1;     /* a ghost reads its cell */
+        }
     }
 }
 
@@ -1561,7 +1714,7 @@ static int rhs_subset(const orc_mesh *m, const orc_params *p, const double *Q, d
         for (int64_t i = 0; i < m->nc; ++i) {
             if (!need[i]) continue;
             double s[10] = {0};
-            for (int p_ = 0; p_ < 4; ++p_) {
+            for (int p_ = 0; p_ < m->nfc; ++p_) {
                 int64_t f = m->cface[i][p_];
                 double sign = m->fcell[f][0] == i ? -1.0 : 1.0;
                 for (int q = 0; q < 10; ++q) s[q] += sign * FF[f][q];

@@ -37,13 +37,24 @@ def build() -> str:
 class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("tau_mode", C.c_int),
                 ("tau_eps", C.c_double), ("tau_C", C.c_double), ("weno_eps", C.c_double),
-                ("gamma_lin", C.c_double)]
+                ("gamma_lin", C.c_double), ("mu_ref", C.c_double), ("T_ref", C.c_double),
+                ("mu_exp", C.c_double), ("prandtl", C.c_double), ("farfield", C.c_double * 5)]
+
+
+# boundary kinds of listed boundary faces
+BC_WALL = 1     # no-slip adiabatic wall
+BC_FAR = 2      # far field (Riemann invariants)
 
 
 def default_params(**kw) -> Params:
-    p = Params(gamma=1.4, cfl=0.3, tau_mode=0, tau_eps=0.05, tau_C=1.0, weno_eps=1e-8, gamma_lin=0.025)
+    p = Params(gamma=1.4, cfl=0.3, tau_mode=0, tau_eps=0.05, tau_C=1.0, weno_eps=1e-8, gamma_lin=0.025,
+               mu_ref=0.0, T_ref=1.0, mu_exp=0.7, prandtl=1.0)
+    p.farfield[:] = (1.0, 0.0, 0.0, 0.0, 1.0)
     for k, v in kw.items():
-        setattr(p, k, v)
+        if k == "farfield":
+            p.farfield[:] = tuple(float(x) for x in v)
+        else:
+            setattr(p, k, v)
     return p
 
 
@@ -54,6 +65,12 @@ def _configure(L):
     """Declares the argument and return types of the oracle's C entry points."""
     L.orc_mesh_new.restype = C.c_void_p
     L.orc_mesh_new.argtypes = [C.c_int64, _dp, C.c_int64, _i64p, _dp, C.c_char_p, C.c_int]
+    L.orc_mesh_new2.restype = C.c_void_p
+    L.orc_mesh_new2.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _i64p, _dp, C.c_int64, _i64p, _ip,
+                                C.c_char_p, C.c_int]
+    L.orc_mesh_info.argtypes = [C.c_void_p, _i64p]
+    L.orc_mesh_face_points.argtypes = [C.c_void_p, _dp, _dp, _ip]
+    L.orc_ghost_state.argtypes = [C.POINTER(Params), C.c_int, _dp, _dp, _dp]
     L.orc_mesh_free.argtypes = [C.c_void_p]
     L.orc_mesh_nfaces.restype = C.c_int64
     L.orc_mesh_nfaces.argtypes = [C.c_void_p]
@@ -126,18 +143,32 @@ class OracleError(RuntimeError):
 class Mesh:
     """Oracle-side mesh: connectivity, geometry and stencils built from nodes + cells."""
 
-    def __init__(self, nodes, cell_nodes, period=(0.0, 0.0, 0.0)):
+    def __init__(self, nodes, cell_nodes, period=(0.0, 0.0, 0.0), bfaces=None, bkinds=None):
+        """cell_nodes [nc][4] (tetrahedra) or [nc][8] (hexahedra); bfaces [nb][3 or 4]
+        node ids of listed boundary faces with bkinds [nb] (BC_WALL / BC_FAR)."""
         L = lib()
         self.nodes = _f64(nodes)
         self.cell_nodes = np.ascontiguousarray(cell_nodes, dtype=np.int64)
         self.period = _f64(period)
+        npc = self.cell_nodes.shape[1]
         err = C.create_string_buffer(256)
-        self._h = L.orc_mesh_new(self.nodes.shape[0], _d(self.nodes), self.cell_nodes.shape[0],
-                                 self.cell_nodes.ctypes.data_as(_i64p), _d(self.period), err, 256)
+        if bfaces is None:
+            bf = np.zeros((0, 4), dtype=np.int64)
+            bk = np.zeros(0, dtype=np.int32)
+        else:
+            bf = np.ascontiguousarray(bfaces, dtype=np.int64)
+            bk = np.ascontiguousarray(bkinds, dtype=np.int32)
+        self._bf, self._bk = bf, bk
+        self._h = L.orc_mesh_new2(self.nodes.shape[0], _d(self.nodes), self.cell_nodes.shape[0], npc,
+                                  self.cell_nodes.ctypes.data_as(_i64p), _d(self.period), bf.shape[0],
+                                  bf.ctypes.data_as(_i64p), bk.ctypes.data_as(_ip), err, 256)
         if not self._h:
             raise OracleError(err.value.decode())
         self.nc = self.cell_nodes.shape[0]
         self.nf = int(L.orc_mesh_nfaces(self._h))
+        info = np.zeros(6, dtype=np.int64)
+        L.orc_mesh_info(self._h, info.ctypes.data_as(_i64p))
+        self.npc, self.nfc, self.ngp, self.msub, self.n_ghosts, self.max_stencil = (int(x) for x in info)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -147,7 +178,8 @@ class Mesh:
 
     @classmethod
     def from_workload(cls, mesh):
-        return cls(mesh.nodes, mesh.cell_nodes, mesh.period)
+        return cls(mesh.nodes, mesh.cell_nodes, mesh.period, getattr(mesh, "bfaces", None),
+                   getattr(mesh, "bkinds", None))
 
     def cells(self):
         vol, cen, hdt = np.empty(self.nc), np.empty((self.nc, 3)), np.empty(self.nc)
@@ -157,23 +189,28 @@ class Mesh:
     def faces(self):
         lr = np.empty((self.nf, 2), dtype=np.int64)
         nrm, area = np.empty((self.nf, 3)), np.empty(self.nf)
-        shift, gp = np.empty((self.nf, 3)), np.empty((self.nf, 3, 3))
+        shift, gp = np.empty((self.nf, 3)), np.empty((self.nf, self.ngp, 3))
         lib().orc_mesh_faces(self._h, lr.ctypes.data_as(_i64p), _d(nrm), _d(area), _d(shift), _d(gp))
-        return {"lr": lr, "normal": nrm, "area": area, "shift": shift, "gauss": gp}
+        pn, pw = np.empty((self.nf, self.ngp, 3)), np.empty((self.nf, self.ngp))
+        kind = np.empty(self.nf, dtype=np.int32)
+        lib().orc_mesh_face_points(self._h, _d(pn), _d(pw), kind.ctypes.data_as(_ip))
+        return {"lr": lr, "normal": nrm, "area": area, "shift": shift, "gauss": gp,
+                "point_normal": pn, "point_weight": pw, "kind": kind}
 
     def neighbors(self):
-        nb = np.empty((self.nc, 4), dtype=np.int64)
+        nb = np.empty((self.nc, self.nfc), dtype=np.int64)
         lib().orc_mesh_neighbors(self._h, nb.ctypes.data_as(_i64p))
         return nb
 
     def stencil(self, i):
-        mem = np.empty(32, dtype=np.int64)
-        sh = np.empty((32, 3))
-        ns = np.empty(4, dtype=np.int32)
-        sub = np.empty((4, 8), dtype=np.int64)
+        """(members, offsets, sub-stencils); member ids >= nc are boundary ghosts."""
+        mem = np.empty(40, dtype=np.int64)
+        sh = np.empty((40, 3))
+        ns = np.empty(8, dtype=np.int32)
+        sub = np.empty((8, 8), dtype=np.int64)
         k = lib().orc_mesh_stencil(self._h, int(i), mem.ctypes.data_as(_i64p), _d(sh),
                                    ns.ctypes.data_as(_ip), sub.ctypes.data_as(_i64p))
-        return mem[:k].copy(), sh[:k].copy(), [sub[s, :ns[s]].copy() for s in range(4)]
+        return mem[:k].copy(), sh[:k].copy(), [sub[s, :ns[s]].copy() for s in range(self.msub)]
 
     def monomial_means(self, i, center, h):
         out = np.empty(9)
@@ -242,8 +279,9 @@ class Mesh:
     def weno_cell(self, q, i, params=None):
         p = params or default_params()
         q = _f64(q, (self.nc, 5))
-        a, b = np.empty((5, 9)), np.empty((4, 5, 3))
-        beta, wbar = np.empty((5, 5)), np.empty((5, 5))
+        M = self.msub
+        a, b = np.empty((5, 9)), np.empty((M, 5, 3))
+        beta, wbar = np.empty((5, M + 1)), np.empty((5, M + 1))
         rc = lib().orc_weno_cell(self._h, C.byref(p), _d(q), int(i), _d(a), _d(b), _d(beta), _d(wbar))
         if rc:
             raise OracleError(f"orc_weno_cell failed ({rc})")
@@ -287,6 +325,15 @@ def slope(U, V, W, lam, K, b):
     if rc:
         raise OracleError("singular moment matrix")
     return a
+
+
+def ghost_state(kind, q, n, params=None):
+    """The state a boundary ghost of `kind` holds next to state q (outward normal n)."""
+    p = params or default_params()
+    q, n = _f64(q), _f64(n)
+    out = np.empty(5)
+    lib().orc_ghost_state(C.byref(p), int(kind), _d(q), _d(n), _d(out))
+    return out
 
 
 def collision(ql, qr, params=None):

@@ -4,8 +4,10 @@ This module only *generates inputs*; it holds none of the scheme's arithmetic.
 Both the GPU path (tests, bench, serving) and the CPU oracle's tests draw their
 inputs from here.
 
-* Mesh: the periodic accuracy-test box of Sec. 5.1, "every cube divided into six
-  tetrahedra".  The split is the Kuhn split along the main diagonal: for cube
+* Meshes: the periodic accuracy-test box of Sec. 5.1, "every cube divided into six
+  tetrahedra" (below), the same box of jittered hexahedra, and the cubed-sphere
+  O-grid of hexahedra around a sphere (Sec. 5.2: six patches of N x N cells by the
+  radial layers).  The split is the Kuhn split along the main diagonal: for cube
   (i, j, k) and each permutation sigma of the axes (lexicographic order), the
   tetrahedron is the lattice path v0 -> v0+e_s1 -> v0+e_s1+e_s2 -> v0+(1,1,1).
   Cell id = 6*((i*N + j)*N + k) + sigma.  Interior vertices are jittered by
@@ -55,13 +57,17 @@ def uniform01(seed: int, count: int, start: int = 0) -> np.ndarray:
 
 @dataclass
 class TetMesh:
-    """A tetrahedral mesh in the form the library and the oracle both take.
+    """A mesh in the form the library and the oracle both take (tetrahedra or
+    hexahedra; the name is historical).
 
     nodes       [n_nodes, 3] float64 coordinates
-    cell_nodes  [n_cells, 4] int64 node ids (0-based)
+    cell_nodes  [n_cells, 4] (tetrahedra) or [n_cells, 8] (hexahedra: nodes 0-3
+                around one face, node k+4 above node k) int64 node ids (0-based)
     period      [3] float64; period[a] > 0 identifies x_a and x_a + period[a]
-    cell_vertices [n_cells, 4, 3] unwrapped vertex coordinates (generator-side
+    cell_vertices [n_cells, 4 or 8, 3] unwrapped vertex coordinates (generator-side
                 only, used to integrate initial data)
+    bfaces, bkinds  listed boundary faces ([nb, 4] node ids) and their kinds
+                (BC_WALL, BC_FAR), or None
     """
     nodes: np.ndarray
     cell_nodes: np.ndarray
@@ -70,6 +76,8 @@ class TetMesh:
     n: int = 0
     box: float = 2.0
     meta: dict = field(default_factory=dict)
+    bfaces: np.ndarray | None = None
+    bkinds: np.ndarray | None = None
 
     @property
     def n_cells(self) -> int:
@@ -133,6 +141,173 @@ def kuhn_box(n, box=2.0, jitter: float = 0.1, seed: int = SEED_ADVECTION,
                    n=int(nv[0]) if cubic else 0, box=float(bv[0]) if cubic else 0.0,
                    meta={"seed": seed, "jitter": jitter, "periodic": periodic, "n": tuple(int(x) for x in nv),
                          "box": tuple(float(x) for x in bv)})
+
+
+# boundary kinds of listed boundary faces
+BC_WALL = 1     # no-slip adiabatic wall
+BC_FAR = 2      # far field (Riemann invariants)
+
+# reference coordinates of the hexahedron's nodes on [0, 1]^3
+HEX_REF = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                    [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], dtype=np.float64)
+
+
+def hex_box(n, box=2.0, jitter: float = 0.1, seed: int = SEED_ADVECTION + 0x4E58,
+            periodic=(True, True, True)) -> TetMesh:
+    """nx ny nz hexahedra (the cubes themselves) in [0, Lx] x [0, Ly] x [0, Lz],
+    interior nodes jittered by U(-jitter h_a, jitter h_a) per component (so the
+    faces are bilinear, not planar).  Cell id = (i*ny + j)*nz + k."""
+    nv = np.array([n, n, n] if np.isscalar(n) else list(n), dtype=np.int64)
+    bv = np.array([box, box, box] if np.isscalar(box) else list(box), dtype=np.float64)
+    if np.any(nv < 5):
+        raise ValueError("hex_box needs n >= 5 per axis (two-layer stencils must not wrap onto themselves)")
+    periodic = tuple(bool(p) for p in periodic)
+    h = bv / nv
+    dims = np.array([nv[a] if periodic[a] else nv[a] + 1 for a in range(3)], dtype=np.int64)
+    ix, iy, iz = np.meshgrid(np.arange(dims[0]), np.arange(dims[1]), np.arange(dims[2]), indexing="ij")
+    idx = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+    nodes = idx.astype(np.float64) * h[None, :]
+    interior = np.all((idx % nv[None, :]) != 0, axis=1)
+    if jitter > 0.0:
+        u = uniform01(seed, 3 * idx.shape[0]).reshape(-1, 3)
+        nodes = nodes + np.where(interior[:, None], (2.0 * u - 1.0) * jitter * h[None, :], 0.0)
+    ci, cj, ck = np.meshgrid(np.arange(nv[0]), np.arange(nv[1]), np.arange(nv[2]), indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)
+    period = np.array([bv[a] if periodic[a] else 0.0 for a in range(3)])
+    cell_nodes = np.empty((base.shape[0], 8), dtype=np.int64)
+    cell_vertices = np.empty((base.shape[0], 8, 3))
+    for v in range(8):
+        lat = base + HEX_REF[v].astype(np.int64)[None, :]
+        wrap = np.zeros_like(lat)
+        for a in range(3):
+            if periodic[a]:
+                wrap[:, a] = lat[:, a] // nv[a]
+        li = lat - wrap * nv[None, :]
+        nid = (li[:, 0] * dims[1] + li[:, 1]) * dims[2] + li[:, 2]
+        cell_nodes[:, v] = nid
+        cell_vertices[:, v, :] = nodes[nid] + wrap * period
+    cubic = bool(np.all(nv == nv[0]) and np.all(bv == bv[0]))
+    return TetMesh(nodes=nodes, cell_nodes=cell_nodes, period=period, cell_vertices=cell_vertices,
+                   n=int(nv[0]) if cubic else 0, box=float(bv[0]) if cubic else 0.0,
+                   meta={"seed": seed, "jitter": jitter, "periodic": periodic, "n": tuple(int(x) for x in nv),
+                         "box": tuple(float(x) for x in bv), "cell": "hex"})
+
+
+def cubed_sphere(n: int, layers: int, r0: float = 0.5, r1: float = 20.0) -> TetMesh:
+    """The O-grid of hexahedra around a sphere (Sec. 5.2): six patches, each the
+    equiangular gnomonic projection of an n x n grid on a cube face, extruded over
+    `layers` radial layers whose radii grow geometrically from r0 (the sphere) to r1
+    (the far field).  Nodes 0-3 of a cell lie on its inner sphere, 4-7 on its outer,
+    so faces 1 and 6 (0-based 0 and 5) are the radial pair.  The inner faces of the
+    first layer are no-slip walls and the outer faces of the last layer far-field
+    faces (bfaces / bkinds).  Cell id = ((patch*n + i)*n + j)*layers + k."""
+    if n < 2 or layers < 4:
+        raise ValueError("cubed_sphere needs n >= 2 and layers >= 4")
+    t = np.tan(np.linspace(-math.pi / 4, math.pi / 4, n + 1))
+    radii = r0 * (r1 / r0) ** (np.arange(layers + 1) / layers)
+    # patch p: axis p // 2, side +1 / -1; (a, b) run over the two other axes in a
+    # right-handed order so that every patch's cells have the same orientation
+    dirs = []
+    for p in range(6):
+        ax, sg = p // 2, (1.0 if p % 2 == 0 else -1.0)
+        o1, o2 = (ax + 1) % 3, (ax + 2) % 3
+        A, B = np.meshgrid(t, t, indexing="ij")
+        d = np.empty((n + 1, n + 1, 3))
+        d[..., ax] = sg
+        d[..., o1] = A if sg > 0 else B
+        d[..., o2] = B if sg > 0 else A
+        dirs.append(d / np.linalg.norm(d, axis=-1, keepdims=True))
+    dirs = np.stack(dirs)                                              # [6, n+1, n+1, 3]
+    # shared patch edges give the same direction: merge them by rounded key
+    key = np.round(dirs.reshape(-1, 3) * 2 ** 30).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inv = inv.reshape(6, n + 1, n + 1)
+    udir = dirs.reshape(-1, 3)[first]
+    nd = udir.shape[0]
+    nodes = (radii[None, :, None] * udir[:, None, :]).reshape(-1, 3)   # node id = dir * (layers+1) + k
+    P, I, J, K = np.meshgrid(np.arange(6), np.arange(n), np.arange(n), np.arange(layers), indexing="ij")
+    P, I, J, K = P.ravel(), I.ravel(), J.ravel(), K.ravel()
+    corner = [(0, 0), (1, 0), (1, 1), (0, 1)]
+    cell_nodes = np.empty((P.shape[0], 8), dtype=np.int64)
+    for v, (di, dj) in enumerate(corner):
+        dn = inv[P, I + di, J + dj]
+        cell_nodes[:, v] = dn * (layers + 1) + K
+        cell_nodes[:, v + 4] = dn * (layers + 1) + K + 1
+    cell_vertices = nodes[cell_nodes]
+    inner = cell_nodes[K == 0][:, :4]
+    outer = cell_nodes[K == layers - 1][:, 4:]
+    bfaces = np.concatenate([inner, outer])
+    bkinds = np.concatenate([np.full(inner.shape[0], BC_WALL), np.full(outer.shape[0], BC_FAR)]).astype(np.int32)
+    return TetMesh(nodes=nodes, cell_nodes=cell_nodes, period=np.zeros(3), cell_vertices=cell_vertices,
+                   n=n, box=0.0, bfaces=bfaces, bkinds=bkinds,
+                   meta={"cell": "hex", "patches": 6, "n": n, "layers": layers, "r0": r0, "r1": r1,
+                         "unique_directions": int(nd)})
+
+
+def hex_cell_average(cell_vertices: np.ndarray, fun, npts: int, chunk: int = 32768) -> np.ndarray:
+    """Cell averages of fun(x, y, z) over trilinear hexahedra: the npts^3
+    Gauss-Legendre product rule over the map, weighted by |det J|."""
+    g, w = np.polynomial.legendre.leggauss(npts)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    R = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)     # [P, 3]
+    W = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel()
+    # shape functions and their derivatives at the points
+    f = np.where(HEX_REF[None, :, :] > 0, R[:, None, :], 1.0 - R[:, None, :])       # [P, 8, 3]
+    df = np.where(HEX_REF[None, :, :] > 0, 1.0, -1.0) * np.ones_like(f)
+    N = f.prod(axis=2)                                                             # [P, 8]
+    dN = np.stack([df[..., 0] * f[..., 1] * f[..., 2], f[..., 0] * df[..., 1] * f[..., 2],
+                   f[..., 0] * f[..., 1] * df[..., 2]], axis=2)                     # [P, 8, 3]
+    out = np.empty(cell_vertices.shape[0])
+    for s in range(0, cell_vertices.shape[0], chunk):
+        v = cell_vertices[s:s + chunk]                                             # [c, 8, 3]
+        x = np.einsum("pk,cka->cpa", N, v)
+        J = np.einsum("pkd,cka->cpad", dN, v)
+        det = np.abs(np.linalg.det(J))
+        wd = det * W[None, :]
+        out[s:s + chunk] = np.sum(fun(x[..., 0], x[..., 1], x[..., 2]) * wd, axis=1) / np.sum(wd, axis=1)
+    return out
+
+
+def hex_volumes(cell_vertices: np.ndarray) -> np.ndarray:
+    """Volumes of trilinear hexahedra (2x2x2 Gauss-Legendre, exact for the Jacobian's degree)."""
+    g, w = np.polynomial.legendre.leggauss(2)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    R = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    W = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel()
+    f = np.where(HEX_REF[None, :, :] > 0, R[:, None, :], 1.0 - R[:, None, :])
+    df = np.where(HEX_REF[None, :, :] > 0, 1.0, -1.0) * np.ones_like(f)
+    dN = np.stack([df[..., 0] * f[..., 1] * f[..., 2], f[..., 0] * df[..., 1] * f[..., 2],
+                   f[..., 0] * f[..., 1] * df[..., 2]], axis=2)
+    J = np.einsum("pkd,cka->cpad", dN, cell_vertices)
+    return np.abs(np.linalg.det(J)) @ W
+
+
+def cell_volumes(mesh: TetMesh) -> np.ndarray:
+    return hex_volumes(mesh.cell_vertices) if mesh.cell_nodes.shape[1] == 8 else tet_volumes(mesh.cell_vertices)
+
+
+@dataclass
+class SphereCase:
+    """Viscous flow past the unit-diameter sphere (Sec. 5.2): free stream
+    (rho, U, V, W, p) = (1, Ma, 0, 0, 1/gamma), mu = mu_inf (T/T_inf)^0.7 with
+    mu_inf = rho U D / Re, T = p/rho.  The initial state is the free stream."""
+    mach: float = 0.2535
+    reynolds: float = 118.0
+    prandtl: float = 0.72
+    gamma: float = 1.4
+
+    def freestream(self):
+        return (1.0, self.mach, 0.0, 0.0, 1.0 / self.gamma)
+
+    def mu_inf(self) -> float:
+        return 1.0 * self.mach * 1.0 / self.reynolds
+
+    def t_inf(self) -> float:
+        return (1.0 / self.gamma) / 1.0
+
+    def conservative(self, mesh: TetMesh) -> np.ndarray:
+        rho, u, v, w, p = self.freestream()
+        return uniform_state(mesh.n_cells, rho=rho, vel=(u, v, w), p=p, gamma=self.gamma)
 
 
 def tet_rule(npts: int):
@@ -208,6 +383,9 @@ class AdvectionCase:
     def density_average(self, mesh: TetMesh, t: float = 0.0, npts: int | None = None) -> np.ndarray:
         if npts is None:
             npts = default_npts(mesh.cell_vertices, math.pi * sum(abs(v) for v in self.k))
+        if mesh.cell_nodes.shape[1] == 8:
+            # the trilinear Jacobian adds degree 2 per direction to the integrand
+            return hex_cell_average(mesh.cell_vertices, self.density_fn(t), npts + 2)
         return cell_average(mesh.cell_vertices, self.density_fn(t), npts)
 
     def conservative(self, mesh: TetMesh, t: float = 0.0, npts: int | None = None) -> np.ndarray:
