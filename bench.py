@@ -31,6 +31,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -123,6 +125,65 @@ def run_gpu(mesh, q0, precision, steps, warmup):
     q, t = s.get_state()
     s.close()
     return {"seconds": el, "setup_s": t_setup, "prof": prof, "info": info, "footprint": foot, "t": t, "q": q}
+
+
+def sphere_bench(n: int, layers: int, run_steps: int, steps: int, warmup: int) -> dict:
+    """The viscous sphere (Sec. 5.2) on the cubed-sphere O-grid of hexahedra, FP64 and
+    FP32-mixed: `steps` timed steps after `warmup`, then the rest of a `run_steps`
+    run from the free stream, and the FP32-mixed state's relative L1 against FP64's
+    at its end."""
+    from paper_2407_00656_amd import hgks
+    from paper_2407_00656_amd import workloads as W
+    case = W.SphereCase()
+    mesh = W.cubed_sphere(n, layers)
+    q0 = case.conservative(mesh)
+    kw = dict(tau_mode=2, mu_ref=case.mu_inf(), T_ref=case.t_inf(), mu_exp=0.7, prandtl=case.prandtl,
+              farfield=case.freestream())
+    nc = mesh.n_cells
+    out = {"workload": f"viscous sphere, cubed-sphere O-grid 6*{n}*{n}*{layers} hexahedra, r 0.5 to 20, "
+                       f"Ma {case.mach}, Re {case.reynolds}, Pr {case.prandtl}, mu ~ T^0.7, no-slip wall, "
+                       f"far field, CFL 0.3", "cells": nc}
+    states = {}
+    for name, prec in (("fp64", hgks.FP64), ("fp32_mixed", hgks.FP32_MIXED)):
+        print(f"bench: sphere {name}", file=sys.stderr, flush=True)
+        s = hgks.Solver(hgks.params(precision=prec, **kw))
+        t0 = time.perf_counter()
+        s.upload(mesh)
+        setup = time.perf_counter() - t0
+        s.init_state(q0)
+        t_run = time.perf_counter()
+        s.step(warmup)
+        s.sync()
+        s.profile_enable(True)
+        s.profile_reset()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        el = time.perf_counter() - t0
+        prof = {k: s.profile_read(k) for k in ("dt", "weno", "flux", "update")}
+        s.profile_enable(False)
+        rest = max(0, run_steps - warmup - steps)
+        s.step(rest)
+        s.sync()
+        run_s = time.perf_counter() - t_run
+        q, t = s.get_state()
+        out["faces"] = s.info()["n_faces"]
+        out[name] = {"value": round(nc * steps / el, 1), "ms_per_step": round(1e3 * el / steps, 4),
+                     "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items()},
+                     "run_steps": warmup + steps + rest, "run_s": round(run_s, 2), "t": t,
+                     "setup_s": round(setup, 2), "footprint_GB": round(s.footprint() / 1e9, 3)}
+        s.close()
+        states[name] = q
+    out["fp32_mixed"]["speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["fp32_mixed"]["ms_per_step"], 3)
+    vol = W.hex_volumes(mesh.cell_vertices)
+    a, b = states["fp32_mixed"], states["fp64"]
+    rho = b[:, 0]
+    p = (case.gamma - 1) * (b[:, 4] - 0.5 * np.sum(b[:, 1:4] ** 2, axis=1) / rho)
+    ms = np.maximum(np.linalg.norm(b[:, 1:4], axis=1), rho * np.sqrt(case.gamma * np.abs(p) / rho))
+    den = np.array([np.sum(rho * vol), *(3 * [np.sum(ms * vol)]), np.sum(np.abs(b[:, 4]) * vol)])
+    out["rel_L1_fp32_mixed_vs_fp64"] = (np.sum(np.abs(a - b) * vol[:, None], axis=0) / den).tolist()
+    out["max_mach"] = float(np.max(np.linalg.norm(b[:, 1:4], axis=1) / rho / np.sqrt(case.gamma * p / rho)))
+    return out
 
 
 def cpu_oracle_step(mesh, q0):
@@ -267,6 +328,9 @@ def main():
                     help="requests of the closed-loop pass that measures the loop's capacity")
     ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--sphere", type=int, default=48, help="cells across a patch of the sphere O-grid (0 skips it)")
+    ap.add_argument("--sphere-layers", type=int, default=64)
+    ap.add_argument("--sphere-run", type=int, default=2000, help="steps of the sphere run (FP64 vs FP32-mixed)")
     ap.add_argument("--cpu-single", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (x5) to calibrate HBM byte counters")
@@ -308,6 +372,10 @@ def main():
         r32 = run_gpu(mesh, q0, hgks.FP32_MIXED, args.steps, args.warmup)
         print("bench: FP32", file=sys.stderr, flush=True)
         r32f = run_gpu(mesh, q0, hgks.FP32, args.steps, args.warmup)
+
+    sph = None
+    if args.sphere > 0:
+        sph = sphere_bench(args.sphere, args.sphere_layers, args.sphere_run, args.steps, args.warmup)
 
     # dominant kernel of the FP64 step and its roofline position
     prof = r64["prof"]
@@ -379,6 +447,7 @@ def main():
             "speedup_vs_fp64": round(r64["seconds"] / r32f["seconds"], 3),
             "weno": reduced_weno(r32f, nc, nf, True)},
         "serve": srv,
+        "sphere": sph,
         "kernels": kernels,
         "setup_s": round(r64["setup_s"], 2),
         "footprint_GB": round(r64["footprint"] / 1e9, 3),

@@ -1,7 +1,7 @@
 /*
  * hgks.h -- C ABI of the MI355X (gfx950) HGKS library: the explicit
- * high-order gas-kinetic step on tetrahedral meshes of arXiv 2407.00656
- * (Wang, Cao, Pan), run in hand-written HIP kernels on one GPU.
+ * high-order gas-kinetic step on tetrahedral and hexahedral meshes of arXiv
+ * 2407.00656 (Wang, Cao, Pan), run in hand-written HIP kernels on one GPU.
  *
  * One step (Sec. 2.2, two-stage fourth-order "S2O4" update) is
  *   Q*      = Q^n + dt/2 L(Q^n) + dt^2/8 dL/dt(Q^n)
@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HGKS_ABI_VERSION 1
+#define HGKS_ABI_VERSION 2
 
 typedef enum {
     HGKS_OK = 0,
@@ -81,22 +81,41 @@ typedef enum {
                                  (non-atomic read-modify-write, class order fixed) */
 } hgks_accumulation;
 
+/* Kinds of listed boundary faces (Sec. 5.2), hexahedral meshes. */
+typedef enum {
+    HGKS_BC_WALL = 1,         /* no-slip adiabatic wall: the ghost holds (rho, -rho U, rho E) */
+    HGKS_BC_FAR = 2           /* far field: the ghost holds the Riemann-invariant state of the
+                                 cell and the free stream (hgks_params.farfield) */
+} hgks_bc_kind;
+
 typedef struct {
     double gamma;             /* specific-heat ratio; internal DOF K = (5 - 3 gamma)/(gamma - 1) (Sec. 2.1) */
     double cfl;               /* dt = cfl * min_i h_i / (|U_i| + c_i), h_i = 6|Omega_i| / sum_p S_ip */
     int tau_mode;             /* 0: tau = 0 (smooth flow, f = g(1 + A t), Sec. 5.1);
-                                 1: tau = tau_eps*dt + tau_C*|p_l - p_r|/(p_l + p_r)*dt */
+                                 1: tau = tau_eps*dt + tau_C*|p_l - p_r|/(p_l + p_r)*dt;
+                                 2: viscous (Sec. 5.2, hexahedral meshes): tau = mu(T0)/p0 +
+                                    tau_C*|p_l - p_r|/(p_l + p_r)*dt with mu = mu_ref (T0/T_ref)^mu_exp,
+                                    T = p/rho of the collided interface state */
     double tau_eps;
     double tau_C;
     double weno_eps;          /* epsilon of the WENO-Z weights (Sec. 2.3) */
-    double gamma_lin;         /* linear weight of each sub-stencil; gamma_0 = 1 - 4 gamma_lin (Sec. 2.3: 0.025) */
+    double gamma_lin;         /* linear weight of each sub-stencil; gamma_0 = 1 - M gamma_lin with M = 4
+                                 sub-stencils (tetrahedra) or 8 (hexahedra) (Sec. 2.3: 0.025) */
     int precision;            /* hgks_precision */
     int accumulation;         /* hgks_accumulation */
     int reorder;              /* 1: renumber cells along a Morton curve of the centroids (default); 0: keep order */
+    double mu_ref;            /* tau_mode 2: viscosity at T_ref */
+    double T_ref;             /* tau_mode 2: reference temperature (T = p/rho) */
+    double mu_exp;            /* tau_mode 2: exponent of the power law (Sec. 5.2: 0.7) */
+    double prandtl;           /* tau_mode 2: Prandtl number; the energy flux takes (1/Pr - 1) times the
+                                 heat flux of the interface distribution in the frame of the collided
+                                 state's velocity (BGK alone has Pr = 1) */
+    double farfield[5];       /* free stream (rho, U, V, W, p) of HGKS_BC_FAR faces */
 } hgks_params;
 
 /* Fills the defaults: gamma 1.4, cfl 0.3, tau_mode 0, tau_eps 0.05, tau_C 1,
- * weno_eps 1e-8, gamma_lin 0.025, FP64, gather accumulation, reorder 1. */
+ * weno_eps 1e-8, gamma_lin 0.025, FP64, gather accumulation, reorder 1,
+ * mu_ref 0, T_ref 1, mu_exp 0.7, prandtl 1, farfield (1, 0, 0, 0, 1). */
 void hgks_default_params(hgks_params *p);
 
 typedef struct {
@@ -121,27 +140,42 @@ hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream,
                         const hgks_allocator *alloc, hgks_ctx **out);
 
 /*
- * Uploads a tetrahedral mesh (Sec. 3.1: CellNode connectivity plus node
- * coordinates) and builds, on the host, everything the step needs: faces
- * (face p of a cell is the one opposite its node p), neighbours, the two-layer
- * WENO stencil of Algorithm 1 and the four tetrahedral sub-stencils of
- * Sec. 2.3, cell and face geometry, the least-squares pseudo-inverses, and the
- * renumbering; then copies the packed arrays to the device.
+ * Uploads a mesh (Sec. 3.1: CellNode connectivity plus node coordinates) and
+ * builds, on the host, everything the step needs: faces, neighbours, the two-layer
+ * WENO stencil of Algorithm 1 and the sub-stencils of Sec. 2.3, cell and face
+ * geometry, the least-squares pseudo-inverses, and the renumbering; then copies
+ * the packed arrays to the device.
  *   xyz         [n_nodes][3] node coordinates
- *   cell_nodes  [n_cells][nodes_per_cell] node ids; nodes_per_cell must be 4
+ *   cell_nodes  [n_cells][nodes_per_cell] node ids.
+ *               nodes_per_cell 4: tetrahedra, face p opposite node p, four
+ *               sub-stencils, three Gauss points a face.
+ *               nodes_per_cell 8: hexahedra (trilinear), nodes 0-3 around one face
+ *               and node k+4 above node k; faces (0,1,2,3), (0,1,5,4), (1,2,6,5),
+ *               (2,3,7,6), (3,0,4,7), (4,5,6,7) are the paper's faces 1..6 (1 and 6
+ *               opposite), eight sub-stencils, and on each bilinear face the 2x2
+ *               Gauss points with their own normals.  Hexahedral meshes take the
+ *               FP64 and FP32-mixed precisions and the gather accumulation.
  *   period      [3]: period[a] > 0 identifies x_a with x_a + period[a] (NULL = none)
- *               An axis with period 0 ends in two transmissive walls, the planes
- *               through its lowest and highest node coordinate: every face that
- *               belongs to one cell only must lie in one of them (all three nodes
- *               there).  Algorithm 1 gives such a face a ghost neighbour "according
- *               to the boundary condition"; here the ghost is the mirror image of
- *               the wall cell in the wall, holding the wall cell's state, and a
- *               ghost's neighbours are the mirror images of the wall cell's.
- *   n_bfaces, bface_nodes, bface_kind: other boundary kinds; must be 0 / NULL
+ *               Tetrahedra: an axis with period 0 ends in two transmissive walls,
+ *               the planes through its lowest and highest node coordinate: every
+ *               face that belongs to one cell only must lie in one of them (all
+ *               three nodes there).  Algorithm 1 gives such a face a ghost neighbour
+ *               "according to the boundary condition"; here the ghost is the mirror
+ *               image of the wall cell in the wall, holding the wall cell's state,
+ *               and a ghost's neighbours are the mirror images of the wall cell's.
+ *   n_bfaces, bface_nodes [n_bfaces][4], bface_kind [n_bfaces] (hgks_bc_kind):
+ *               listed boundary faces of a hexahedral mesh without periodic axes
+ *               (0 / NULL otherwise); every face of one cell must be listed.  The
+ *               ghost across a listed face is the cell's mirror image in the face's
+ *               plane, holds the ghost state of the cell (no-slip wall or far field)
+ *               and has no neighbours of its own; at the face's Gauss points the
+ *               right side is the ghost map of the left reconstruction (wall: the
+ *               momentum negated and the gradient reflected; far field: the
+ *               Riemann-invariant state of the left value, no gradient).
  * Replaces any previous mesh and state.
- * Errors: INVALID_ARG, BAD_MESH (degenerate cell, a face shared by more than two
- * cells, an unshared face off the walls, a stencil reaching both walls of an axis,
- * a rank-deficient least-squares stencil), OOM, DEVICE.
+ * Errors: INVALID_ARG, BAD_MESH (degenerate or folded cell, a face shared by more
+ * than two cells, an unshared face off the walls or not listed, a stencil reaching
+ * both walls of an axis, a rank-deficient least-squares stencil), OOM, DEVICE.
  */
 hgks_status hgks_mesh_upload(hgks_ctx *ctx, int64_t n_nodes, const double *xyz,
                              int64_t n_cells, int nodes_per_cell, const int64_t *cell_nodes,
@@ -168,7 +202,8 @@ hgks_status hgks_get_state(hgks_ctx *ctx, double *q_out, double *t_out);
 /* Waits for the context's queued work.  Errors: DEVICE, NONPHYSICAL. */
 hgks_status hgks_sync(hgks_ctx *ctx);
 
-/* Mesh sizes after upload: cells, faces, two-layer stencil slots, colour classes
+/* Mesh sizes after upload: cells, faces, two-layer stencil slots (16 for tetrahedra;
+ * for hexahedra the largest stencil of the mesh, 24 on a regular lattice), colour classes
  * (with HGKS_ACC_COLOURED: 4 when the cell graph is bipartite, else at most 5;
  * 1 with the gather accumulation). */
 hgks_status hgks_mesh_info(const hgks_ctx *ctx, int64_t *n_cells, int64_t *n_faces,
@@ -191,13 +226,16 @@ void hgks_destroy(hgks_ctx *ctx);
 
 /*
  * Host-only inspection of the mesh precompute (no GPU needed): builds exactly
- * what mesh_upload would build and reports it in the library's internal order.
- *   stats [8]: n_faces, stencil slots (16), max distinct big-stencil members,
- *              min distinct big-stencil members, n_colours, max |pinv A - I|
- *              over all cells, max |sum_p n_p S_p| over all cells (closure),
- *              number of duplicate slots
+ * what mesh_upload would build (without listed boundary faces) and reports it in
+ * the library's internal order.
+ *   stats [8]: n_faces, stencil slots (16 for tetrahedra, the largest stencil for
+ *              hexahedra), max distinct big-stencil members, min distinct
+ *              big-stencil members, n_colours, max |pinv A - I| over all cells,
+ *              max |sum_p n_p S_p| over all cells (closure), number of duplicate
+ *              slots (tetrahedra)
  *   perm  [n_cells] (nullable): internal cell c holds caller cell perm[c]
- *   sten  [16][n_cells] (nullable): slot cell ids (internal numbering)
+ *   sten  [slots][n_cells] (nullable): slot cell ids (internal numbering); for
+ *         hexahedra size it from a first call's stats[1]
  * Errors as mesh_upload.
  */
 hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const double *xyz,
@@ -222,7 +260,8 @@ hgks_status hgks_pool_create(int device, void *hip_stream, size_t hbm_budget, hg
  * parameters hgks_create would reject, n_cells <= 0 or nodes_per_cell != 4. */
 hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int nodes_per_cell, size_t *bytes);
 /* Adds a context (mesh uploaded, state initialised); returns its slot id.  A context
- * belongs to at most one pool at a time.
+ * belongs to at most one pool at a time; pools take tetrahedral contexts (a
+ * hexahedral context steps on its own: INVALID_ARG).
  * Errors: STATE, INVALID_ARG (other device, already in a pool), OOM (budget exceeded). */
 hgks_status hgks_pool_add(hgks_pool *pool, hgks_ctx *ctx, int *slot);
 /* Advances the listed slots by nsteps S2O4 steps each (CFL dt per slot). */

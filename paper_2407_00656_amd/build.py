@@ -41,7 +41,7 @@ def build(verbose: bool = False, resource_usage: bool = False) -> str:
     if resource_usage:
         sys.stdout.write(r.stderr)
     objs.append(ku)
-    for src in ("mesh_build.cpp", "capi.cpp"):
+    for src in ("mesh_build.cpp", "mesh_hex.cpp", "capi.cpp"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o"))
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -86,6 +86,9 @@ struct hgks_ctx {
     std::string err;
     bool has_mesh = false, has_state = false;
     bool walls = false;           // the mesh has wall faces (a non-periodic axis)
+    bool hex = false;             // hexahedral mesh (its own kernels; steps alone, not in a pool)
+    int64_t ng = 0;               // ghosts of listed boundary faces (hexahedra)
+    int ns = 0;                   // stencil slots (hexahedra)
     int64_t nc = 0, nf = 0;
     std::vector<int64_t> perm;
     std::vector<int32_t> colour_offsets;   // face offsets of each colour class
@@ -189,15 +192,41 @@ hgks_status check_params(const hgks_params *p) {
     if (!p) return HGKS_E_INVALID_ARG;
     if (!(p->gamma > 1.0 && p->gamma < 5.0 / 3.0 + 1e-12)) return HGKS_E_INVALID_ARG;
     if (!(p->cfl > 0.0) || !(p->weno_eps > 0.0) || !(p->gamma_lin > 0.0 && p->gamma_lin < 0.25)) return HGKS_E_INVALID_ARG;
-    if (p->tau_mode < 0 || p->tau_mode > 1) return HGKS_E_INVALID_ARG;
+    if (p->tau_mode < 0 || p->tau_mode > 2) return HGKS_E_INVALID_ARG;
+    if (p->tau_mode == 2) {
+        if (!(p->mu_ref >= 0.0) || !(p->T_ref > 0.0) || !std::isfinite(p->mu_exp) || !(p->prandtl > 0.0) ||
+            !(p->tau_C >= 0.0))
+            return HGKS_E_INVALID_ARG;
+        if (!(p->farfield[0] > 0.0) || !(p->farfield[4] > 0.0)) return HGKS_E_INVALID_ARG;
+    }
     if (p->precision != HGKS_FP64 && p->precision != HGKS_FP32_MIXED && p->precision != HGKS_FP32)
         return HGKS_E_INVALID_ARG;
     if (p->accumulation != HGKS_ACC_GATHER && p->accumulation != HGKS_ACC_COLOURED) return HGKS_E_INVALID_ARG;
     return HGKS_OK;
 }
 
+// Queue one S2O4 step of a hexahedral context: per stage the ghost states, WENO,
+// the Gauss-point flux into the per-face buffer and the six-face update.
+void enqueue_step_hex(hgks_ctx *c, double dt_fixed) {
+    const bool mixed = c->prm.precision != HGKS_FP64;
+    hipStream_t s = c->stream;
+    timed(c, 0, [&] { launch_dt_final(c->d_desc, 1, dt_fixed, s); });
+    for (int stage = 1; stage <= 2; ++stage) {
+        timed(c, 1, [&] {
+            launch_hex_ghost(c->d_desc, (int)c->ng, stage, s);
+            launch_hex_weno(c->d_desc, c->d_ctiles, c->n_ctiles, stage, mixed, s);
+        });
+        timed(c, 2, [&] { launch_hex_flux(c->d_desc, c->d_ftiles, c->n_ftiles, stage, mixed, c->prm.tau_mode, s); });
+        timed(c, 3, [&] { launch_update(c->d_desc, c->d_ctiles, c->n_ctiles, stage, false, false, s, 6); });
+    }
+}
+
 // Queue one S2O4 step of a single context.
 void enqueue_step(hgks_ctx *c, double dt_fixed) {
+    if (c->hex) {
+        enqueue_step_hex(c, dt_fixed);
+        return;
+    }
     const int prec = c->prm.precision;
     const bool mixed = prec != HGKS_FP64;
     const bool tau0 = tau0_of(c->prm);
@@ -218,6 +247,164 @@ void enqueue_step(hgks_ctx *c, double dt_fixed) {
     }
 }
 
+// Device layout of a hexahedral context (FP64 storage; the FP32-mixed form keeps
+// FP32 reconstruction records).
+struct HexLayout {
+    size_t sten, pinv, binv, cgeo, cface, fcell, fgeo, gcell, gkind, gnrm, G, Q, Qs, R, C, FF, dtpart, scal, desc,
+        tiles, total;
+};
+
+HexLayout hex_layout(int64_t nc, int64_t nf, int64_t ng, int ns, int n_ctiles, int n_ftiles, bool mixed) {
+    HexLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t p = o; o += up(bytes); return p; };
+    const size_t g1 = (size_t)std::max<int64_t>(ng, 1);
+    L.sten = take((size_t)ns * nc * 4);
+    L.pinv = take((size_t)9 * ns * nc * 8);
+    L.binv = take((size_t)HEX_BINV * nc * 8);
+    L.cgeo = take((size_t)CGEO * nc * 8);
+    L.cface = take((size_t)6 * nc * 4);
+    L.fcell = take((size_t)2 * nf * 4);
+    L.fgeo = take((size_t)HEX_FGEO * nf * 8);
+    L.gcell = take(g1 * 4);
+    L.gkind = take(g1 * 4);
+    L.gnrm = take(3 * g1 * 8);
+    L.G = take(5 * g1 * 8);
+    L.Q = take((size_t)5 * nc * 8);
+    L.Qs = take((size_t)5 * nc * 8);
+    L.R = take((size_t)5 * nc * 8);
+    L.C = take((size_t)5 * NCOEF * nc * (mixed ? 4 : 8));
+    L.FF = take((size_t)10 * nf * 8);
+    L.dtpart = take((size_t)n_ctiles * 8);
+    L.scal = take(64);
+    L.desc = take(sizeof(ProbDesc));
+    L.tiles = take((size_t)(n_ctiles + n_ftiles) * sizeof(Tile));
+    L.total = o;
+    return L;
+}
+
+void fill_constants(ProbDesc &D, const hgks_params &p) {
+    D.gamma = p.gamma;
+    D.K = (5.0 - 3.0 * p.gamma) / (p.gamma - 1.0);
+    D.weno_eps = p.weno_eps;
+    D.gamma_lin = p.gamma_lin;
+    D.cfl = p.cfl;
+    D.tau_eps = p.tau_eps;
+    D.tau_C = p.tau_C;
+    D.tau_mode = p.tau_mode;
+    D.mixed = p.precision != HGKS_FP64 ? 1 : 0;
+    D.mu_ref = p.mu_ref;
+    D.T_ref = p.T_ref;
+    D.mu_exp = p.mu_exp;
+    D.prandtl = p.prandtl;
+    for (int k = 0; k < 5; ++k) D.farfield[k] = p.farfield[k];
+}
+
+hgks_status upload_hex(hgks_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_cells, const int64_t *cell_nodes,
+                       const double *period, int64_t n_bfaces, const int64_t *bface_nodes, const int32_t *bface_kind) {
+    if (c->prm.precision == HGKS_FP32)
+        return fail(c, HGKS_E_INVALID_ARG, "hexahedral meshes take the FP64 and FP32-mixed precisions");
+    if (c->prm.accumulation != HGKS_ACC_GATHER)
+        return fail(c, HGKS_E_INVALID_ARG, "hexahedral meshes take the gather accumulation");
+    HexMesh hm;
+    std::string err;
+    hgks_status st = build_hex_mesh(c->prm, n_nodes, xyz, n_cells, cell_nodes, period, n_bfaces, bface_nodes,
+                                    bface_kind, hm, err);
+    if (st != HGKS_OK) return fail(c, st, err);
+    HIPCHK(c, hipSetDevice(c->device));
+    release(c);
+    const bool mixed = c->prm.precision != HGKS_FP64;
+    std::vector<Tile> ct, ft;
+    const int nct = n_cell_tiles(hm.nc);
+    for (int t = 0; t < nct; ++t) {
+        int b = t * UPD_TILE;
+        ct.push_back({0, b, t, (int32_t)std::min<int64_t>(hm.nc, b + UPD_TILE)});
+    }
+    xcd_order(ct, 0, ct.size());
+    for (int64_t b = 0; b < hm.nf; b += HEX_FLUX_FACES)
+        ft.push_back({0, (int32_t)b, (int)ft.size(), (int32_t)std::min<int64_t>(hm.nf, b + HEX_FLUX_FACES)});
+    xcd_order(ft, 0, ft.size());
+    HexLayout L = hex_layout(hm.nc, hm.nf, hm.ng, hm.ns, (int)ct.size(), (int)ft.size(), mixed);
+    void *mem = nullptr;
+    if (c->user_alloc) {
+        mem = c->alloc.alloc(L.total, c->stream, c->alloc.user);
+        if (!mem) return fail(c, HGKS_E_OOM, "allocator returned NULL");
+    } else {
+        hipError_t e = hipMalloc(&mem, L.total);
+        if (e != hipSuccess) return fail(c, HGKS_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->base = (char *)mem;
+    c->bytes = L.total;
+    char *B = c->base;
+    ProbDesc &D = c->desc;
+    D = ProbDesc{};
+    D.nc = (int32_t)hm.nc;
+    D.nf = (int32_t)hm.nf;
+    D.n_cell_tiles = (int32_t)ct.size();
+    D.ns = hm.ns;
+    D.ng = (int32_t)hm.ng;
+    D.sten = (const int32_t *)(B + L.sten);
+    D.hpinv = (const double *)(B + L.pinv);
+    D.hbinv = (const double *)(B + L.binv);
+    D.cgeo = (const double *)(B + L.cgeo);
+    D.cface = (const int32_t *)(B + L.cface);
+    D.fcell = (const int32_t *)(B + L.fcell);
+    D.fgeo = (const double *)(B + L.fgeo);
+    D.gcell = (const int32_t *)(B + L.gcell);
+    D.gkind = (const int32_t *)(B + L.gkind);
+    D.gnrm = (const double *)(B + L.gnrm);
+    D.G = (double *)(B + L.G);
+    D.Q = (double *)(B + L.Q);
+    D.Qs = (double *)(B + L.Qs);
+    D.R = (double *)(B + L.R);
+    D.C = mixed ? nullptr : (double *)(B + L.C);
+    D.C32 = mixed ? (float *)(B + L.C) : nullptr;
+    D.FF = (double *)(B + L.FF);
+    D.dtpart = (double *)(B + L.dtpart);
+    D.dt = (double *)(B + L.scal);
+    D.time = (double *)(B + L.scal + 8);
+    D.flag = (int32_t *)(B + L.scal + 16);
+    fill_constants(D, c->prm);
+    c->d_desc = (ProbDesc *)(B + L.desc);
+    c->d_ctiles = (Tile *)(B + L.tiles);
+    c->d_ftiles = c->d_ctiles + ct.size();
+    c->n_ctiles = (int)ct.size();
+    c->n_ftiles = (int)ft.size();
+    c->h_ctiles = ct;
+    c->h_ftiles = ft;
+    hipStream_t s = c->stream;
+    auto h2d = [&](const void *dst, const void *src, size_t n) {
+        return hipMemcpyAsync((void *)dst, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIPCHK(c, h2d(D.sten, hm.sten.data(), hm.sten.size() * 4));
+    HIPCHK(c, h2d(D.hpinv, hm.pinv.data(), hm.pinv.size() * 8));
+    HIPCHK(c, h2d(D.hbinv, hm.binv.data(), hm.binv.size() * 8));
+    HIPCHK(c, h2d(D.cgeo, hm.cgeo.data(), hm.cgeo.size() * 8));
+    HIPCHK(c, h2d(D.cface, hm.cface.data(), hm.cface.size() * 4));
+    HIPCHK(c, h2d(D.fcell, hm.fcell.data(), hm.fcell.size() * 4));
+    HIPCHK(c, h2d(D.fgeo, hm.fgeo.data(), hm.fgeo.size() * 8));
+    if (hm.ng > 0) {
+        HIPCHK(c, h2d(D.gcell, hm.gcell.data(), hm.gcell.size() * 4));
+        HIPCHK(c, h2d(D.gkind, hm.gkind.data(), hm.gkind.size() * 4));
+        HIPCHK(c, h2d(D.gnrm, hm.gnrm.data(), (size_t)3 * hm.ng * 8));
+    }
+    HIPCHK(c, h2d(c->d_desc, &D, sizeof(ProbDesc)));
+    HIPCHK(c, h2d(c->d_ctiles, ct.data(), ct.size() * sizeof(Tile)));
+    HIPCHK(c, h2d(c->d_ftiles, ft.data(), ft.size() * sizeof(Tile)));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->nc = hm.nc;
+    c->nf = hm.nf;
+    c->ng = hm.ng;
+    c->ns = hm.ns;
+    c->perm = std::move(hm.perm);
+    c->colour_offsets.assign({0, (int32_t)hm.nf});
+    c->walls = false;
+    c->hex = true;
+    c->has_mesh = true;
+    c->has_state = false;
+    return HGKS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -234,6 +421,13 @@ void hgks_default_params(hgks_params *p) {
     p->precision = HGKS_FP64;
     p->accumulation = HGKS_ACC_GATHER;
     p->reorder = 1;
+    p->mu_ref = 0.0;
+    p->T_ref = 1.0;
+    p->mu_exp = 0.7;
+    p->prandtl = 1.0;
+    p->farfield[0] = 1.0;
+    p->farfield[1] = p->farfield[2] = p->farfield[3] = 0.0;
+    p->farfield[4] = 1.0;
 }
 
 hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream, const hgks_allocator *alloc,
@@ -274,8 +468,11 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
                              const int64_t *bface_nodes, const int32_t *bface_kind) {
     if (!c) return HGKS_E_INVALID_ARG;
     if (c->pool_refs) return fail(c, HGKS_E_STATE, "context is in a pool");
+    if (npc == 8) return upload_hex(c, n_nodes, xyz, n_cells, cell_nodes, period, n_bfaces, bface_nodes, bface_kind);
     if (n_bfaces != 0 || bface_nodes || bface_kind)
-        return fail(c, HGKS_E_INVALID_ARG, "boundary faces are not supported: every face must join two cells");
+        return fail(c, HGKS_E_INVALID_ARG, "listed boundary faces are taken on hexahedral meshes only");
+    if (c->prm.tau_mode == 2)
+        return fail(c, HGKS_E_INVALID_ARG, "the viscous collision time (tau_mode 2) is taken on hexahedral meshes only");
     HostMesh hm;
     std::string err;
     hgks_status st = build_mesh(c->prm, n_nodes, xyz, n_cells, npc, cell_nodes, period, hm, err);
@@ -408,6 +605,9 @@ hgks_status hgks_mesh_upload(hgks_ctx *c, int64_t n_nodes, const double *xyz, in
     c->perm = std::move(hm.perm);
     c->colour_offsets = hm.colour_offsets;
     c->walls = hm.n_wall_faces > 0;
+    c->hex = false;
+    c->ng = 0;
+    c->ns = SLOTS;
     c->has_mesh = true;
     c->has_state = false;
     return HGKS_OK;
@@ -515,7 +715,7 @@ hgks_status hgks_mesh_info(const hgks_ctx *c, int64_t *n_cells, int64_t *n_faces
     if (!c->has_mesh) return HGKS_E_STATE;
     if (n_cells) *n_cells = c->nc;
     if (n_faces) *n_faces = c->nf;
-    if (slots) *slots = SLOTS;
+    if (slots) *slots = c->ns;
     if (ncol) *ncol = (int32_t)c->colour_offsets.size() - 1;
     return HGKS_OK;
 }
@@ -572,6 +772,25 @@ hgks_status hgks_inspect_mesh(const hgks_params *params, int64_t n_nodes, const 
     hgks_params p;
     if (params) p = *params; else hgks_default_params(&p);
     if (check_params(&p) != HGKS_OK) return HGKS_E_INVALID_ARG;
+    if (npc == 8) {
+        HexMesh hx;
+        std::string err;
+        hgks_status st = build_hex_mesh(p, n_nodes, xyz, n_cells, cell_nodes, period, 0, nullptr, nullptr, hx, err, true);
+        if (st != HGKS_OK) return st;
+        if (stats) {
+            stats[0] = (double)hx.nf;
+            stats[1] = hx.ns;
+            stats[2] = hx.max_members;
+            stats[3] = hx.min_members;
+            stats[4] = 1;
+            stats[5] = hx.pinv_residual;
+            stats[6] = hx.closure;
+            stats[7] = 0;
+        }
+        if (perm) std::memcpy(perm, hx.perm.data(), hx.perm.size() * 8);
+        if (sten) std::memcpy(sten, hx.sten.data(), hx.sten.size() * 4);
+        return HGKS_OK;
+    }
     HostMesh hm;
     std::string err;
     hgks_status st = build_mesh(p, n_nodes, xyz, n_cells, npc, cell_nodes, period, hm, err, true);
@@ -798,7 +1017,7 @@ hgks_status hgks_pool_footprint(const hgks_params *params, int64_t n_cells, int 
 hgks_status hgks_pool_add(hgks_pool *p, hgks_ctx *c, int *slot) {
     if (!p || !c || !slot) return HGKS_E_INVALID_ARG;
     if (!c->has_state) return HGKS_E_STATE;
-    if (c->device != p->device || c->prm.accumulation != HGKS_ACC_GATHER) return HGKS_E_INVALID_ARG;
+    if (c->device != p->device || c->prm.accumulation != HGKS_ACC_GATHER || c->hex) return HGKS_E_INVALID_ARG;
     if (p->budget && p->used + c->bytes > p->budget) return HGKS_E_OOM;
     if (c->pool) return HGKS_E_INVALID_ARG;     // a context belongs to one pool at a time
     // the pool runs on its own stream: finish the context's queued work first

@@ -37,6 +37,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <string>
 #include <utility>
@@ -110,6 +111,47 @@ hgks_status build_mesh(const hgks_params &prm, int64_t n_nodes, const double *xy
                        HostMesh &out, std::string &err, bool diagnostics = false);
 
 int host_threads();
+
+// (A^T A)^{-1} A^T of a full-column-rank m x n matrix (row-major, n <= 9) through a
+// Cholesky factor of A^T A; false on a negligible pivot (rank deficiency).
+bool pinv_normal(int m, int n, const double *A, double *P);
+
+// Runs f(begin, end) over [0, n) on the host threads.
+void parallel_range(int64_t n, const std::function<void(int64_t, int64_t)> &f);
+
+// Hexahedral meshes (nodes 0-3 around one face, node k+4 above node k; faces in
+// the order 0 = (0,1,2,3), 1 = (0,1,5,4), 2 = (1,2,6,5), 3 = (2,3,7,6), 4 = (3,0,4,7),
+// 5 = (4,5,6,7), so that faces 0 and 5 are opposite, as faces 1 and 6 of Sec. 2.3).
+constexpr int HEX_FGEO = 34;       // per face: 4 x (n(3), w, y_l(3)), dlr(3), mean normal(3)
+constexpr int HEX_BINV = 72;       // per cell: 8 sub-stencils x 3 x 3
+// sub-stencils of Sec. 2.3 as face indices: S_1 = {i1,i2,i3}, ..., S_8 = {i6,i5,i2}
+constexpr int HEXSUB[8][3] = {{0, 1, 2}, {0, 2, 3}, {0, 3, 4}, {0, 4, 1}, {5, 1, 2}, {5, 2, 3}, {5, 3, 4}, {5, 4, 1}};
+
+struct HexMesh {
+    int64_t nc = 0, nf = 0, ng = 0;
+    int ns = 0;                     // stencil slots (0..5 the face neighbours in face order)
+    std::vector<int64_t> perm;      // internal cell c holds caller cell perm[c]
+    hvec<int32_t> sten;             // [ns][nc] member ids; id >= nc is ghost id - nc
+    hvec<double> pinv;              // [9 ns][nc]: row r, slot s at (r ns + s)
+    hvec<double> binv;              // [72][nc]: sub-stencil m, row k, member t at (m 3 + k) 3 + t
+    hvec<double> cgeo;              // [9][nc] as the tetrahedral layout
+    hvec<int32_t> cface;            // [6][nc] (face << 1) | (cell is the face's right cell)
+    hvec<int32_t> fcell;            // [2][nf]; right = -kind at a listed boundary face
+    hvec<double> fgeo;              // [34][nf]
+    hvec<int32_t> gcell, gkind;     // [ng]
+    hvec<double> gnrm;              // [3][ng] outward (mean) normal of the ghost's face
+    // diagnostics
+    int max_members = 0, min_members = 0;
+    double pinv_residual = 0.0, closure = 0.0;
+};
+
+// Builds the device-ready arrays of a hexahedral mesh.  Boundary faces: listed faces
+// (kinds HGKS_BC_WALL, HGKS_BC_FAR; no periodic axis then), every other face shared
+// by two cells (periodic images allowed).
+hgks_status build_hex_mesh(const hgks_params &prm, int64_t n_nodes, const double *xyz, int64_t n_cells,
+                           const int64_t *cell_nodes, const double *period, int64_t n_bfaces,
+                           const int64_t *bface_nodes, const int32_t *bface_kind, HexMesh &out, std::string &err,
+                           bool diagnostics = false);
 
 // The big-stencil pseudo-inverse rounded to FP32 in quad rows: quad row k of cell i
 // holds pair rows 2k and 2k+1, out[(k * nc + i) * 4 + e] (FP32 form; multithreaded).

@@ -39,6 +39,17 @@ struct ProbDesc {
                                   // (a member mirrored in a wall sits at mir - x)
     double gamma, K, weno_eps, gamma_lin, cfl, tau_eps, tau_C;
     int32_t tau_mode, mixed;
+    // viscous collision time (tau_mode 2) and the free stream of far-field faces
+    double mu_ref, T_ref, mu_exp, prandtl;
+    double farfield[5];
+    // hexahedral meshes (ns stencil slots, ng ghosts of listed boundary faces)
+    int32_t ns, ng;
+    const double *hpinv;          // big-stencil pseudo-inverse [9 ns][nc]
+    const double *hbinv;          // sub-stencil inverses [72][nc]
+    const int32_t *gcell;         // ghost -> its cell [ng]
+    const int32_t *gkind;         // ghost kind (HGKS_BC_WALL / HGKS_BC_FAR) [ng]
+    const double *gnrm;           // ghost face's outward mean normal [3][ng]
+    double *G;                    // ghost states of the current stage [5][ng]
 };
 
 struct Tile {
@@ -61,7 +72,16 @@ void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntile
                  bool coloured, bool walls, hipStream_t s);
 // s32: the FP32 form's storage (state, cell geometry, face fluxes in FP32)
 void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, bool s32,
-                   hipStream_t s);
+                   hipStream_t s, int faces_per_cell = 4);
+
+// Hexahedral meshes: ghost states, WENO (one wave per variable of 64 cells), the
+// Gauss-point flux (tau = 0, tau > 0 shock mode, or viscous) into the per-face buffer.
+constexpr int HEX_WENO_CELLS = 64;
+constexpr int HEX_FLUX_FACES = 64;   // faces per flux workgroup (four lanes a face)
+void launch_hex_ghost(const ProbDesc *d, int ng, int stage, hipStream_t s);
+void launch_hex_weno(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s);
+void launch_hex_flux(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, int tau_mode,
+                     hipStream_t s);
 void launch_dt_local(const ProbDesc *probs, const Tile *tiles, int ntiles, bool s32, hipStream_t s);
 void launch_dt_final(const ProbDesc *probs, int nprobs, double dt_fixed, hipStream_t s);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);

@@ -12,6 +12,9 @@
 //              the S2O4 update does not use).
 //   k_flux     the same for tau > 0: one wave per Gauss point, the three
 //              contributions summed through LDS.
+//   k_*_hex    the same steps on hexahedral meshes (eight sub-stencils, 2x2 Gauss
+//              points on bilinear faces, listed wall and far-field boundaries,
+//              viscous collision time).
 //   k_update   S2O4 stage update (Sec. 2.2).  Each cell gathers its four face
 //              fluxes in a fixed order: deterministic, no atomics.  The second
 //              stage also forms the next step's CFL bound per tile.
@@ -98,6 +101,8 @@ __device__ __forceinline__ void stg(void *base, uint32_t off, const T &v) {
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ double hg_exp(double x) { return exp(x); }
 __device__ __forceinline__ float hg_exp(float x) { return expf(x); }
+__device__ __forceinline__ double hg_pow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float hg_pow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double hg_abs(double x) { return fabs(x); }
 __device__ __forceinline__ float hg_abs(float x) { return fabsf(x); }
 // Reciprocal and reciprocal square root.  FP64: the hardware estimate refined by
@@ -833,10 +838,10 @@ __device__ __forceinline__ void second_moment_jvp(const T n[3], const T U[3], T 
 // over u > 0 (sgn = +1, the left state) or u < 0 (sgn = -1).  The time slope A
 // follows from <a_1 u + a_2 v + a_3 w + A> = 0, i.e. rho <(A.psi) psi> = -sum_j
 // dF_j/dQ dQ/dx_j (Euler Jacobians along the frame axes).
-template <class T>
+template <class T, bool WMOM = false>
 __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], const T n[3], const T t1[3],
                                              const T t2[3], T h0, T h1, T K, T gam, T Kp3, T c4k, T e0[5], T e1[5],
-                                             T e2[5]) {
+                                             T e2[5], T w0[5] = nullptr, T w1[5] = nullptr, T w2[5] = nullptr) {
     const State<T> s = make_state(Qf, gam, Kp3, c4k);
     const T *e[3] = {n, t1, t2};
     const T u[3] = {s.U, s.V, s.W};
@@ -877,6 +882,23 @@ __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], con
 #pragma unroll
     for (int k = 0; k < 5; ++k) e1[k] += t[k];
     apsi<T, 1, 0, 0>(M, A, e2);
+    if constexpr (WMOM) {
+        // the same three pieces without the factor u: the conserved moments
+        //   w0 = <psi>,  w1 = sum_j <u_j (a_j.psi) psi>,  w2 = <(A.psi) psi>
+        w0[0] = M.u[0];
+        w0[1] = M.u[1];
+        w0[2] = M.u[0] * M.v[1];
+        w0[3] = M.u[0] * M.w[1];
+        w0[4] = T(0.5) * (M.u[2] + M.u[0] * (M.v[2] + M.w[2] + M.xi2));
+        apsi<T, 1, 0, 0>(M, a[0], w1);
+        apsi<T, 0, 1, 0>(M, a[1], t);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) w1[k] += t[k];
+        apsi<T, 0, 0, 1>(M, a[2], t);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) w1[k] += t[k];
+        apsi<T, 0, 0, 0>(M, A, w2);
+    }
 }
 
 // General collision time (Eq. flux with tau > 0): the equilibrium part and both
@@ -888,25 +910,19 @@ __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], con
 //     formed.  The sum over the frame directions j equals the sum over the axes.
 //   * Initial parts, in the local frame (n, t1, t2), where the half-space moments
 //     factorise (initial_part).
-template <class T>
+//   * VISC (tau_mode 2): tau = mu(T0)/p0 + the pressure-jump term with the power-law
+//     viscosity of the collided state, and for Pr != 1 the energy flux takes
+//     (1/Pr - 1) times the heat flux of the interface distribution in the frame of
+//     U0: q = F_E - U0.F_m + |U0|^2/2 F_rho - U0.n (W_E - U0.W_m + |U0|^2/2 W_rho), with
+//     W the distribution's conserved moments (time-fitted like F): the equilibrium
+//     part's are Q0 and its time derivative (the u_j-weighted slope term is -Q_t),
+//     the initial parts' come from their half-space moments.
+template <class T, bool VISC = false>
 __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], const T qr[5], const T gr[5][3],
                                               const T n[3], T dt, const ProbDesc &P, T F[5], T dF[5]) {
     const T K = (T)P.K, Kp3 = K + T(3), gam = (T)P.gamma, gm1 = gam - T(1), c4k = T(4) / Kp3;
     const SideG<T> sl = side_state(ql, n, gm1), sr = side_state(qr, n, gm1);
-    // time-integral weights: F = (4 I(dt/2) - I(dt)) / dt, dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
     const T pl = sl.rho * sl.i2l, pr = sr.rho * sr.i2l;
-    T tau = T(0);
-    if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
-    T q1[6], qh[6], cF[6], cD[6];
-    const T Eh = tau > T(0) ? hg_exp(T(-0.5) * dt / tau) : T(0);
-    q_coef(dt, tau, Eh * Eh, q1);
-    q_coef(T(0.5) * dt, tau, Eh, qh);
-    const T idt = T(1) / dt;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        cF[k] = (T(4) * qh[k] - q1[k]) * idt;
-        cD[k] = T(4) * (q1[k] - T(2) * qh[k]) * idt * idt;
-    }
     // collision: Q0 = int_{u_n>0} psi g_l + int_{u_n<0} psi g_r (normal moments only)
     T ml[3], mr[3];
     mom_half<T, 3>(sl.un, sl.lam, sl.i2l, T(1), ml);
@@ -924,6 +940,22 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     const T u20 = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
     const T p0 = gm1 * (E0 - T(0.5) * rho0 * u20);
     const T H0 = (E0 + p0) * ir0;
+    // time-integral weights: F = (4 I(dt/2) - I(dt)) / dt, dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
+    T tau = T(0);
+    if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
+    if constexpr (VISC)
+        tau = (T)P.mu_ref * hg_pow(p0 * ir0 / (T)P.T_ref, (T)P.mu_exp) / p0 +
+              (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
+    T q1[6], qh[6], cF[6], cD[6];
+    const T Eh = tau > T(0) ? hg_exp(T(-0.5) * dt / tau) : T(0);
+    q_coef(dt, tau, Eh * Eh, q1);
+    q_coef(T(0.5) * dt, tau, Eh, qh);
+    const T idt = T(1) / dt;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        cF[k] = (T(4) * qh[k] - q1[k]) * idt;
+        cD[k] = T(4) * (q1[k] - T(2) * qh[k]) * idt * idt;
+    }
     T gsum[5][3];
 #pragma unroll
     for (int q = 0; q < 5; ++q)
@@ -956,25 +988,34 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     // initial parts, local frame
     T t1[3], t2[3];
     frame(n, t1, t2);
-    T Fl[5], dFl[5];
+    const bool heat = VISC && P.prandtl != 1.0;
+    T Fl[5], dFl[5], Wl[5], dWl[5];
     {
-        T Qf[5], e0[5], e1[5], e2[5];
+        T Qf[5], e0[5], e1[5], e2[5], w0[5], w1[5], w2[5];
         rot_in(ql, n, t1, t2, Qf);
-        initial_part(Qf, gl, n, t1, t2, ml[0], ml[1], K, gam, Kp3, c4k, e0, e1, e2);
+        initial_part<T, VISC>(Qf, gl, n, t1, t2, ml[0], ml[1], K, gam, Kp3, c4k, e0, e1, e2, w0, w1, w2);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             Fl[k] = sl.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
             dFl[k] = sl.rho * (cD[3] * e0[k] + cD[4] * e1[k] + cD[5] * e2[k]);
+            if constexpr (VISC) {
+                Wl[k] = sl.rho * (cF[3] * w0[k] + cF[4] * w1[k] + cF[5] * w2[k]);
+                dWl[k] = sl.rho * (cD[3] * w0[k] + cD[4] * w1[k] + cD[5] * w2[k]);
+            }
         }
     }
     {
-        T Qf[5], e0[5], e1[5], e2[5];
+        T Qf[5], e0[5], e1[5], e2[5], w0[5], w1[5], w2[5];
         rot_in(qr, n, t1, t2, Qf);
-        initial_part(Qf, gr, n, t1, t2, mr[0], mr[1], K, gam, Kp3, c4k, e0, e1, e2);
+        initial_part<T, VISC>(Qf, gr, n, t1, t2, mr[0], mr[1], K, gam, Kp3, c4k, e0, e1, e2, w0, w1, w2);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             Fl[k] += sr.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
             dFl[k] += sr.rho * (cD[3] * e0[k] + cD[4] * e1[k] + cD[5] * e2[k]);
+            if constexpr (VISC) {
+                Wl[k] += sr.rho * (cF[3] * w0[k] + cF[4] * w1[k] + cF[5] * w2[k]);
+                dWl[k] += sr.rho * (cD[3] * w0[k] + cD[4] * w1[k] + cD[5] * w2[k]);
+            }
         }
     }
     T Fg[5], dFg[5];
@@ -984,6 +1025,27 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     for (int k = 0; k < 5; ++k) {
         F[k] += Fg[k];
         dF[k] += dFg[k];
+    }
+    if constexpr (VISC) {
+        if (heat) {
+            T W[5], dW[5];
+            rot_out(Wl, n, t1, t2, W);
+            rot_out(dWl, n, t1, t2, dW);
+            const T Q0[5] = {rho0, mom0[0], mom0[1], mom0[2], E0};
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                W[k] += cF[0] * Q0[k] + (cF[2] - cF[1]) * Qt[k];
+                dW[k] += cD[0] * Q0[k] + (cD[2] - cD[1]) * Qt[k];
+            }
+            const T h2 = T(0.5) * u20;
+            const T qh = F[4] - (u0[0] * F[1] + u0[1] * F[2] + u0[2] * F[3]) + h2 * F[0] -
+                         un0 * (W[4] - (u0[0] * W[1] + u0[1] * W[2] + u0[2] * W[3]) + h2 * W[0]);
+            const T dqh = dF[4] - (u0[0] * dF[1] + u0[1] * dF[2] + u0[2] * dF[3]) + h2 * dF[0] -
+                          un0 * (dW[4] - (u0[0] * dW[1] + u0[1] * dW[2] + u0[2] * dW[3]) + h2 * dW[0]);
+            const T cpr = T(1) / (T)P.prandtl - T(1);
+            F[4] += cpr * qh;
+            dF[4] += cpr * dqh;
+        }
     }
 }
 
@@ -1588,7 +1650,7 @@ __device__ __forceinline__ double cfl_bound(const ProbDesc &P, uint32_t i, const
     return Sto<S32>::ld(P.cgeo, 8, (uint32_t)P.nc, i) / (sqrt(u * u + v * v + w * w) + c);
 }
 
-template <int STAGE, bool COLOURED, bool S32 = false>
+template <int STAGE, bool COLOURED, bool S32 = false, int NFC = 4>
 __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict__ probs,
                                                       const Tile *__restrict__ tiles) {
     using ST = Sto<S32>;
@@ -1610,7 +1672,7 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
 #pragma unroll
             for (int k = 0; k < 10; ++k) s[k] = 0.0;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {       // the cell's four faces, fixed order
+            for (int p = 0; p < NFC; ++p) {     // the cell's faces, fixed order
                 const uint32_t code = (uint32_t)ldg<int32_t>(P.cface + (size_t)p * nc, i * 4u);
                 const uint32_t f = code >> 1;
                 const double sg = (code & 1u) ? 1.0 : -1.0;   // the normal points out of the left cell
@@ -1705,6 +1767,334 @@ __global__ void k_fill(double *p, double v, int64_t n) {
 }
 
 // ----------------------------------------------------------------------------
+// hexahedral meshes
+// ----------------------------------------------------------------------------
+
+// Far-field state by Riemann invariants (characteristic boundary, Sec. 5.2) for the
+// outward normal n: the outgoing invariant U.n + 2c/(g-1) comes from q, the incoming
+// U.n - 2c/(g-1) from the free stream; entropy p/rho^g and tangential velocity from
+// q at an outflow, from the free stream at an inflow.  A supersonic outflow keeps
+// q, a supersonic inflow takes the free stream.
+template <class T>
+__device__ __forceinline__ void farfield_state(const ProbDesc &P, const T q[5], const T n[3], T out[5]) {
+    const T g = (T)P.gamma, gm1 = g - T(1);
+    const T ir = T(1) / q[0];
+    const T u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+    const T pi = gm1 * (q[4] - T(0.5) * q[0] * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+    const T rf = (T)P.farfield[0], pf = (T)P.farfield[4];
+    const T uf[3] = {(T)P.farfield[1], (T)P.farfield[2], (T)P.farfield[3]};
+    const T ci = sqrt(g * pi * ir), cf = sqrt(g * pf / rf);
+    const T vi = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    const T vf = uf[0] * n[0] + uf[1] * n[1] + uf[2] * n[2];
+    T rb, pb, ub[3];
+    if (vi >= ci) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) out[k] = q[k];
+        return;
+    }
+    if (vi <= -ci) {
+        rb = rf;
+        pb = pf;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ub[a] = uf[a];
+    } else {
+        const T Rp = vi + T(2) * ci / gm1, Rm = vf - T(2) * cf / gm1;
+        const T vb = T(0.5) * (Rp + Rm), cb = T(0.25) * gm1 * (Rp - Rm);
+        const bool outflow = vb > T(0);
+        const T ent = outflow ? pi / hg_pow(q[0], g) : pf / hg_pow(rf, g);
+        const T vt = outflow ? vi : vf;
+        rb = hg_pow(cb * cb / (g * ent), T(1) / gm1);
+        pb = rb * cb * cb / g;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ub[a] = (outflow ? u[a] : uf[a]) - vt * n[a] + vb * n[a];
+    }
+    out[0] = rb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[1 + a] = rb * ub[a];
+    out[4] = pb / gm1 + T(0.5) * rb * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+}
+
+// Ghost states of the listed boundary faces for the stage's state: a wall ghost holds
+// (rho, -rho U, rho E) of its cell, a far-field ghost the Riemann-invariant state of
+// its cell for the face's mean normal.  The WENO pass reads them as stencil members.
+__global__ __launch_bounds__(256) void k_ghost_hex(const ProbDesc *__restrict__ d, int stage) {
+    const ProbDesc &P = *d;
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t ng = (uint32_t)P.ng, nc = (uint32_t)P.nc;
+    if (g >= ng) return;
+    const uint32_t c = (uint32_t)P.gcell[g];
+    const double *Qa = stage == 1 ? P.Q : P.Qs;
+    double q[5], o[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = Qa[(size_t)v * nc + c];
+    if (P.gkind[g] == HGKS_BC_WALL) {
+        o[0] = q[0]; o[1] = -q[1]; o[2] = -q[2]; o[3] = -q[3]; o[4] = q[4];
+    } else {
+        const double n[3] = {P.gnrm[g], P.gnrm[ng + g], P.gnrm[2 * ng + g]};
+        farfield_state<double>(P, q, n, o);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) P.G[(size_t)v * ng + g] = o[v];
+}
+
+// WENO on hexahedra (Sec. 2.3, M = 8): wave v of a workgroup forms variable v of its
+// 64 cells, one lane a cell.  The big-stencil fit a = P (Q_k - Q_i) streams the
+// pseudo-inverse once (each of its rows is read by the five waves of the workgroup,
+// four of them from cache); the eight linear fits of the exactly determined
+// sub-stencils {i, i_a, i_b, i_c} use their precomputed 3x3 inverses on the first
+// six slots (the face neighbours in face order); the smoothness indicators, WENO-Z
+// weights (gamma_0 = 1 - 8 gamma) and the combined polynomial follow the tetrahedral
+// kernel, and the record layout is the same, so the flux reads it alike.
+template <bool MIXED>
+__global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc *__restrict__ probs,
+                                                                  const Tile *__restrict__ tiles, int stage) {
+    using T = typename std::conditional<MIXED, float, double>::type;
+    const Tile tl = tiles[blockIdx.x];
+    const ProbDesc &P = probs[tl.prob];
+    const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / HEX_WENO_CELLS));
+    const uint32_t i = (uint32_t)tl.begin + threadIdx.x % HEX_WENO_CELLS;
+    if (i >= (uint32_t)tl.end) return;
+    const uint32_t nc = (uint32_t)P.nc, ng = (uint32_t)P.ng;
+    const int ns = P.ns;
+    const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)v * nc;
+    const double *Gv = P.G + (size_t)v * ng;
+    const double qi = Qv[i];
+    auto member = [&](int s) {
+        const uint32_t id = (uint32_t)P.sten[(size_t)s * nc + i];
+        return (id < nc ? Qv[id] : Gv[id - nc]) - qi;
+    };
+    double a64[9], d6[6];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) a64[r] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        d6[s] = member(s);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) a64[r] = fma(P.hpinv[((size_t)r * ns + s) * nc + i], d6[s], a64[r]);
+    }
+    for (int s = 6; s < ns; ++s) {
+        const double d = member(s);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) a64[r] = fma(P.hpinv[((size_t)r * ns + s) * nc + i], d, a64[r]);
+    }
+    T a[9], M[6];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) a[r] = (T)a64[r];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) M[q] = (T)P.cgeo[(size_t)(1 + q) * nc + i];
+    const double *B = P.hbinv + i;
+    auto sub_fit = [&](int m, T b[3]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) s = fma(B[(size_t)((m * 3 + k) * 3 + t) * nc], d6[HEXSUB[m][t]], s);
+            b[k] = (T)s;
+        }
+    };
+    // smoothness indicators in scaled coordinates (mean over the cell of the squared
+    // first derivatives, plus the squared second derivatives of P0)
+    T beta[9];
+    beta[0] = a[0] * a[0] + quad_form(M, T(2) * a[3], a[6], a[7]) + a[1] * a[1] + quad_form(M, a[6], T(2) * a[4], a[8]) +
+              a[2] * a[2] + quad_form(M, a[7], a[8], T(2) * a[5]) +
+              T(4) * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]) + a[6] * a[6] + a[7] * a[7] + a[8] * a[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        T b[3];
+        sub_fit(m, b);
+        beta[1 + m] = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    }
+    const T gl = (T)P.gamma_lin, g0 = T(1) - T(8) * gl, eps = (T)P.weno_eps;
+    T tauZ = T(0);
+#pragma unroll
+    for (int m = 1; m < 9; ++m) tauZ += hg_abs(beta[0] - beta[m]);
+    tauZ *= T(0.125);
+    T w[9], ws = T(0);
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        w[m] = (m == 0 ? g0 : gl) * (T(1) + tauZ * hg_rcp(beta[m] + eps));
+        ws += w[m];
+    }
+    const T inv = hg_rcp(ws);
+    const T s0 = w[0] * inv * hg_rcp(g0);
+    const T ih = (T)P.cgeo[i], ih2 = ih * ih;
+    T c[10];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[1 + k] = s0 * a[k];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        T b[3];
+        sub_fit(m, b);
+        const T al = w[1 + m] * inv - s0 * gl;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c[1 + k] += al * b[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[1 + k] *= ih;
+    T dev = T(0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const T cq = s0 * a[3 + q];
+        dev -= cq * M[q];
+        c[4 + q] = cq * ih2;
+    }
+    if constexpr (!MIXED) {
+        c[0] = qi + dev;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            stg<d2>(reinterpret_cast<d2 *>(P.C) + (size_t)(v * 5 + k) * nc, i * 16u, d2{c[2 * k], c[2 * k + 1]});
+    } else {
+        c[0] = dev;                       // deviation from the FP64 cell mean
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            stg<f2>(reinterpret_cast<f2 *>(P.C32) + (size_t)(v * 5 + k) * nc, i * 8u, f2{c[2 * k], c[2 * k + 1]});
+    }
+}
+
+// The two sides of Gauss point g of face f in precision T: the left reconstruction,
+// and on the right the right cell's, or at a listed boundary face the ghost's (wall:
+// the momentum negated and the gradient reflected in the face's mean plane; far
+// field: the Riemann-invariant state of the left value for the point's normal, no
+// gradient).  Where a side is non-physical the point is first order (zero
+// gradients, cell averages for the non-physical sides; the ghost's average is the
+// ghost state of the left cell's).  Returns the point's normal and weight.
+template <class T, bool REC32>
+__device__ __forceinline__ void hex_point(const ProbDesc &P, int stage, uint32_t f, uint32_t g, T n[3], double &w,
+                                          T qL[5], T gL[5][3], T qR[5], T gR[5][3]) {
+    const uint32_t nf = (uint32_t)P.nf;
+    auto fg = [&](uint32_t k) { return P.fgeo[(size_t)k * nf + f]; };
+    T yl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        n[a] = (T)fg(7 * g + a);
+        yl[a] = (T)fg(7 * g + 4 + a);
+    }
+    w = fg(7 * g + 3);
+    const uint32_t l = (uint32_t)P.fcell[f];
+    const int32_t r = P.fcell[nf + f];
+    recon_point<T, false, REC32>(P, stage, l, yl, qL, gL);
+    T nm[3];
+    if (r >= 0) {
+        T yr[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) yr[a] = yl[a] + (T)fg(28 + a);
+        recon_point<T, false, REC32>(P, stage, (uint32_t)r, yr, qR, gR);
+    } else if (r == -HGKS_BC_WALL) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) nm[a] = (T)fg(31 + a);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T sg = (q >= 1 && q <= 3) ? T(-1) : T(1);
+            const T gn = gL[q][0] * nm[0] + gL[q][1] * nm[1] + gL[q][2] * nm[2];
+            qR[q] = sg * qL[q];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gR[q][a] = sg * (gL[q][a] - T(2) * gn * nm[a]);
+        }
+    } else {
+        farfield_state<T>(P, qL, n, qR);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gR[q][0] = gR[q][1] = gR[q][2] = T(0);
+    }
+    const bool okL = physical_point(qL), okR = physical_point(qR);
+    if (!(okL && okR)) {
+        T ml[5];
+        cell_mean<T>(P, stage, l, ml);
+        if (!okL)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) qL[q] = ml[q];
+        if (!okR) {
+            if (r >= 0) {
+                cell_mean<T>(P, stage, (uint32_t)r, qR);
+            } else if (r == -HGKS_BC_WALL) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) qR[q] = (q >= 1 && q <= 3) ? -ml[q] : ml[q];
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nm[a] = (T)fg(31 + a);
+                farfield_state<T>(P, ml, nm, qR);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gL[q][a] = gR[q][a] = T(0);
+    }
+}
+
+// Point flux of Gauss point g of face f in precision T (TM: tau mode), times the
+// point's weight.  With T = float a point whose sides differ by more than 30% in
+// density or pressure under tau > 0, or whose flux is not finite, is refused
+// (false) and evaluated in FP64 by the caller, as on tetrahedra.
+template <class T, bool REC32, int TM>
+__device__ __forceinline__ bool hex_point_flux(const ProbDesc &P, int stage, uint32_t f, uint32_t g, double Fo[5],
+                                               double dFo[5]) {
+    T n[3], qL[5], gL[5][3], qR[5], gR[5][3], F[5], dF[5];
+    double w;
+    hex_point<T, REC32>(P, stage, f, g, n, w, qL, gL, qR, gR);
+    if constexpr (sizeof(T) == 4 && TM != 0) {
+        const T gm1 = (T)P.gamma - T(1);
+        const T pL = gm1 * (qL[4] - T(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) / qL[0]);
+        const T pR = gm1 * (qR[4] - T(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) / qR[0]);
+        if (!(hg_abs(pL - pR) <= T(0.3) * (pL + pR) && hg_abs(qL[0] - qR[0]) <= T(0.3) * (qL[0] + qR[0]))) return false;
+    }
+    if constexpr (TM == 0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gL[q][a] += gR[q][a];
+        gks_flux_tau0<T>(qL, qR, gL, n, P, F, dF);
+    } else {
+        gks_flux_full<T, TM == 2>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+    }
+    if constexpr (sizeof(T) == 4)
+        if (!finite_flux(F, dF)) return false;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        Fo[k] = w * (double)F[k];
+        dFo[k] = w * (double)dF[k];
+    }
+    return true;
+}
+
+// Face flux on hexahedra: four consecutive lanes take the four Gauss points of a
+// face and sum their weighted fluxes across the lanes ((g0 + g1) + (g2 + g3)); the
+// first lane writes S-weighted (F, dF) to the per-face buffer.
+template <bool MIXED, int TM>
+__global__ __launch_bounds__(4 * HEX_FLUX_FACES) void k_flux_hex(const ProbDesc *__restrict__ probs,
+                                                                  const Tile *__restrict__ tiles, int stage) {
+    const Tile tl = tiles[blockIdx.x];
+    const ProbDesc &P = probs[tl.prob];
+    const uint32_t g = threadIdx.x & 3u;
+    const uint32_t f = (uint32_t)tl.begin + threadIdx.x / 4u;
+    const bool ok = f < (uint32_t)tl.end;
+    double Fo[5], dFo[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Fo[k] = dFo[k] = 0.0;
+    if (ok) {
+        bool done;
+        if constexpr (MIXED) done = hex_point_flux<float, true, TM>(P, stage, f, g, Fo, dFo);
+        else done = hex_point_flux<double, false, TM>(P, stage, f, g, Fo, dFo);
+        if constexpr (MIXED)
+            if (!done) hex_point_flux<double, true, TM>(P, stage, f, g, Fo, dFo);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        Fo[k] += __shfl_xor(Fo[k], 1);
+        Fo[k] += __shfl_xor(Fo[k], 2);
+        dFo[k] += __shfl_xor(dFo[k], 1);
+        dFo[k] += __shfl_xor(dFo[k], 2);
+    }
+    if (ok && g == 0) {
+        const uint32_t nf = (uint32_t)P.nf;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            P.FF[(size_t)k * nf + f] = Fo[k];
+            P.FF[(size_t)(5 + k) * nf + f] = dFo[k];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // launch wrappers
 // ----------------------------------------------------------------------------
 constexpr int WENO_CELLS = HGKS_WENO_CELLS;     // cells per WENO workgroup (16, 32 or 64)
@@ -1793,10 +2183,39 @@ void launch_flux(const ProbDesc *probs, int nprobs, const Tile *tiles, int ntile
 #undef HGKS_FLUX
 }
 
+void launch_hex_ghost(const ProbDesc *d, int ng, int stage, hipStream_t s) {
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(k_ghost_hex, dim3((ng + 255) / 256), dim3(256), 0, s, d, stage);
+}
+
+void launch_hex_weno(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (mixed) hipLaunchKernelGGL(k_weno_hex<true>, dim3(ntiles), dim3(5 * HEX_WENO_CELLS), 0, s, d, tiles, stage);
+    else hipLaunchKernelGGL(k_weno_hex<false>, dim3(ntiles), dim3(5 * HEX_WENO_CELLS), 0, s, d, tiles, stage);
+}
+
+void launch_hex_flux(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, int tau_mode,
+                     hipStream_t s) {
+    if (ntiles <= 0) return;
+    dim3 g(ntiles), b(4 * HEX_FLUX_FACES);
+#define HGKS_HF(M, TM) hipLaunchKernelGGL((k_flux_hex<M, TM>), g, b, 0, s, d, tiles, stage)
+    if (mixed) {
+        if (tau_mode == 0) HGKS_HF(true, 0); else if (tau_mode == 1) HGKS_HF(true, 1); else HGKS_HF(true, 2);
+    } else {
+        if (tau_mode == 0) HGKS_HF(false, 0); else if (tau_mode == 1) HGKS_HF(false, 1); else HGKS_HF(false, 2);
+    }
+#undef HGKS_HF
+}
+
 void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, bool s32,
-                   hipStream_t s) {
+                   hipStream_t s, int faces_per_cell) {
     if (ntiles <= 0) return;
     dim3 g(ntiles), b(UPD_TILE);
+    if (faces_per_cell == 6) {          // hexahedra: FP64 storage, per-face buffer
+        if (stage == 1) hipLaunchKernelGGL((k_update<1, false, false, 6>), g, b, 0, s, probs, tiles);
+        else hipLaunchKernelGGL((k_update<2, false, false, 6>), g, b, 0, s, probs, tiles);
+        return;
+    }
 #define HGKS_UPD(ST, CO, S) hipLaunchKernelGGL((k_update<ST, CO, S>), g, b, 0, s, probs, tiles)
     if (stage == 1) {
         if (s32) { if (coloured) HGKS_UPD(1, true, true); else HGKS_UPD(1, false, true); }

@@ -51,6 +51,8 @@ static void parallel_for(int64_t n, F &&f) {
     for (auto &x : th) x.join();
 }
 
+void parallel_range(int64_t n, const std::function<void(int64_t, int64_t)> &f) { parallel_for(n, f); }
+
 void pinv0_quads_f32(const HostMesh &hm, float *out) {
     const int64_t n = hm.nc;
     const double *p = hm.pinv0.data();
@@ -62,34 +64,7 @@ void pinv0_quads_f32(const HostMesh &hm, float *out) {
     });
 }
 
-namespace {
-
-struct V3 {
-    double x, y, z;
-};
-inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
-inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
-inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
-
-// A stencil member: cell id and, per axis, its placement: on a periodic axis the
-// image shift k (x + k * period), on a non-periodic axis 0 (the cell itself), -1 or
-// +1 (its mirror image in the low or high wall: 2 lo - x or 2 hi - x).
-struct Member {
-    int32_t cell;
-    int8_t s[3];
-    bool operator==(const Member &o) const {
-        return cell == o.cell && s[0] == o.s[0] && s[1] == o.s[1] && s[2] == o.s[2];
-    }
-};
-
-// Quadratic basis order: xx, yy, zz, xy, xz, yz (indices into a symmetric 3x3)
-constexpr int QA[6] = {0, 1, 2, 0, 0, 1};
-constexpr int QB[6] = {0, 1, 2, 1, 2, 2};
-
-// Pseudo-inverse of a full-column-rank m x n matrix (row-major, m <= 16, n <= 9) by
+// Pseudo-inverse of a full-column-rank m x n matrix (row-major, any m, n <= 9) by
 // the normal equations: P (n x m, row-major) = (A^T A)^{-1} A^T with a Cholesky
 // factor of A^T A (the least-squares fit the oracle solves the same way).  Returns
 // false when a pivot of the factor is negligible against the largest (rank
@@ -133,6 +108,33 @@ bool pinv_normal(int m, int n, const double *A, double *P) {
     }
     return true;
 }
+
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+// A stencil member: cell id and, per axis, its placement: on a periodic axis the
+// image shift k (x + k * period), on a non-periodic axis 0 (the cell itself), -1 or
+// +1 (its mirror image in the low or high wall: 2 lo - x or 2 hi - x).
+struct Member {
+    int32_t cell;
+    int8_t s[3];
+    bool operator==(const Member &o) const {
+        return cell == o.cell && s[0] == o.s[0] && s[1] == o.s[1] && s[2] == o.s[2];
+    }
+};
+
+// Quadratic basis order: xx, yy, zz, xy, xz, yz (indices into a symmetric 3x3)
+constexpr int QA[6] = {0, 1, 2, 0, 0, 1};
+constexpr int QB[6] = {0, 1, 2, 1, 2, 2};
 
 // Proper edge colouring of a graph with n vertices, edges (eu[e], ev[e]) and largest
 // degree at most 4 (faces of tetrahedra): colour[e] in [0, k), no two edges of one

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libhgks.so")
 OK, E_INVALID_ARG, E_BAD_MESH, E_STATE, E_OOM, E_DEVICE, E_NONPHYSICAL = range(7)
 FP64, FP32_MIXED, FP32 = 0, 1, 2
 ACC_GATHER, ACC_COLOURED = 0, 1
+BC_WALL, BC_FAR = 1, 2
 KERNEL_IDS = {"dt": 0, "weno": 1, "flux": 2, "update": 3}
 
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_MESH", 3: "STATE", 4: "OOM", 5: "DEVICE", 6: "NONPHYSICAL"}
@@ -32,7 +33,8 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("tau_mode", C.c_int),
                 ("tau_eps", C.c_double), ("tau_C", C.c_double), ("weno_eps", C.c_double),
                 ("gamma_lin", C.c_double), ("precision", C.c_int), ("accumulation", C.c_int),
-                ("reorder", C.c_int)]
+                ("reorder", C.c_int), ("mu_ref", C.c_double), ("T_ref", C.c_double), ("mu_exp", C.c_double),
+                ("prandtl", C.c_double), ("farfield", C.c_double * 5)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -89,7 +91,10 @@ def params(**kw) -> Params:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise AttributeError(k)
-        setattr(p, k, v)
+        if k == "farfield":
+            p.farfield[:] = tuple(float(x) for x in v)
+        else:
+            setattr(p, k, v)
     return p
 
 
@@ -139,14 +144,29 @@ class Solver:
     def __del__(self):
         self.close()
 
-    def mesh_upload(self, nodes, cell_nodes, period=(0.0, 0.0, 0.0)):
+    def mesh_upload(self, nodes, cell_nodes, period=(0.0, 0.0, 0.0), bfaces=None, bkinds=None):
+        """cell_nodes [n, 4] (tetrahedra) or [n, 8] (hexahedra); bfaces [nb, 4] node ids
+        of listed boundary faces with bkinds [nb] (BC_WALL / BC_FAR), hexahedra only."""
         nodes = _f64(nodes)
         cells = np.ascontiguousarray(cell_nodes, dtype=np.int64)
         per = _f64(period)
+        if bfaces is None:
+            nb, bf, bk = 0, None, None
+        else:
+            bf_a = np.ascontiguousarray(bfaces, dtype=np.int64)
+            bk_a = np.ascontiguousarray(bkinds, dtype=np.int32)
+            if bk_a.shape[0] != bf_a.shape[0]:
+                raise ValueError("one kind per boundary face")
+            nb, bf, bk = bf_a.shape[0], bf_a.ctypes.data_as(_i64p), bk_a.ctypes.data_as(_i32p)
         self._check(lib().hgks_mesh_upload(self._h, nodes.shape[0], nodes.ctypes.data_as(_dp), cells.shape[0],
                                            cells.shape[1], cells.ctypes.data_as(_i64p), per.ctypes.data_as(_dp),
-                                           0, None, None))
+                                           nb, bf, bk))
         self.n_cells = cells.shape[0]
+
+    def upload(self, mesh):
+        """mesh_upload of a workload mesh (nodes, cell_nodes, period, listed boundary faces)."""
+        self.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period, getattr(mesh, "bfaces", None),
+                         getattr(mesh, "bkinds", None))
 
     def init_state(self, q, t0: float = 0.0):
         q = _f64(q)
@@ -205,10 +225,20 @@ def inspect_mesh(nodes, cell_nodes, period=(0.0, 0.0, 0.0), prm: Params | None =
     nc = cells.shape[0]
     stats = np.zeros(8)
     perm = np.empty(nc, dtype=np.int64)
-    sten = np.empty((16, nc), dtype=np.int32)
-    st = lib().hgks_inspect_mesh(C.byref(prm) if prm is not None else None, nodes.shape[0], nodes.ctypes.data_as(_dp),
-                                 nc, cells.shape[1], cells.ctypes.data_as(_i64p), per.ctypes.data_as(_dp),
-                                 stats.ctypes.data_as(_dp), perm.ctypes.data_as(_i64p), sten.ctypes.data_as(_i32p))
+
+    def call(sten):
+        return lib().hgks_inspect_mesh(C.byref(prm) if prm is not None else None, nodes.shape[0],
+                                       nodes.ctypes.data_as(_dp), nc, cells.shape[1], cells.ctypes.data_as(_i64p),
+                                       per.ctypes.data_as(_dp), stats.ctypes.data_as(_dp), perm.ctypes.data_as(_i64p),
+                                       sten.ctypes.data_as(_i32p) if sten is not None else None)
+    if cells.shape[1] == 8:
+        st = call(None)                    # the slot count first
+        sten = np.empty((int(stats[1]) if st == OK else 0, nc), dtype=np.int32)
+        if st == OK:
+            st = call(sten)
+    else:
+        sten = np.empty((16, nc), dtype=np.int32)
+        st = call(sten)
     if st != OK:
         raise HGKSError(st, "hgks_inspect_mesh failed")
     keys = ["n_faces", "slots", "max_members", "min_members", "n_colours", "pinv_residual", "closure", "dup_slots"]

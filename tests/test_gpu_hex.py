@@ -1,0 +1,203 @@
+"""GPU parity on hexahedral meshes (Sec. 2.3 hexahedral stencils, Sec. 5.2 viscous
+flow past a sphere): the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars as for tetrahedra: the FP64 path within 1e-12 (per conserved variable,
+scaled as in helpers.scaled_err) after each step from an identical state, the
+FP32-mixed form within 1e-5 relative L1 after the run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2407_00656_amd import hgks
+from paper_2407_00656_amd import workloads as W
+from tests.helpers import rel_l1_scaled, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sphere_params(case, **kw):
+    base = dict(tau_mode=2, mu_ref=case.mu_inf(), T_ref=case.t_inf(), mu_exp=0.7, prandtl=case.prandtl,
+                farfield=case.freestream())
+    base.update(kw)
+    return base
+
+
+def oracle_params(**kw):
+    keep = ("tau_mode", "tau_eps", "tau_C", "weno_eps", "gamma_lin", "cfl", "mu_ref", "T_ref", "mu_exp", "prandtl",
+            "farfield")
+    return O.default_params(**{k: v for k, v in kw.items() if k in keep})
+
+
+def solver(mesh, q, **kw):
+    s = hgks.Solver(hgks.params(**kw))
+    s.upload(mesh)
+    s.init_state(q)
+    return s
+
+
+def per_step(mesh, q0, nsteps, **kw):
+    om = O.Mesh.from_workload(mesh)
+    op = oracle_params(**kw)
+    s = solver(mesh, q0, **kw)
+    worst = np.zeros(5)
+    q = q0
+    for k in range(nsteps):
+        dt_gpu = s.step(1, want_dt=True)
+        q_gpu, _ = s.get_state()
+        q_orc, dt_orc = om.step(q, 1, params=op)
+        assert abs(dt_gpu - dt_orc) <= 1e-14 * dt_orc, (k, dt_gpu, dt_orc)
+        e = scaled_err(q_gpu, q_orc)
+        worst = np.maximum(worst, e)
+        assert np.all(e <= TOL64), (k, e)
+        q = q_gpu
+    s.close()
+    return worst
+
+
+def smooth_hex_state(mesh, amp=0.15, k=(1, 2, 1), vel=(0.8, -0.3, 0.5)):
+    return W.AdvectionCase(amp=amp, k=k, vel=vel).conservative(mesh)
+
+
+def bumped_freestream(mesh, case, amp=0.05):
+    """The free stream with a smooth density and pressure bump near the sphere, so
+    that every term of the viscous flux sees gradients."""
+    q = case.conservative(mesh)
+    c = mesh.cell_vertices.mean(axis=1)
+    r = np.linalg.norm(c - np.array([0.8, 0.0, 0.0]), axis=1)
+    bump = 1.0 + amp * np.exp(-(r / 0.6) ** 2)
+    rho = q[:, 0] * bump
+    u = q[:, 1:4] / q[:, :1]
+    p = (case.gamma - 1) * (q[:, 4] - 0.5 * q[:, 0] * np.sum(u * u, axis=1)) * bump ** 1.2
+    out = np.empty_like(q)
+    out[:, 0] = rho
+    out[:, 1:4] = rho[:, None] * u
+    out[:, 4] = p / (case.gamma - 1) + 0.5 * rho * np.sum(u * u, axis=1)
+    return out
+
+
+@pytest.mark.parametrize("n,jitter", [(6, 0.15), (7, 0.1)])
+def test_hex_box_fp64_every_step(n, jitter):
+    """Jittered periodic hex boxes (216 and 343 cells: ragged last tiles), smooth
+    data, tau = 0, three steps each matched."""
+    say(f"case: hex box N={n} tau0 fp64")
+    mesh = W.hex_box(n, jitter=jitter)
+    worst = per_step(mesh, smooth_hex_state(mesh), 3)
+    say("worst", worst)
+
+
+def test_hex_box_fp64_tau_positive():
+    say("case: hex box N=6 tau_mode 1 fp64")
+    mesh = W.hex_box(6, jitter=0.15)
+    per_step(mesh, smooth_hex_state(mesh), 2, tau_mode=1)
+
+
+def test_hex_box_conservation():
+    """Totals on the periodic hex box stay put to rounding over ten steps."""
+    say("case: hex box conservation")
+    mesh = W.hex_box(6, jitter=0.15)
+    q0 = smooth_hex_state(mesh)
+    vol = W.hex_volumes(mesh.cell_vertices)
+    s = solver(mesh, q0)
+    s.step(10)
+    q, _ = s.get_state()
+    s.close()
+    assert np.all(np.abs((q - q0).T @ vol) <= 1e-12 * np.abs(q0).T @ vol)
+
+
+@pytest.mark.parametrize("prandtl", [1.0, 0.72])
+def test_sphere_viscous_fp64_every_step(prandtl):
+    """A small cubed-sphere O-grid (6*4*4 cells by 8 layers), viscous collision time with
+    mu ~ T^0.7, no-slip wall and far field, three steps each matched."""
+    say(f"case: sphere N=4 L=8 viscous Pr={prandtl} fp64")
+    case = W.SphereCase()
+    mesh = W.cubed_sphere(4, 8)
+    q0 = bumped_freestream(mesh, case)
+    worst = per_step(mesh, q0, 3, **sphere_params(case, prandtl=prandtl))
+    say("worst", worst)
+
+
+def test_sphere_fp32_mixed_run():
+    """The FP32-mixed form on the small O-grid after 20 viscous steps: within 1e-5
+    relative L1 (per variable, momentum against a momentum scale) of the oracle."""
+    say("case: sphere N=4 L=8 viscous fp32-mixed 20 steps")
+    case = W.SphereCase()
+    mesh = W.cubed_sphere(4, 8)
+    q0 = bumped_freestream(mesh, case)
+    kw = sphere_params(case)
+    s = solver(mesh, q0, precision=hgks.FP32_MIXED, **kw)
+    s.step(20)
+    q, _ = s.get_state()
+    s.close()
+    om = O.Mesh.from_workload(mesh)
+    q_orc = q0
+    for _ in range(20):           # the oracle takes its own CFL steps from its own state
+        q_orc, _ = om.step(q_orc, 1, params=oracle_params(**kw))
+    err = rel_l1_scaled(q, q_orc, W.hex_volumes(mesh.cell_vertices))
+    say("rel L1", err)
+    assert np.all(err < TOL32), err
+
+
+def test_hex_box_fp32_mixed_run():
+    say("case: hex box N=6 fp32-mixed 20 steps")
+    mesh = W.hex_box(6, jitter=0.15)
+    q0 = smooth_hex_state(mesh)
+    s = solver(mesh, q0, precision=hgks.FP32_MIXED)
+    s.step(20)
+    q, _ = s.get_state()
+    s.close()
+    q_orc, _ = O.Mesh.from_workload(mesh).step(q0, 20)
+    err = rel_l1_scaled(q, q_orc, W.hex_volumes(mesh.cell_vertices))
+    say("rel L1", err)
+    assert np.all(err < TOL32), err
+
+
+def test_sphere_full_size_sampled_step():
+    """The sphere workload itself (6*48*48 cells by 64 layers, 884,736 hexes): one
+    viscous FP64 step, 64 sampled cells (wall, far field and interior) against the
+    oracle's step of those cells from the same state."""
+    say("case: sphere N=48 L=64 sampled step fp64")
+    case = W.SphereCase()
+    mesh = W.cubed_sphere(48, 64)
+    q0 = bumped_freestream(mesh, case)
+    kw = sphere_params(case)
+    s = solver(mesh, q0, **kw)
+    dt = s.step(1, want_dt=True)
+    q, _ = s.get_state()
+    s.close()
+    say("gpu step done", dt)
+    rng = np.random.default_rng(7)
+    layers = 64
+    k = np.arange(mesh.n_cells) % layers
+    cells = np.concatenate([rng.choice(np.flatnonzero(k == 0), 24, replace=False),
+                            rng.choice(np.flatnonzero(k == layers - 1), 16, replace=False),
+                            rng.choice(mesh.n_cells, 24, replace=False)])
+    om = O.Mesh.from_workload(mesh)
+    ref = om.step_sample(q0, dt, cells, params=oracle_params(**kw))
+    e = scaled_err(q[cells], ref)
+    say("sampled worst", e)
+    assert np.all(e <= TOL64), e
+
+
+def test_hex_rejects_what_it_does_not_take():
+    mesh = W.hex_box(5, jitter=0.0)
+    for kw in (dict(precision=hgks.FP32), dict(accumulation=hgks.ACC_COLOURED)):
+        s = hgks.Solver(hgks.params(**kw))
+        with pytest.raises(hgks.HGKSError):
+            s.upload(mesh)
+        s.close()
+    tets = W.kuhn_box(5)
+    s = hgks.Solver(hgks.params(tau_mode=2, mu_ref=1e-3))
+    with pytest.raises(hgks.HGKSError):
+        s.upload(tets)
+    s.close()

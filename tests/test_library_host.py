@@ -95,8 +95,11 @@ def test_bad_meshes_are_rejected():
     with pytest.raises(hgks.HGKSError) as e:             # wrapped cells without their period
         hgks.inspect_mesh(m.nodes, m.cell_nodes, (0.0, 0.0, 0.0))
     assert e.value.status == hgks.E_BAD_MESH
-    with pytest.raises(hgks.HGKSError) as e:             # hexahedra are not supported
+    with pytest.raises(hgks.HGKSError) as e:             # degenerate hexahedra (all nodes one point)
         hgks.inspect_mesh(m.nodes, np.zeros((4, 8), dtype=np.int64), m.period)
+    assert e.value.status == hgks.E_BAD_MESH
+    with pytest.raises(hgks.HGKSError) as e:             # neither tetrahedra nor hexahedra
+        hgks.inspect_mesh(m.nodes, np.zeros((4, 6), dtype=np.int64), m.period)
     assert e.value.status == hgks.E_INVALID_ARG
     bad = m.cell_nodes.copy()
     bad[5, 1] = m.n_nodes + 3
@@ -128,3 +131,33 @@ def test_footprint_by_precision():
     assert f[hgks.FP32] < 0.53 * f[hgks.FP64]          # about half the memory of FP64
     with pytest.raises(hgks.HGKSError):
         hgks.pool_footprint(hgks.params(precision=3), nc)
+
+
+@pytest.mark.parametrize("n,jitter", [(5, 0.2), (6, 0.0)])
+def test_hex_precompute_matches_oracle(n, jitter):
+    """Hexahedral boxes: the host precompute's faces, its big stencils (as sets of
+    caller cells, the six face neighbours first in face order) and its pseudo-inverse
+    agree with the oracle's independent construction; the bilinear faces close."""
+    m = W.hex_box(n, jitter=jitter)
+    r = hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period)
+    st = r["stats"]
+    om = O.Mesh.from_workload(m)
+    assert st["n_faces"] == om.nf == 3 * m.n_cells
+    assert st["slots"] == 24 and st["max_members"] == 24 and st["min_members"] == 24
+    assert st["pinv_residual"] < 1e-12 and st["closure"] < 1e-14
+    perm, sten = r["perm"], r["sten"]
+    nb = om.neighbors()
+    for c in range(0, m.n_cells, 7):
+        i = perm[c]
+        members = perm[sten[:, c]]
+        assert list(members[:6]) == list(nb[i])
+        mem, _, _ = om.stencil(i)
+        assert set(members.tolist()) == set(mem.tolist())
+
+
+def test_hex_meshes_need_their_boundary_faces_listed():
+    """A non-periodic hex box has unshared faces: without a boundary-face list the
+    precompute refuses it (hexahedral meshes have no axis walls)."""
+    m = W.hex_box(5, periodic=(False, True, True))
+    with pytest.raises(hgks.HGKSError):
+        hgks.inspect_mesh(m.nodes, m.cell_nodes, m.period)
