@@ -106,3 +106,37 @@ def test_config2_order_study(jitter, eps):
         assert all(2.85 <= o <= 3.15 for o in orders), orders
     else:
         assert all(2.8 <= o <= 3.15 for o in orders), orders
+
+
+@pytest.mark.parametrize("weno_eps,lo", [(1.0, 2.85), (1e-8, 1.8)])
+def test_hex_order_on_the_gpu(weno_eps, lo):
+    """Hexahedral boxes N = 16, 24, 32 without jitter, T = 0.05, dt = T / (0.75 N):
+    with near-linear weights the L1 density error falls at third order (the oracle
+    measures 2.86 and 2.91 at N = 12/16/24); with the default WENO-Z epsilon the
+    weights leave the linear ones at the extrema and the observed order on these
+    meshes is lower (reported, bounded below by 1.8).  FP32-mixed stays within 1e-5
+    relative L1 of FP64."""
+    case = W.AdvectionCase()
+    T = 0.05
+    res = []
+    for n in (16, 24, 32):
+        mesh = W.hex_box(n, jitter=0.0)
+        q0 = case.conservative(mesh)
+        steps = int(round(0.75 * n))
+        out = {}
+        for prec in (hgks.FP64, hgks.FP32_MIXED):
+            s = hgks.Solver(hgks.params(precision=prec, weno_eps=weno_eps))
+            s.upload(mesh)
+            s.init_state(q0)
+            s.step(steps, dt_fixed=T / steps)
+            out[prec], _ = s.get_state()
+            s.close()
+        vol = W.hex_volumes(mesh.cell_vertices)
+        e = W.error_norms(vol, out[hgks.FP64][:, 0], case.density_average(mesh, T))
+        d = rel_l1_scaled(out[hgks.FP32_MIXED], out[hgks.FP64], vol)
+        say(f"hex N={n} eps={weno_eps}: L1 {e['L1']:.4e} Linf {e['Linf']:.4e}; FP32-mixed vs FP64 {d.max():.2e}")
+        assert np.all(d < 1e-5)
+        res.append((n, e["L1"]))
+    orders = [math.log(a[1] / b[1]) / math.log(b[0] / a[0]) for a, b in zip(res, res[1:])]
+    say("hex orders", orders)
+    assert all(lo <= o <= 3.2 for o in orders), orders
