@@ -841,7 +841,7 @@ __device__ __forceinline__ void second_moment_jvp(const T n[3], const T U[3], T 
 template <class T, bool WMOM = false>
 __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], const T n[3], const T t1[3],
                                              const T t2[3], T h0, T h1, T K, T gam, T Kp3, T c4k, T e0[5], T e1[5],
-                                             T e2[5], T w0[5] = nullptr, T w1[5] = nullptr, T w2[5] = nullptr) {
+                                             T e2[5], const T *u0l = nullptr, T h2 = T(0), T *sw = nullptr) {
     const State<T> s = make_state(Qf, gam, Kp3, c4k);
     const T *e[3] = {n, t1, t2};
     const T u[3] = {s.U, s.V, s.W};
@@ -883,21 +883,26 @@ __device__ __forceinline__ void initial_part(const T Qf[5], const T g[5][3], con
     for (int k = 0; k < 5; ++k) e1[k] += t[k];
     apsi<T, 1, 0, 0>(M, A, e2);
     if constexpr (WMOM) {
-        // the same three pieces without the factor u: the conserved moments
-        //   w0 = <psi>,  w1 = sum_j <u_j (a_j.psi) psi>,  w2 = <(A.psi) psi>
-        w0[0] = M.u[0];
-        w0[1] = M.u[1];
-        w0[2] = M.u[0] * M.v[1];
-        w0[3] = M.u[0] * M.w[1];
-        w0[4] = T(0.5) * (M.u[2] + M.u[0] * (M.v[2] + M.w[2] + M.xi2));
-        apsi<T, 1, 0, 0>(M, a[0], w1);
-        apsi<T, 0, 1, 0>(M, a[1], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) w1[k] += t[k];
-        apsi<T, 0, 0, 1>(M, a[2], t);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) w1[k] += t[k];
-        apsi<T, 0, 0, 0>(M, A, w2);
+        // the same three pieces without the factor u, the conserved moments
+        //   w0 = <psi>,  w1 = sum_j <u_j (a_j.psi) psi>,  w2 = <(A.psi) psi>,
+        // each contracted at once to w_E - U0.w_m + |U0|^2/2 w_rho (U0 in this frame:
+        // u0l), the only combination the heat flux takes
+        auto con = [&](const T w[5]) { return w[4] - (u0l[0] * w[1] + u0l[1] * w[2] + u0l[2] * w[3]) + h2 * w[0]; };
+        T w[5];
+        w[0] = M.u[0];
+        w[1] = M.u[1];
+        w[2] = M.u[0] * M.v[1];
+        w[3] = M.u[0] * M.w[1];
+        w[4] = T(0.5) * (M.u[2] + M.u[0] * (M.v[2] + M.w[2] + M.xi2));
+        sw[0] = con(w);
+        apsi<T, 1, 0, 0>(M, a[0], w);
+        sw[1] = con(w);
+        apsi<T, 0, 1, 0>(M, a[1], w);
+        sw[1] += con(w);
+        apsi<T, 0, 0, 1>(M, a[2], w);
+        sw[1] += con(w);
+        apsi<T, 0, 0, 0>(M, A, w);
+        sw[2] = con(w);
     }
 }
 
@@ -943,8 +948,8 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
     // time-integral weights: F = (4 I(dt/2) - I(dt)) / dt, dF = 4 (I(dt) - 2 I(dt/2)) / dt^2
     T tau = T(0);
     if (P.tau_mode == 1) tau = (T)P.tau_eps * dt + (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
-    if constexpr (VISC)
-        tau = (T)P.mu_ref * hg_pow(p0 * ir0 / (T)P.T_ref, (T)P.mu_exp) / p0 +
+    if constexpr (VISC)   // mu_ref (T0/T_ref)^mu_exp as exp(mu_exp log(T0/T_ref)): no library call
+        tau = (T)P.mu_ref * hg_exp((T)P.mu_exp * log(p0 * ir0 / (T)P.T_ref)) / p0 +
               (T)P.tau_C * hg_abs(pl - pr) / (pl + pr) * dt;
     T q1[6], qh[6], cF[6], cD[6];
     const T Eh = tau > T(0) ? hg_exp(T(-0.5) * dt / tau) : T(0);
@@ -985,37 +990,48 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
         F[k] = cF[0] * Fe[k] + cF[1] * Se[k] + cF[2] * Ft[k];
         dF[k] = cD[0] * Fe[k] + cD[1] * Se[k] + cD[2] * Ft[k];
     }
+    const T h2 = T(0.5) * u20;
+    T SW = T(0), dSW = T(0);
+    if constexpr (VISC) {
+        // the equilibrium part's conserved moments for the heat flux: Q0, and Q_t through
+        // the slope and time terms (the u_j-weighted slope term integrates to -Q_t),
+        // contracted here so that Q0 and Q_t need not stay live
+        auto con = [&](T r, T m0, T m1, T m2, T e) { return e - (u0[0] * m0 + u0[1] * m1 + u0[2] * m2) + h2 * r; };
+        const T cq0 = con(rho0, mom0[0], mom0[1], mom0[2], E0), cqt = con(Qt[0], Qt[1], Qt[2], Qt[3], Qt[4]);
+        SW = cF[0] * cq0 + (cF[2] - cF[1]) * cqt;
+        dSW = cD[0] * cq0 + (cD[2] - cD[1]) * cqt;
+    }
     // initial parts, local frame
     T t1[3], t2[3];
     frame(n, t1, t2);
-    const bool heat = VISC && P.prandtl != 1.0;
-    T Fl[5], dFl[5], Wl[5], dWl[5];
+    const T u0l[3] = {un0, u0[0] * t1[0] + u0[1] * t1[1] + u0[2] * t1[2], u0[0] * t2[0] + u0[1] * t2[1] + u0[2] * t2[2]};
+    T Fl[5], dFl[5];
     {
-        T Qf[5], e0[5], e1[5], e2[5], w0[5], w1[5], w2[5];
+        T Qf[5], e0[5], e1[5], e2[5], sw[3];
         rot_in(ql, n, t1, t2, Qf);
-        initial_part<T, VISC>(Qf, gl, n, t1, t2, ml[0], ml[1], K, gam, Kp3, c4k, e0, e1, e2, w0, w1, w2);
+        initial_part<T, VISC>(Qf, gl, n, t1, t2, ml[0], ml[1], K, gam, Kp3, c4k, e0, e1, e2, u0l, h2, sw);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             Fl[k] = sl.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
             dFl[k] = sl.rho * (cD[3] * e0[k] + cD[4] * e1[k] + cD[5] * e2[k]);
-            if constexpr (VISC) {
-                Wl[k] = sl.rho * (cF[3] * w0[k] + cF[4] * w1[k] + cF[5] * w2[k]);
-                dWl[k] = sl.rho * (cD[3] * w0[k] + cD[4] * w1[k] + cD[5] * w2[k]);
-            }
+        }
+        if constexpr (VISC) {
+            SW += sl.rho * (cF[3] * sw[0] + cF[4] * sw[1] + cF[5] * sw[2]);
+            dSW += sl.rho * (cD[3] * sw[0] + cD[4] * sw[1] + cD[5] * sw[2]);
         }
     }
     {
-        T Qf[5], e0[5], e1[5], e2[5], w0[5], w1[5], w2[5];
+        T Qf[5], e0[5], e1[5], e2[5], sw[3];
         rot_in(qr, n, t1, t2, Qf);
-        initial_part<T, VISC>(Qf, gr, n, t1, t2, mr[0], mr[1], K, gam, Kp3, c4k, e0, e1, e2, w0, w1, w2);
+        initial_part<T, VISC>(Qf, gr, n, t1, t2, mr[0], mr[1], K, gam, Kp3, c4k, e0, e1, e2, u0l, h2, sw);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             Fl[k] += sr.rho * (cF[3] * e0[k] + cF[4] * e1[k] + cF[5] * e2[k]);
             dFl[k] += sr.rho * (cD[3] * e0[k] + cD[4] * e1[k] + cD[5] * e2[k]);
-            if constexpr (VISC) {
-                Wl[k] += sr.rho * (cF[3] * w0[k] + cF[4] * w1[k] + cF[5] * w2[k]);
-                dWl[k] += sr.rho * (cD[3] * w0[k] + cD[4] * w1[k] + cD[5] * w2[k]);
-            }
+        }
+        if constexpr (VISC) {
+            SW += sr.rho * (cF[3] * sw[0] + cF[4] * sw[1] + cF[5] * sw[2]);
+            dSW += sr.rho * (cD[3] * sw[0] + cD[4] * sw[1] + cD[5] * sw[2]);
         }
     }
     T Fg[5], dFg[5];
@@ -1027,21 +1043,9 @@ __device__ __forceinline__ void gks_flux_full(const T ql[5], const T gl[5][3], c
         dF[k] += dFg[k];
     }
     if constexpr (VISC) {
-        if (heat) {
-            T W[5], dW[5];
-            rot_out(Wl, n, t1, t2, W);
-            rot_out(dWl, n, t1, t2, dW);
-            const T Q0[5] = {rho0, mom0[0], mom0[1], mom0[2], E0};
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                W[k] += cF[0] * Q0[k] + (cF[2] - cF[1]) * Qt[k];
-                dW[k] += cD[0] * Q0[k] + (cD[2] - cD[1]) * Qt[k];
-            }
-            const T h2 = T(0.5) * u20;
-            const T qh = F[4] - (u0[0] * F[1] + u0[1] * F[2] + u0[2] * F[3]) + h2 * F[0] -
-                         un0 * (W[4] - (u0[0] * W[1] + u0[1] * W[2] + u0[2] * W[3]) + h2 * W[0]);
-            const T dqh = dF[4] - (u0[0] * dF[1] + u0[1] * dF[2] + u0[2] * dF[3]) + h2 * dF[0] -
-                          un0 * (dW[4] - (u0[0] * dW[1] + u0[1] * dW[2] + u0[2] * dW[3]) + h2 * dW[0]);
+        if (P.prandtl != 1.0) {
+            const T qh = F[4] - (u0[0] * F[1] + u0[1] * F[2] + u0[2] * F[3]) + h2 * F[0] - un0 * SW;
+            const T dqh = dF[4] - (u0[0] * dF[1] + u0[1] * dF[2] + u0[2] * dF[3]) + h2 * dF[0] - un0 * dSW;
             const T cpr = T(1) / (T)P.prandtl - T(1);
             F[4] += cpr * qh;
             dF[4] += cpr * dqh;
@@ -1838,60 +1842,109 @@ __global__ __launch_bounds__(256) void k_ghost_hex(const ProbDesc *__restrict__ 
 }
 
 // WENO on hexahedra (Sec. 2.3, M = 8): wave v of a workgroup forms variable v of its
-// 64 cells, one lane a cell.  The big-stencil fit a = P (Q_k - Q_i) streams the
-// pseudo-inverse once (each of its rows is read by the five waves of the workgroup,
-// four of them from cache); the eight linear fits of the exactly determined
+// 64 cells, one lane a cell.  The big-stencil fit a = P (Q_k - Q_i) takes the
+// pseudo-inverse through LDS in chunks of six slots: the workgroup's 320 threads
+// copy a chunk's rows once (coalesced, each value read from HBM once), and the five
+// waves read it from there.  The eight linear fits of the exactly determined
 // sub-stencils {i, i_a, i_b, i_c} use their precomputed 3x3 inverses on the first
-// six slots (the face neighbours in face order); the smoothness indicators, WENO-Z
-// weights (gamma_0 = 1 - 8 gamma) and the combined polynomial follow the tetrahedral
-// kernel, and the record layout is the same, so the flux reads it alike.
+// six slots (the face neighbours in face order) and stay in registers; the
+// smoothness indicators, WENO-Z weights (gamma_0 = 1 - 8 gamma) and the combined
+// polynomial follow the tetrahedral kernel, and the record layout is the same, so
+// the flux reads it alike.
+constexpr int HEX_PCHUNK = 6;
+
 template <bool MIXED>
 __global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc *__restrict__ probs,
                                                                   const Tile *__restrict__ tiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
+    __shared__ double sp[HEX_PCHUNK * 9][HEX_WENO_CELLS];
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
     const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / HEX_WENO_CELLS));
-    const uint32_t i = (uint32_t)tl.begin + threadIdx.x % HEX_WENO_CELLS;
-    if (i >= (uint32_t)tl.end) return;
+    const uint32_t lane = threadIdx.x % HEX_WENO_CELLS;
+    const uint32_t i = (uint32_t)tl.begin + lane;
+    const uint32_t ncell = (uint32_t)(tl.end - tl.begin);
+    const bool act = lane < ncell;
     const uint32_t nc = (uint32_t)P.nc, ng = (uint32_t)P.ng;
     const int ns = P.ns;
     const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)v * nc;
     const double *Gv = P.G + (size_t)v * ng;
-    const double qi = Qv[i];
+    const double qi = act ? Qv[i] : 0.0;
     auto member = [&](int s) {
         const uint32_t id = (uint32_t)P.sten[(size_t)s * nc + i];
         return (id < nc ? Qv[id] : Gv[id - nc]) - qi;
     };
+    // copy rows r of slots s0 .. s0 + cnt - 1 of the tile's cells into sp[(s - s0) 9 + r]
+    auto stage_chunk = [&](int s0, int cnt) {
+        for (uint32_t e = threadIdx.x; e < (uint32_t)(cnt * 9 * HEX_WENO_CELLS); e += 5 * HEX_WENO_CELLS) {
+            const uint32_t c = e % HEX_WENO_CELLS, rs = e / HEX_WENO_CELLS;
+            const uint32_t sl = rs / 9u, r = rs % 9u;
+            sp[rs][c] = c < ncell ? P.hpinv[((size_t)r * ns + s0 + sl) * nc + tl.begin + c] : 0.0;
+        }
+    };
     double a64[9], d6[6];
 #pragma unroll
     for (int r = 0; r < 9; ++r) a64[r] = 0.0;
+    stage_chunk(0, HEX_PCHUNK);          // the first chunk: the six face neighbours
+    __syncthreads();
+    if (act) {
+        if constexpr (MIXED) {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        d6[s] = member(s);
+            for (int s = 0; s < 6; ++s) d6[s] = member(s);
+        }
 #pragma unroll
-        for (int r = 0; r < 9; ++r) a64[r] = fma(P.hpinv[((size_t)r * ns + s) * nc + i], d6[s], a64[r]);
+        for (int s = 0; s < 6; ++s) {
+            if constexpr (!MIXED) d6[s] = member(s);
+#pragma unroll
+            for (int r = 0; r < 9; ++r) a64[r] = fma(sp[s * 9 + r][lane], d6[s], a64[r]);
+        }
     }
-    for (int s = 6; s < ns; ++s) {
-        const double d = member(s);
+    for (int s0 = HEX_PCHUNK; s0 < ns; s0 += HEX_PCHUNK) {
+        const int cnt = min(HEX_PCHUNK, ns - s0);
+        __syncthreads();                  // the previous chunk is consumed
+        stage_chunk(s0, cnt);
+        __syncthreads();
+        if (act && !MIXED) {
+            for (int sl = 0; sl < cnt; ++sl) {
+                const double d = member(s0 + sl);
 #pragma unroll
-        for (int r = 0; r < 9; ++r) a64[r] = fma(P.hpinv[((size_t)r * ns + s) * nc + i], d, a64[r]);
+                for (int r = 0; r < 9; ++r) a64[r] = fma(sp[sl * 9 + r][lane], d, a64[r]);
+            }
+        } else if (act) {
+            // FP32-mixed (fewer registers): all of the chunk's gathers first (ids, then
+            // values), then the products; in FP64 the extra registers cost a wave per
+            // SIMD and more than the early gathers gain
+            uint32_t id[HEX_PCHUNK];
+            double d[HEX_PCHUNK];
+#pragma unroll
+            for (int sl = 0; sl < HEX_PCHUNK; ++sl)
+                id[sl] = sl < cnt ? (uint32_t)P.sten[(size_t)(s0 + sl) * nc + i] : i;
+#pragma unroll
+            for (int sl = 0; sl < HEX_PCHUNK; ++sl) d[sl] = (id[sl] < nc ? Qv[id[sl]] : Gv[id[sl] - nc]) - qi;
+#pragma unroll
+            for (int sl = 0; sl < HEX_PCHUNK; ++sl)
+                if (sl < cnt)
+#pragma unroll
+                    for (int r = 0; r < 9; ++r) a64[r] = fma(sp[sl * 9 + r][lane], d[sl], a64[r]);
+        }
     }
+    if (!act) return;
     T a[9], M[6];
 #pragma unroll
     for (int r = 0; r < 9; ++r) a[r] = (T)a64[r];
 #pragma unroll
     for (int q = 0; q < 6; ++q) M[q] = (T)P.cgeo[(size_t)(1 + q) * nc + i];
     const double *B = P.hbinv + i;
-    auto sub_fit = [&](int m, T b[3]) {
+    T b[8][3];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double s = 0.0;
+            double t = 0.0;
 #pragma unroll
-            for (int t = 0; t < 3; ++t) s = fma(B[(size_t)((m * 3 + k) * 3 + t) * nc], d6[HEXSUB[m][t]], s);
-            b[k] = (T)s;
+            for (int u = 0; u < 3; ++u) t = fma(B[(size_t)((m * 3 + k) * 3 + u) * nc], d6[HEXSUB[m][u]], t);
+            b[m][k] = (T)t;
         }
-    };
     // smoothness indicators in scaled coordinates (mean over the cell of the squared
     // first derivatives, plus the squared second derivatives of P0)
     T beta[9];
@@ -1899,11 +1952,7 @@ __global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc 
               a[2] * a[2] + quad_form(M, a[7], a[8], T(2) * a[5]) +
               T(4) * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]) + a[6] * a[6] + a[7] * a[7] + a[8] * a[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        T b[3];
-        sub_fit(m, b);
-        beta[1 + m] = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-    }
+    for (int m = 0; m < 8; ++m) beta[1 + m] = b[m][0] * b[m][0] + b[m][1] * b[m][1] + b[m][2] * b[m][2];
     const T gl = (T)P.gamma_lin, g0 = T(1) - T(8) * gl, eps = (T)P.weno_eps;
     T tauZ = T(0);
 #pragma unroll
@@ -1923,11 +1972,9 @@ __global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc 
     for (int k = 0; k < 3; ++k) c[1 + k] = s0 * a[k];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-        T b[3];
-        sub_fit(m, b);
         const T al = w[1 + m] * inv - s0 * gl;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) c[1 + k] += al * b[k];
+        for (int k = 0; k < 3; ++k) c[1 + k] += al * b[m][k];
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[1 + k] *= ih;
@@ -2059,9 +2106,12 @@ __device__ __forceinline__ bool hex_point_flux(const ProbDesc &P, int stage, uin
 // Face flux on hexahedra: four consecutive lanes take the four Gauss points of a
 // face and sum their weighted fluxes across the lanes ((g0 + g1) + (g2 + g3)); the
 // first lane writes S-weighted (F, dF) to the per-face buffer.
+// Two waves per SIMD, except the FP64 viscous variant: held to 256 registers it spills
+// some 700 bytes a lane and runs at less than half the speed of one wave with its
+// 256 + 174 registers (1.9 against 4.4 ms a launch on the 884,736-cell O-grid).
 template <bool MIXED, int TM>
-__global__ __launch_bounds__(4 * HEX_FLUX_FACES) void k_flux_hex(const ProbDesc *__restrict__ probs,
-                                                                  const Tile *__restrict__ tiles, int stage) {
+__global__ __launch_bounds__(4 * HEX_FLUX_FACES) __attribute__((amdgpu_waves_per_eu((MIXED || TM != 2) ? 2 : 1))) void k_flux_hex(
+    const ProbDesc *__restrict__ probs, const Tile *__restrict__ tiles, int stage) {
     const Tile tl = tiles[blockIdx.x];
     const ProbDesc &P = probs[tl.prob];
     const uint32_t g = threadIdx.x & 3u;
