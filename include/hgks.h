@@ -55,9 +55,9 @@ typedef enum {
     HGKS_FP32_MIXED = 1       /* FP64 geometry, pseudo-inverse contraction, state and
                                  accumulation; FP32 smoothness indicators, weights,
                                  Gauss-point reconstruction and gas-kinetic flux
-                                 (with tau > 0, Gauss points across a shock, where the
-                                 two sides differ by more than 30%, are evaluated in
-                                 FP64) */,
+                                 (with tau > 0, a Gauss point with a cold side, whose
+                                 energy is more than 90% kinetic, is evaluated in FP64:
+                                 there FP32 loses the pressure and the micro-slopes) */,
     HGKS_FP32 = 2             /* the single-precision build (Sec. 5.1, the memory and time
                                  comparison of FP32 against FP64): the state (Q^n, Q*, and
                                  the stage-2 base), the cell and face geometry, the face
@@ -65,7 +65,7 @@ typedef enum {
                                  the big-stencil pseudo-inverse (each value rounded once);
                                  both WENO contractions, the sub-stencil fits, the weights
                                  and the gas-kinetic flux run in FP32 (tau > 0 Gauss points
-                                 across a shock in FP64, as in the FP32-mixed form).  The
+                                 with a cold side in FP64, as in the FP32-mixed form).  The
                                  few operations of the stage update run in FP64 registers
                                  on FP32 operands and are rounded once on store; dt and the
                                  time stay FP64, and so do the centroids the sub-stencil

@@ -1431,12 +1431,26 @@ __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, ui
     gks_flux_full<double>(qL, gL, qR, gR, nd, P.dt[0], P, Fo, dFo);
 }
 
-// The FP32-mixed form evaluates the tau > 0 flux in FP32 away from discontinuities.
-// A Gauss point where the two reconstructed sides differ by more than 30% in density
-// or pressure (a shock), where the positivity fallback acts, or whose flux is not
-// finite, is left to the FP64 evaluation of the fix-up pass (returns false).  (An
-// FP32 evaluation at every point went non-physical next to a diaphragm on large
-// meshes; with the FP64 path taking the shock points both shock-tube layouts run.)
+// Whether a point state is well conditioned for the FP32 tau > 0 flux: its energy
+// is not mostly kinetic, kappa = E / (rho e) <= 10 (ke <= 0.9 E).  The pressure
+// (gamma-1)(E - |m|^2 / 2 rho) of a state loses about eps kappa of relative
+// precision, and the closed-form micro-slope solve multiplies that error again by
+// about kappa (its energy component is c4 (R4 - 2 U.R) with c4 ~ lam^2 and terms of
+// size |U|^2 b cancelling): in FP32, eps kappa^2 stays below 1e-5 for kappa <= 10,
+// i.e. up to a local Mach number of 5.7 in the frame of the stored state.  Every
+// FP32 point flux that departed from FP64 by more than 1e-3 on the 12.6 M-cell
+// doubled shock tube (753 points, all in the first steps after the diaphragm)
+// had a side with kappa >= 37: a reconstructed state almost without internal
+// energy, whose slope moments came out wrong by up to four orders of magnitude.
+template <class T>
+__device__ __forceinline__ bool warm_point(const T q[5]) {
+    return T(18) * q[0] * q[4] >= T(10) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+}
+
+// The FP32-mixed (and FP32) form evaluates the tau > 0 flux in FP32 where both
+// reconstructed sides are warm (warm_point).  A point with a cold side, where the
+// positivity fallback acts, or whose flux is not finite, is left to the FP64
+// evaluation of the fix-up pass (returns false).
 template <bool WALLS, bool S32 = false>
 __device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, uint32_t f, uint32_t g, uint32_t l,
                                                   uint32_t r, bool wall, double Fo[5], double dFo[5]) {
@@ -1447,10 +1461,7 @@ __device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, 
     recon_point<float, false, true, S32>(P, stage, r, yr, qR, gR);
     if constexpr (WALLS) reflect_grad(gR, n, wall ? 2.0f : 0.0f);
     if (!(physical_point(qL) && physical_point(qR))) return false;
-    const float gm1 = (float)P.gamma - 1.0f;
-    const float pL = gm1 * (qL[4] - 0.5f * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) / qL[0]);
-    const float pR = gm1 * (qR[4] - 0.5f * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) / qR[0]);
-    if (!(hg_abs(pL - pR) <= 0.3f * (pL + pR) && hg_abs(qL[0] - qR[0]) <= 0.3f * (qL[0] + qR[0]))) return false;
+    if (!(warm_point(qL) && warm_point(qR))) return false;
     float F[5], dF[5];
     gks_flux_full<float>(qL, gL, qR, gR, n, (float)P.dt[0], P, F, dF);
     if (!finite_flux(F, dF)) return false;
@@ -2069,21 +2080,17 @@ __device__ __forceinline__ void hex_point(const ProbDesc &P, int stage, uint32_t
 }
 
 // Point flux of Gauss point g of face f in precision T (TM: tau mode), times the
-// point's weight.  With T = float a point whose sides differ by more than 30% in
-// density or pressure under tau > 0, or whose flux is not finite, is refused
-// (false) and evaluated in FP64 by the caller, as on tetrahedra.
+// point's weight.  With T = float a point with a cold side under tau > 0
+// (warm_point), or whose flux is not finite, is refused (false) and evaluated in
+// FP64 by the caller, as on tetrahedra.
 template <class T, bool REC32, int TM>
 __device__ __forceinline__ bool hex_point_flux(const ProbDesc &P, int stage, uint32_t f, uint32_t g, double Fo[5],
                                                double dFo[5]) {
     T n[3], qL[5], gL[5][3], qR[5], gR[5][3], F[5], dF[5];
     double w;
     hex_point<T, REC32>(P, stage, f, g, n, w, qL, gL, qR, gR);
-    if constexpr (sizeof(T) == 4 && TM != 0) {
-        const T gm1 = (T)P.gamma - T(1);
-        const T pL = gm1 * (qL[4] - T(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) / qL[0]);
-        const T pR = gm1 * (qR[4] - T(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) / qR[0]);
-        if (!(hg_abs(pL - pR) <= T(0.3) * (pL + pR) && hg_abs(qL[0] - qR[0]) <= T(0.3) * (qL[0] + qR[0]))) return false;
-    }
+    if constexpr (sizeof(T) == 4 && TM != 0)
+        if (!(warm_point(qL) && warm_point(qR))) return false;
     if constexpr (TM == 0) {
 #pragma unroll
         for (int q = 0; q < 5; ++q)
