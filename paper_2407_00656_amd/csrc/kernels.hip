@@ -1432,16 +1432,18 @@ __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, ui
 }
 
 // Whether a point state is well conditioned for the FP32 tau > 0 flux: its energy
-// is not mostly kinetic, kappa = E / (rho e) <= 10 (ke <= 0.9 E).  The pressure
+// is not mostly kinetic, kappa = E / (rho e) <= 10 (ke <= 0.9 E; a local Mach
+// number up to 5.7 in the frame of the stored state).  The pressure
 // (gamma-1)(E - |m|^2 / 2 rho) of a state loses about eps kappa of relative
-// precision, and the closed-form micro-slope solve multiplies that error again by
-// about kappa (its energy component is c4 (R4 - 2 U.R) with c4 ~ lam^2 and terms of
-// size |U|^2 b cancelling): in FP32, eps kappa^2 stays below 1e-5 for kappa <= 10,
-// i.e. up to a local Mach number of 5.7 in the frame of the stored state.  Every
-// FP32 point flux that departed from FP64 by more than 1e-3 on the 12.6 M-cell
-// doubled shock tube (753 points, all in the first steps after the diaphragm)
-// had a side with kappa >= 37: a reconstructed state almost without internal
-// energy, whose slope moments came out wrong by up to four orders of magnitude.
+// precision; the closed-form micro-slope solve (energy component c4 (R4 - 2 U.R),
+// c4 ~ lam^2, terms of size |U|^2 b cancelling) and the initial parts' half-space
+// slope moments (terms growing like U^k that cancel) amplify it further.  In FP32
+// the slope solve alone stays within 1e-5 for kappa <= 10 and exceeds 1e-4 from
+// kappa = 1e3.  Every FP32 point flux that departed from FP64 by more than 1e-3 on
+// the 12.6 M-cell doubled shock tube (753 points, all in the first steps after the
+// diaphragm) had a side with kappa >= 37: a reconstructed state almost without
+// internal energy, whose slope moments came out wrong by up to four orders of
+// magnitude; none with kappa < 37 departed.
 template <class T>
 __device__ __forceinline__ bool warm_point(const T q[5]) {
     return T(18) * q[0] * q[4] >= T(10) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
