@@ -42,39 +42,6 @@ _i64p = C.POINTER(C.c_int64)
 _i32p = C.POINTER(C.c_int32)
 _lib = None
 
-# hgks_allocator: void *(*alloc)(size_t, void *stream, void *user); void (*free)(void *, void *stream, void *user)
-_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
-_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
-
-
-class Allocator(C.Structure):
-    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
-
-
-class TorchAllocator:
-    """Device memory from PyTorch's caching allocator, handed to the library through
-    its allocator callbacks (so PyTorch owns and recycles the context's memory).
-    Keep the object alive as long as the contexts that use it (Solver holds it)."""
-
-    def __init__(self, device: int = 0):
-        import torch
-        self._torch = torch
-        self.device = device
-
-        def alloc(nbytes, stream, user):
-            try:
-                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0)))
-            except Exception:        # out of memory: the library reports HGKS_E_OOM
-                return None
-
-        def free(ptr, stream, user):
-            if ptr:
-                torch.cuda.caching_allocator_delete(int(ptr))
-
-        self._alloc = _ALLOC_FN(alloc)
-        self._free = _FREE_FN(free)
-        self.struct = Allocator(self._alloc, self._free, None)
-
 
 def lib():
     """Loads libhgks.so; raises if it has not been built."""
@@ -84,7 +51,7 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
         L = C.CDLL(LIB_PATH)
         L.hgks_default_params.argtypes = [C.POINTER(Params)]
-        L.hgks_create.argtypes = [C.POINTER(Params), C.c_int, C.c_void_p, C.POINTER(Allocator), C.POINTER(C.c_void_p)]
+        L.hgks_create.argtypes = [C.POINTER(Params), C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
         L.hgks_mesh_upload.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_int64, C.c_int, _i64p, _dp, C.c_int64,
                                        _i64p, _i32p]
         L.hgks_init_state.argtypes = [C.c_void_p, _dp, C.c_double]
@@ -141,30 +108,24 @@ OWN_STREAM = "own"
 
 def _stream_handle(stream):
     """None: the device's null stream; "own": a stream the context (pool) creates and
-    destroys (HGKS_OWN_STREAM); an int: a hipStream_t handle; a torch.cuda.Stream: its
-    handle."""
+    destroys (HGKS_OWN_STREAM); an int: a hipStream_t handle."""
     if stream is None:
         return None
-    if isinstance(stream, str) and stream == OWN_STREAM:
+    if stream == OWN_STREAM:
         return 1
     if isinstance(stream, int):
         return stream
-    if hasattr(stream, "cuda_stream"):
-        return int(stream.cuda_stream)
-    raise TypeError(f"stream must be None, 'own', a hipStream_t handle or a torch.cuda.Stream, got {stream!r}")
+    raise TypeError(f"stream must be None, 'own' or a hipStream_t handle, got {stream!r}")
 
 
 class Solver:
     """One HGKS problem on one GPU (hgks_ctx)."""
 
-    def __init__(self, prm: Params | None = None, device: int = 0, stream=None, allocator: TorchAllocator | None = None):
-        """allocator: None (the library's hipMalloc) or a TorchAllocator."""
+    def __init__(self, prm: Params | None = None, device: int = 0, stream=None):
         L = lib()
         self.params = prm if prm is not None else params()
-        self.allocator = allocator            # kept alive for the context's frees
         h = C.c_void_p()
-        st = L.hgks_create(C.byref(self.params), int(device), _stream_handle(stream),
-                           C.byref(allocator.struct) if allocator is not None else None, C.byref(h))
+        st = L.hgks_create(C.byref(self.params), int(device), _stream_handle(stream), None, C.byref(h))
         if st != OK:
             raise HGKSError(st, "hgks_create failed")
         self._h = h

@@ -431,28 +431,3 @@ def test_destroying_a_pooled_context_detaches_it():
     b.step(1)                                 # out of the pool, the context steps alone again
     b.close()
     ref.close()
-
-
-def test_torch_allocator_and_stream():
-    """Device memory from PyTorch's caching allocator and work on a torch stream: the
-    same state bitwise as the library's own allocation on the null stream; the
-    memory is PyTorch's while the context lives and goes back to it on destroy."""
-    import torch
-    say("case: torch allocator and stream")
-    mesh, case, q0 = advection_case(6)
-    ref = make_solver(mesh, q0)
-    ref.step(3)
-    q_ref, _ = ref.get_state()
-    ref.close()
-    torch.cuda.init()
-    before = torch.cuda.memory_allocated(0)
-    st = torch.cuda.Stream()
-    s = hgks.Solver(hgks.params(), stream=st, allocator=hgks.TorchAllocator(0))
-    s.mesh_upload(mesh.nodes, mesh.cell_nodes, mesh.period)
-    s.init_state(q0)
-    assert torch.cuda.memory_allocated(0) - before >= s.footprint()
-    s.step(3)
-    q, _ = s.get_state()
-    s.close()
-    assert torch.cuda.memory_allocated(0) == before
-    assert np.array_equal(q, q_ref)
