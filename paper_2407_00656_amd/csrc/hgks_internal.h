@@ -124,15 +124,20 @@ void parallel_range(int64_t n, const std::function<void(int64_t, int64_t)> &f);
 // 5 = (4,5,6,7), so that faces 0 and 5 are opposite, as faces 1 and 6 of Sec. 2.3).
 constexpr int HEX_FGEO = 34;       // per face: 4 x (n(3), w, y_l(3)), dlr(3), mean normal(3)
 constexpr int HEX_BINV = 72;       // per cell: 8 sub-stencils x 3 x 3
+// Stencil slots of a hexahedral cell: the two layers of a hexahedral lattice (6 face
+// neighbours, 12 across the edges, 6 two faces away).  Shorter stencils (cells at a
+// listed boundary or at an edge shared by three cells) are padded; a mesh with a
+// longer one (an edge shared by five or more cells) is refused.
+constexpr int HEX_SLOTS = 24;
 // sub-stencils of Sec. 2.3 as face indices: S_1 = {i1,i2,i3}, ..., S_8 = {i6,i5,i2}
 constexpr int HEXSUB[8][3] = {{0, 1, 2}, {0, 2, 3}, {0, 3, 4}, {0, 4, 1}, {5, 1, 2}, {5, 2, 3}, {5, 3, 4}, {5, 4, 1}};
 
 struct HexMesh {
     int64_t nc = 0, nf = 0, ng = 0;
-    int ns = 0;                     // stencil slots (0..5 the face neighbours in face order)
+    int ns = 0;                     // stencil slots, HEX_SLOTS (0..5 the face neighbours in face order)
     std::vector<int64_t> perm;      // internal cell c holds caller cell perm[c]
     hvec<int32_t> sten;             // [ns][nc] member ids; id >= nc is ghost id - nc
-    hvec<double> pinv;              // [9 ns][nc]: row r, slot s at (r ns + s)
+    hvec<double> pinv;              // pair rows [9 ns / 2][nc][2]: row r, slot s at ((r ns / 2 + s / 2) nc + c) 2 + s % 2
     hvec<double> binv;              // [72][nc]: sub-stencil m, row k, member t at (m 3 + k) 3 + t
     hvec<double> cgeo;              // [9][nc] as the tetrahedral layout
     hvec<int32_t> cface;            // [6][nc] (face << 1) | (cell is the face's right cell)

@@ -77,6 +77,7 @@ void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int sta
 // Hexahedral meshes: ghost states, WENO (one wave per variable of 64 cells), the
 // Gauss-point flux (tau = 0, tau > 0 shock mode, or viscous) into the per-face buffer.
 constexpr int HEX_WENO_CELLS = 64;
+constexpr int HEX_NS = HEX_SLOTS;    // stencil slots the WENO kernel holds (shorter stencils padded)
 constexpr int HEX_FLUX_FACES = 64;   // faces per flux workgroup (four lanes a face)
 void launch_hex_ghost(const ProbDesc *d, int ng, int stage, hipStream_t s);
 void launch_hex_weno(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s);

@@ -327,6 +327,26 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
 // spare lanes only help with the copy.
 constexpr int WPAIRS0 = 72;
 
+// The (tile, part) unit of this workgroup when each 64-cell tile is split over SPLIT
+// workgroups.  Workgroups go to the eight XCDs round-robin by id, and the tile table
+// is laid out so that XCD x owns a contiguous run of tiles at one workgroup a tile;
+// with SPLIT a tile, XCD x takes a contiguous run of (tile, part) units in cell order,
+// and the tile's slot in the table is found by inverting that layout.
+template <int SPLIT>
+__device__ __forceinline__ void split_tile(uint32_t &kt, uint32_t &part) {
+    const uint32_t nb = gridDim.x, xcd = blockIdx.x & 7u;
+    const uint32_t bx = xcd * (nb >> 3) + min(xcd, nb & 7u) + (blockIdx.x >> 3);
+    const uint32_t jt = bx / SPLIT, nt = nb / SPLIT;
+    kt = jt;
+    if (nt >= 16u) {
+        const uint32_t q8 = nt >> 3, r8 = nt & 7u, big = r8 * (q8 + 1u);
+        const uint32_t xx = jt < big ? jt / (q8 + 1u) : r8 + (jt - big) / q8;
+        const uint32_t qq = jt < big ? jt % (q8 + 1u) : (jt - big) % q8;
+        kt = 8u * qq + xx;
+    }
+    part = bx % SPLIT;
+}
+
 template <int WC>
 constexpr int weno_threads() { return (5 * WC + 63) / 64 * 64; }
 
@@ -355,25 +375,12 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     f2(*sub32)[WC] = reinterpret_cast<f2(*)[WC]>(smem + 36 * 16 * WC);
     double(*sgeo)[WC] = reinterpret_cast<double(*)[WC]>(smem + (36 * 16 + 36 * 8) * WC);   // FP32 form only
     int32_t(*sid)[WC] = reinterpret_cast<int32_t(*)[WC]>(smem + (F32 ? 36 * 16 + 36 * 8 + 7 * 8 : WPAIRS0 * 16) * WC);
-    // Workgroups go to the eight XCDs round-robin by id, and the tile table is laid
-    // out so that XCD x owns a contiguous run of tiles when each tile has one
-    // workgroup.  A tile here has SPLIT workgroups, so renumber: XCD x takes a
-    // contiguous run of (tile, part) units in cell order, and the tile's slot in
-    // the table is found by inverting that layout.
-    const uint32_t nb = gridDim.x, xcd = blockIdx.x & 7u;
-    const uint32_t bx = xcd * (nb >> 3) + min(xcd, nb & 7u) + (blockIdx.x >> 3);
-    const uint32_t jt = bx / SPLIT, nt = nb / SPLIT;
-    uint32_t kt = jt;
-    if (nt >= 16u) {
-        const uint32_t q8 = nt >> 3, r8 = nt & 7u, big = r8 * (q8 + 1u);
-        const uint32_t xx = jt < big ? jt / (q8 + 1u) : r8 + (jt - big) / q8;
-        const uint32_t qq = jt < big ? jt % (q8 + 1u) : (jt - big) % q8;
-        kt = 8u * qq + xx;
-    }
+    uint32_t kt, part;
+    split_tile<SPLIT>(kt, part);
     const Tile tl = tiles[kt];
     const ProbDesc &P = probs[tl.prob];
     const uint32_t nc = (uint32_t)P.nc;
-    const uint32_t c0 = tl.begin + (bx % SPLIT) * WC;   // first cell of this workgroup
+    const uint32_t c0 = tl.begin + part * WC;   // first cell of this workgroup
     const uint32_t last = (uint32_t)tl.end - 1;
     const d2 *p0 = reinterpret_cast<const d2 *>(P.pinv0);
     const f4 *p32 = reinterpret_cast<const f4 *>(P.pinv32);
@@ -1854,100 +1861,124 @@ __global__ __launch_bounds__(256) void k_ghost_hex(const ProbDesc *__restrict__ 
     for (int v = 0; v < 5; ++v) P.G[(size_t)v * ng + g] = o[v];
 }
 
-// WENO on hexahedra (Sec. 2.3, M = 8): wave v of a workgroup forms variable v of its
-// 64 cells, one lane a cell.  The big-stencil fit a = P (Q_k - Q_i) takes the
-// pseudo-inverse through LDS in chunks of six slots: the workgroup's 320 threads
-// copy a chunk's rows once (coalesced, each value read from HBM once), and the five
-// waves read it from there.  The eight linear fits of the exactly determined
-// sub-stencils {i, i_a, i_b, i_c} use their precomputed 3x3 inverses on the first
-// six slots (the face neighbours in face order) and stay in registers; the
-// smoothness indicators, WENO-Z weights (gamma_0 = 1 - 8 gamma) and the combined
-// polynomial follow the tetrahedral kernel, and the record layout is the same, so
-// the flux reads it alike.
-constexpr int HEX_PCHUNK = 6;
+// WENO on hexahedra (Sec. 2.3, M = 8).  A workgroup of 128 threads takes 16 cells
+// (four workgroups per 64-cell tile, XCD-contiguous as for tetrahedra):
+//  - the threads load the cells' HEX_NS stencil ids into LDS and stream the 16
+//    cells' big-stencil pseudo-inverses (9 rows x HEX_NS slots as 108 pair rows,
+//    non-temporal, each value read from HBM once) through registers into LDS in
+//    NCH chunks of slots, the next chunk fetched as the previous one is consumed
+//    (two chunks: 15.4 KB of LDS, six to eight workgroups a CU);
+//  - lane (v, c), v < 5, gathers all HEX_NS member differences of variable v of
+//    cell c at once (ghost members from the stage's ghost states), then forms the
+//    big-stencil fit a = P (Q_k - Q_i) chunk by chunk from LDS;
+//  - thread (m, c) loads the 3x3 inverse of sub-stencil m of cell c, the exactly
+//    determined fit on {i, i_a, i_b, i_c} with i_a.. among the face neighbours (slots
+//    0-5 in face order), and writes it over the consumed rows; the lanes form the
+//    eight linear fits from there;
+//  - the smoothness indicators, WENO-Z weights (gamma_0 = 1 - 8 gamma) and the
+//    combined polynomial follow the tetrahedral kernel, in the same record layout.
+constexpr int HEX_WC = 16;
 
-template <bool MIXED>
-__global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc *__restrict__ probs,
-                                                                  const Tile *__restrict__ tiles, int stage) {
+template <bool MIXED, int NCH>
+__global__ __launch_bounds__(weno_threads<HEX_WC>()) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 1))) void k_weno_hex(const ProbDesc *__restrict__ probs,
+                                                                      const Tile *__restrict__ tiles, int stage) {
     using T = typename std::conditional<MIXED, float, double>::type;
-    __shared__ double sp[HEX_PCHUNK * 9][HEX_WENO_CELLS];
-    const Tile tl = tiles[blockIdx.x];
+    constexpr int WC = HEX_WC, NT = weno_threads<WC>(), NS = HEX_NS;
+    constexpr int SPLIT = HEX_WENO_CELLS / WC;
+    constexpr int CH = NS / 2 / NCH, CROWS = 9 * CH;    // pair columns and pair rows of a chunk
+    static_assert(8 * WC <= NT, "one sub-stencil inverse per thread");
+    static_assert(CROWS * 16 >= 72 * 8, "the inverses fit over a chunk");
+    __shared__ __attribute__((aligned(16))) char smem[(CROWS * 16 + NS * 4) * WC];
+    d2(*sp)[WC] = reinterpret_cast<d2(*)[WC]>(smem);
+    double(*sb)[WC] = reinterpret_cast<double(*)[WC]>(smem);          // the inverses, after the big fit
+    int32_t(*sid)[WC] = reinterpret_cast<int32_t(*)[WC]>(smem + CROWS * 16 * WC);
+    uint32_t kt, part;
+    split_tile<SPLIT>(kt, part);
+    const Tile tl = tiles[kt];
     const ProbDesc &P = probs[tl.prob];
-    const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / HEX_WENO_CELLS));
-    const uint32_t lane = threadIdx.x % HEX_WENO_CELLS;
-    const uint32_t i = (uint32_t)tl.begin + lane;
-    const uint32_t ncell = (uint32_t)(tl.end - tl.begin);
-    const bool act = lane < ncell;
     const uint32_t nc = (uint32_t)P.nc, ng = (uint32_t)P.ng;
-    const int ns = P.ns;
-    const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)v * nc;
-    const double *Gv = P.G + (size_t)v * ng;
-    const double qi = act ? Qv[i] : 0.0;
-    auto member = [&](int s) {
-        const uint32_t id = (uint32_t)P.sten[(size_t)s * nc + i];
-        return (id < nc ? Qv[id] : Gv[id - nc]) - qi;
-    };
-    // copy rows r of slots s0 .. s0 + cnt - 1 of the tile's cells into sp[(s - s0) 9 + r]
-    auto stage_chunk = [&](int s0, int cnt) {
-        for (uint32_t e = threadIdx.x; e < (uint32_t)(cnt * 9 * HEX_WENO_CELLS); e += 5 * HEX_WENO_CELLS) {
-            const uint32_t c = e % HEX_WENO_CELLS, rs = e / HEX_WENO_CELLS;
-            const uint32_t sl = rs / 9u, r = rs % 9u;
-            sp[rs][c] = c < ncell ? P.hpinv[((size_t)r * ns + s0 + sl) * nc + tl.begin + c] : 0.0;
+    const uint32_t c0 = (uint32_t)tl.begin + part * WC, last = (uint32_t)tl.end - 1;
+    // 1. stencil ids, then the pseudo-inverse stream into registers
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(NS * WC); e += NT)
+        sid[e / WC][e % WC] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
+    constexpr int PER = (CROWS * WC + NT - 1) / NT;
+    const d2 *p0 = reinterpret_cast<const d2 *>(P.hpinv);
+    d2 reg[NCH][PER];                    // (one chunk live at a time)
+    auto stream = [&](int h) {           // chunk h: pair columns h CH .. h CH + CH - 1 of the nine rows
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t e = threadIdx.x + k * NT, lr = e / WC;
+            const uint32_t grow = (lr / CH) * (NS / 2) + h * CH + lr % CH;
+            if (e < (uint32_t)(CROWS * WC)) reg[h][k] = ldg_stream(p0 + (size_t)grow * nc, min(c0 + e % WC, last) * 16u);
         }
     };
-    double a64[9], d6[6];
+    auto put = [&](int h) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t e = threadIdx.x + k * NT;
+            if (e < (uint32_t)(CROWS * WC)) sp[e / WC][e % WC] = reg[h][k];
+        }
+    };
+    stream(0);                           // later chunks are fetched as the previous one is consumed
+    const uint32_t v = threadIdx.x / WC, cl = threadIdx.x % WC;
+    const bool active = v < 5u;
+    const uint32_t i = min(c0 + cl, last);
+    const bool ok = active && c0 + cl <= last;
+    const uint32_t vrow = active ? v : 0u;
+    const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)vrow * nc;
+    const double *Gv = P.G + (size_t)vrow * ng;
+    double qi = 0.0, geo[7];
+    if (active) {
+        qi = Qv[i];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) geo[q] = ldg<double>(P.cgeo + (size_t)q * nc, i * 8u);
+    }
+    __syncthreads();                     // ids in LDS
+    // 2. the member differences, all gathers in flight together
+    double d[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const uint32_t id = (uint32_t)sid[s][cl];
+        d[s] = active ? (id < nc ? Qv[id] : Gv[id - nc]) - qi : 0.0;
+    }
+    // 3. the big-stencil fit, chunk by chunk (slot order within each row's sum);
+    // thread (m, c) fetches its sub-stencil inverse meanwhile
+    const uint32_t fm = threadIdx.x / WC;
+    double binv[9], a64[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) a64[r] = 0.0;
-    stage_chunk(0, HEX_PCHUNK);          // the first chunk: the six face neighbours
-    __syncthreads();
-    if (act) {
-        if constexpr (MIXED) {
 #pragma unroll
-            for (int s = 0; s < 6; ++s) d6[s] = member(s);
-        }
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            if constexpr (!MIXED) d6[s] = member(s);
-#pragma unroll
-            for (int r = 0; r < 9; ++r) a64[r] = fma(sp[s * 9 + r][lane], d6[s], a64[r]);
-        }
-    }
-    for (int s0 = HEX_PCHUNK; s0 < ns; s0 += HEX_PCHUNK) {
-        const int cnt = min(HEX_PCHUNK, ns - s0);
-        __syncthreads();                  // the previous chunk is consumed
-        stage_chunk(s0, cnt);
+    for (int h = 0; h < NCH; ++h) {
+        if (h > 0) __syncthreads();      // the previous chunk is consumed
+        if (h > 0) stream(h);
+        put(h);
         __syncthreads();
-        if (act && !MIXED) {
-            for (int sl = 0; sl < cnt; ++sl) {
-                const double d = member(s0 + sl);
+        if (h == NCH - 1) {
 #pragma unroll
-                for (int r = 0; r < 9; ++r) a64[r] = fma(sp[sl * 9 + r][lane], d, a64[r]);
+            for (int q = 0; q < 9; ++q) binv[q] = ldg<double>(P.hbinv + (size_t)(fm * 9 + q) * nc, i * 8u);
+        }
+#pragma unroll 3                         // fully unrolled, the LDS reads of all rows go up front (512 registers)
+        for (int r = 0; r < 9; ++r) {
+            double acc = a64[r];
+#pragma unroll
+            for (int s2 = 0; s2 < CH; ++s2) {
+                const d2 pp = sp[r * CH + s2][cl];
+                acc = fma(pp.x, d[2 * (h * CH + s2)], acc);
+                acc = fma(pp.y, d[2 * (h * CH + s2) + 1], acc);
             }
-        } else if (act) {
-            // FP32-mixed (fewer registers): all of the chunk's gathers first (ids, then
-            // values), then the products; in FP64 the extra registers cost a wave per
-            // SIMD and more than the early gathers gain
-            uint32_t id[HEX_PCHUNK];
-            double d[HEX_PCHUNK];
-#pragma unroll
-            for (int sl = 0; sl < HEX_PCHUNK; ++sl)
-                id[sl] = sl < cnt ? (uint32_t)P.sten[(size_t)(s0 + sl) * nc + i] : i;
-#pragma unroll
-            for (int sl = 0; sl < HEX_PCHUNK; ++sl) d[sl] = (id[sl] < nc ? Qv[id[sl]] : Gv[id[sl] - nc]) - qi;
-#pragma unroll
-            for (int sl = 0; sl < HEX_PCHUNK; ++sl)
-                if (sl < cnt)
-#pragma unroll
-                    for (int r = 0; r < 9; ++r) a64[r] = fma(sp[sl * 9 + r][lane], d[sl], a64[r]);
+            a64[r] = acc;
         }
     }
-    if (!act) return;
+    __syncthreads();                     // every lane has read the big rows
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sb[fm * 9 + q][cl] = binv[q];
+    __syncthreads();
+    if (!ok) return;
     T a[9], M[6];
 #pragma unroll
     for (int r = 0; r < 9; ++r) a[r] = (T)a64[r];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) M[q] = (T)P.cgeo[(size_t)(1 + q) * nc + i];
-    const double *B = P.hbinv + i;
+    for (int q = 0; q < 6; ++q) M[q] = (T)geo[1 + q];
     T b[8][3];
 #pragma unroll
     for (int m = 0; m < 8; ++m)
@@ -1955,7 +1986,7 @@ __global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc 
         for (int k = 0; k < 3; ++k) {
             double t = 0.0;
 #pragma unroll
-            for (int u = 0; u < 3; ++u) t = fma(B[(size_t)((m * 3 + k) * 3 + u) * nc], d6[HEXSUB[m][u]], t);
+            for (int u = 0; u < 3; ++u) t = fma(sb[(m * 3 + k) * 3 + u][cl], d[HEXSUB[m][u]], t);
             b[m][k] = (T)t;
         }
     // smoothness indicators in scaled coordinates (mean over the cell of the squared
@@ -1979,7 +2010,7 @@ __global__ __launch_bounds__(5 * HEX_WENO_CELLS) void k_weno_hex(const ProbDesc 
     }
     const T inv = hg_rcp(ws);
     const T s0 = w[0] * inv * hg_rcp(g0);
-    const T ih = (T)P.cgeo[i], ih2 = ih * ih;
+    const T ih = (T)geo[0], ih2 = ih * ih;
     T c[10];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[1 + k] = s0 * a[k];
@@ -2083,8 +2114,8 @@ __device__ __forceinline__ void hex_point(const ProbDesc &P, int stage, uint32_t
 
 // Point flux of Gauss point g of face f in precision T (TM: tau mode), times the
 // point's weight.  With T = float a point with a cold side under tau > 0
-// (warm_point), or whose flux is not finite, is refused (false) and evaluated in
-// FP64 by the caller, as on tetrahedra.
+// (warm_point), or whose flux is not finite, is refused (false): its face is then
+// evaluated in FP64 by the fix-up pass, as on tetrahedra.
 template <class T, bool REC32, int TM>
 __device__ __forceinline__ bool hex_point_flux(const ProbDesc &P, int stage, uint32_t f, uint32_t g, double Fo[5],
                                                double dFo[5]) {
@@ -2115,6 +2146,10 @@ __device__ __forceinline__ bool hex_point_flux(const ProbDesc &P, int stage, uin
 // Face flux on hexahedra: four consecutive lanes take the four Gauss points of a
 // face and sum their weighted fluxes across the lanes ((g0 + g1) + (g2 + g3)); the
 // first lane writes S-weighted (F, dF) to the per-face buffer.
+// FP32-mixed: a point the FP32 flux refuses makes its face's sum NaN, and the face is
+// left to the FP64 pass below (flag[1] raised, cleared by the stage update), as on
+// tetrahedra; with no FP64 code inline the FP32 kernels need 113 / 129 / 208 registers
+// (tau = 0 / shock mode / viscous) instead of 155 / 256 / 256 plus 264 spilled.
 // Two waves per SIMD, except the FP64 viscous variant: held to 256 registers it spills
 // some 700 bytes a lane and runs at less than half the speed of one wave with its
 // 256 + 174 registers (1.9 against 4.4 ms a launch on the 884,736-cell O-grid).
@@ -2130,11 +2165,11 @@ __global__ __launch_bounds__(4 * HEX_FLUX_FACES) __attribute__((amdgpu_waves_per
 #pragma unroll
     for (int k = 0; k < 5; ++k) Fo[k] = dFo[k] = 0.0;
     if (ok) {
-        bool done;
-        if constexpr (MIXED) done = hex_point_flux<float, true, TM>(P, stage, f, g, Fo, dFo);
-        else done = hex_point_flux<double, false, TM>(P, stage, f, g, Fo, dFo);
-        if constexpr (MIXED)
-            if (!done) hex_point_flux<double, true, TM>(P, stage, f, g, Fo, dFo);
+        if constexpr (MIXED) {
+            if (!hex_point_flux<float, true, TM>(P, stage, f, g, Fo, dFo)) Fo[0] = __builtin_nan("");
+        } else {
+            hex_point_flux<double, false, TM>(P, stage, f, g, Fo, dFo);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -2149,6 +2184,37 @@ __global__ __launch_bounds__(4 * HEX_FLUX_FACES) __attribute__((amdgpu_waves_per
         for (int k = 0; k < 5; ++k) {
             P.FF[(size_t)k * nf + f] = Fo[k];
             P.FF[(size_t)(5 + k) * nf + f] = dFo[k];
+        }
+    }
+    if constexpr (MIXED) {
+        const uint64_t bad = __ballot(ok && g == 0u && !(Fo[0] - Fo[0] == 0.0));
+        if (bad != 0 && (threadIdx.x & 63u) == 0) P.flag[1] = 1;
+    }
+}
+
+// Faces the FP32-mixed hexahedral flux left (a NaN flux): the four Gauss points again
+// in FP64 from the FP32 records, summed in the same order.  One lane a face, a grid
+// stride over the face tiles, after one look at the flag (nothing to do is the
+// common case); the recomputation is rare and may use scratch memory.
+template <int TM>
+__global__ __launch_bounds__(HEX_FLUX_FACES) void k_flux_hex_fix(const ProbDesc *__restrict__ d,
+                                                                  const Tile *__restrict__ tiles, int ntiles, int stage) {
+    const ProbDesc &P = *d;
+    if (ldg<int32_t>(P.flag, 4u) == 0) return;
+    const uint32_t nf = (uint32_t)P.nf;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const uint32_t f = (uint32_t)tl.begin + threadIdx.x;
+        if (f >= (uint32_t)tl.end) continue;
+        const double f0 = P.FF[f];
+        if (f0 - f0 == 0.0) continue;                     // finite: done in FP32
+        double F[4][5], dF[4][5];
+#pragma unroll 1
+        for (uint32_t g = 0; g < 4u; ++g) hex_point_flux<double, true, TM>(P, stage, f, g, F[g], dF[g]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            P.FF[(size_t)k * nf + f] = (F[0][k] + F[1][k]) + (F[2][k] + F[3][k]);
+            P.FF[(size_t)(5 + k) * nf + f] = (dF[0][k] + dF[1][k]) + (dF[2][k] + dF[3][k]);
         }
     }
 }
@@ -2249,8 +2315,9 @@ void launch_hex_ghost(const ProbDesc *d, int ng, int stage, hipStream_t s) {
 
 void launch_hex_weno(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, hipStream_t s) {
     if (ntiles <= 0) return;
-    if (mixed) hipLaunchKernelGGL(k_weno_hex<true>, dim3(ntiles), dim3(5 * HEX_WENO_CELLS), 0, s, d, tiles, stage);
-    else hipLaunchKernelGGL(k_weno_hex<false>, dim3(ntiles), dim3(5 * HEX_WENO_CELLS), 0, s, d, tiles, stage);
+    const dim3 g(ntiles * (HEX_WENO_CELLS / HEX_WC)), b(weno_threads<HEX_WC>());
+    if (mixed) hipLaunchKernelGGL((k_weno_hex<true, 2>), g, b, 0, s, d, tiles, stage);
+    else hipLaunchKernelGGL((k_weno_hex<false, 2>), g, b, 0, s, d, tiles, stage);
 }
 
 void launch_hex_flux(const ProbDesc *d, const Tile *tiles, int ntiles, int stage, bool mixed, int tau_mode,
@@ -2264,6 +2331,12 @@ void launch_hex_flux(const ProbDesc *d, const Tile *tiles, int ntiles, int stage
         if (tau_mode == 0) HGKS_HF(false, 0); else if (tau_mode == 1) HGKS_HF(false, 1); else HGKS_HF(false, 2);
     }
 #undef HGKS_HF
+    if (mixed) {              // faces left to FP64 by the FP32 pass
+        const dim3 gf(std::min(ntiles, 8 * device_cus())), bf(HEX_FLUX_FACES);
+#define HGKS_HX(TM) hipLaunchKernelGGL((k_flux_hex_fix<TM>), gf, bf, 0, s, d, tiles, ntiles, stage)
+        if (tau_mode == 0) HGKS_HX(0); else if (tau_mode == 1) HGKS_HX(1); else HGKS_HX(2);
+#undef HGKS_HX
+    }
 }
 
 void launch_update(const ProbDesc *probs, const Tile *tiles, int ntiles, int stage, bool coloured, bool s32,

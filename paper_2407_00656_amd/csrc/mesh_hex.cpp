@@ -505,7 +505,12 @@ hgks_status build_hex_mesh(const hgks_params &prm, int64_t nn, const double *xyz
               "five cells)";
         return HGKS_E_BAD_MESH;
     }
-    const int ns = smax.load();
+    if (smax.load() > HEX_SLOTS) {
+        err = "a hexahedral stencil has more than " + std::to_string(HEX_SLOTS) +
+              " members (an edge shared by more than four cells)";
+        return HGKS_E_BAD_MESH;
+    }
+    const int ns = HEX_SLOTS;
     out.sten.resize((size_t)ns * nc);
     out.pinv.resize((size_t)9 * ns * nc);
     out.binv.resize((size_t)HEX_BINV * nc);
@@ -535,7 +540,8 @@ hgks_status build_hex_mesh(const hgks_params &prm, int64_t nn, const double *xyz
             }
             for (int s = 0; s < ns; ++s) {
                 out.sten[(size_t)s * nc + i] = s < K ? S[s].id : (int32_t)i;
-                for (int r = 0; r < 9; ++r) out.pinv[((size_t)r * ns + s) * nc + i] = s < K ? Pm[(size_t)r * K + s] : 0.0;
+                for (int r = 0; r < 9; ++r)
+                    out.pinv[(((size_t)r * (ns / 2) + s / 2) * nc + i) * 2 + (s & 1)] = s < K ? Pm[(size_t)r * K + s] : 0.0;
             }
             if (diagnostics) {
                 for (int r = 0; r < 9; ++r)

@@ -162,6 +162,45 @@ def test_hex_box_fp32_mixed_run():
     assert np.all(err < TOL32), err
 
 
+def cold_stream_state(mesh, umax=9.0):
+    """rho = 1, p = 1 and a shear stream u = umax (1 + sin(pi y)) / 2 along x on
+    [0, 2]^3 (no compression): kappa = E / (rho e) = 1 + u^2 / 5 runs from 1 to 17,
+    so the FP32 flux refuses the Gauss points of the fast (cold) layer (kappa > 10)
+    and takes the others."""
+    c = mesh.cell_vertices.mean(axis=1)
+    u = umax * 0.5 * (1.0 + np.sin(np.pi * c[:, 1]))
+    q = np.zeros((mesh.n_cells, 5))
+    q[:, 0] = 1.0
+    q[:, 1] = u
+    q[:, 4] = 1.0 / 0.4 + 0.5 * u * u
+    return q
+
+
+@pytest.mark.parametrize("tau_mode", [1, 2])
+def test_hex_box_fp32_mixed_cold_stream(tau_mode):
+    """The FP32-mixed hexahedral flux refuses the cold half's Gauss points; their
+    faces come out NaN and the FP64 fix-up pass recomputes them.  After 6 steps
+    the state is finite and within 1e-5 relative L1 of the oracle's."""
+    say(f"case: hex box N=6 cold stream fp32-mixed tau_mode={tau_mode} 6 steps")
+    mesh = W.hex_box(6, jitter=0.15)
+    q0 = cold_stream_state(mesh)
+    kappa = q0[:, 4] / (q0[:, 4] - 0.5 * q0[:, 1] ** 2)
+    assert np.any(kappa > 12.0) and np.any(kappa < 8.0)
+    case = W.SphereCase()
+    kw = dict(tau_mode=tau_mode)
+    if tau_mode == 2:
+        kw.update(mu_ref=1e-3, T_ref=1.0, mu_exp=0.7, prandtl=case.prandtl)
+    s = solver(mesh, q0, precision=hgks.FP32_MIXED, **kw)
+    s.step(6)
+    q, _ = s.get_state()
+    s.close()
+    q_orc, _ = O.Mesh.from_workload(mesh).step(q0, 6, params=oracle_params(**kw))
+    assert np.all(np.isfinite(q))
+    err = rel_l1_scaled(q, q_orc, W.hex_volumes(mesh.cell_vertices))
+    say("rel L1", err)
+    assert np.all(err < TOL32), err
+
+
 def test_sphere_full_size_sampled_step():
     """The sphere workload itself (6*48*48 cells by 64 layers, 884,736 hexes): one
     viscous FP64 step, 64 sampled cells (wall, far field and interior) against the
