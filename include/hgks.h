@@ -154,7 +154,9 @@ hgks_status hgks_create(const hgks_params *params, int device, void *hip_stream,
  *               (2,3,7,6), (3,0,4,7), (4,5,6,7) are the paper's faces 1..6 (1 and 6
  *               opposite), eight sub-stencils, and on each bilinear face the 2x2
  *               Gauss points with their own normals.  Hexahedral meshes take the
- *               FP64 and FP32-mixed precisions and the gather accumulation.
+ *               FP64 and FP32-mixed precisions and the gather accumulation; a
+ *               two-layer stencil of more than 24 cells (an edge shared by five or
+ *               more cells) is refused (BAD_MESH).
  *   period      [3]: period[a] > 0 identifies x_a with x_a + period[a] (NULL = none)
  *               Tetrahedra: an axis with period 0 ends in two transmissive walls,
  *               the planes through its lowest and highest node coordinate: every
@@ -202,8 +204,8 @@ hgks_status hgks_get_state(hgks_ctx *ctx, double *q_out, double *t_out);
 /* Waits for the context's queued work.  Errors: DEVICE, NONPHYSICAL. */
 hgks_status hgks_sync(hgks_ctx *ctx);
 
-/* Mesh sizes after upload: cells, faces, two-layer stencil slots (16 for tetrahedra;
- * for hexahedra the largest stencil of the mesh, 24 on a regular lattice), colour classes
+/* Mesh sizes after upload: cells, faces, two-layer stencil slots (16 for tetrahedra,
+ * 24 for hexahedra), colour classes
  * (with HGKS_ACC_COLOURED: 4 when the cell graph is bipartite, else at most 5;
  * 1 with the gather accumulation). */
 hgks_status hgks_mesh_info(const hgks_ctx *ctx, int64_t *n_cells, int64_t *n_faces,
@@ -228,8 +230,8 @@ void hgks_destroy(hgks_ctx *ctx);
  * Host-only inspection of the mesh precompute (no GPU needed): builds exactly
  * what mesh_upload would build (without listed boundary faces) and reports it in
  * the library's internal order.
- *   stats [8]: n_faces, stencil slots (16 for tetrahedra, the largest stencil for
- *              hexahedra), max distinct big-stencil members, min distinct
+ *   stats [8]: n_faces, stencil slots (16 for tetrahedra, 24 for hexahedra),
+ *              max distinct big-stencil members, min distinct
  *              big-stencil members, n_colours, max |pinv A - I| over all cells,
  *              max |sum_p n_p S_p| over all cells (closure), number of duplicate
  *              slots (tetrahedra)

@@ -79,12 +79,38 @@ __device__ __forceinline__ f4 ldg_stream_f4(const void *base, uint32_t off) {
     const v4f v = __builtin_nontemporal_load((gptr<const v4f>)((gptr<const char>)base + off));
     return {v.x, v.y, v.z, v.w};
 }
+__device__ __forceinline__ f2 ldg_stream_f2(const void *base, uint32_t off) {
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = __builtin_nontemporal_load((gptr<const v2f>)((gptr<const char>)base + off));
+    return {v.x, v.y};
+}
+// Streaming scalar load / store (read once, or written for a later kernel that
+// gathers it): kept out of the way of the reusable lines.
+template <class T>
+__device__ __forceinline__ T ldg_nt(const void *base, uint32_t off) {
+    return __builtin_nontemporal_load((gptr<const T>)((gptr<const char>)base + off));
+}
+template <class T>
+__device__ __forceinline__ void stg_nt(void *base, uint32_t off, T v) {
+    __builtin_nontemporal_store(v, (gptr<T>)((gptr<char>)base + off));
+}
 #else
 __device__ __forceinline__ d2 ldg_stream(const void *base, uint32_t off) {
     return *(const d2 *)((const char *)base + off);
 }
 __device__ __forceinline__ f4 ldg_stream_f4(const void *base, uint32_t off) {
     return *(const f4 *)((const char *)base + off);
+}
+__device__ __forceinline__ f2 ldg_stream_f2(const void *base, uint32_t off) {
+    return *(const f2 *)((const char *)base + off);
+}
+template <class T>
+__device__ __forceinline__ T ldg_nt(const void *base, uint32_t off) {
+    return *(const T *)((const char *)base + off);
+}
+template <class T>
+__device__ __forceinline__ void stg_nt(void *base, uint32_t off, T v) {
+    *(T *)((char *)base + off) = v;
 }
 template <class T>
 __device__ __forceinline__ T ldg(const void *base, uint32_t off) {
@@ -144,6 +170,9 @@ struct Sto {
     }
     __device__ static __forceinline__ void st(double *base, size_t row, uint32_t n, uint32_t i, double v) {
         stg<E>(reinterpret_cast<E *>(base) + row * n, i * SZ, (E)v);
+    }
+    __device__ static __forceinline__ void st_nt(double *base, size_t row, uint32_t n, uint32_t i, double v) {
+        stg_nt<E>(reinterpret_cast<E *>(base) + row * n, i * SZ, (E)v);
     }
 };
 
@@ -1214,11 +1243,11 @@ __device__ __forceinline__ void load_fgeo(const ProbDesc &P, uint32_t f, double 
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if constexpr (S32) {
-            const f2 pr = ldg<f2>(reinterpret_cast<const f2 *>(P.fgeo) + k * nf, f * 8u);
+            const f2 pr = ldg_stream_f2(reinterpret_cast<const f2 *>(P.fgeo) + k * nf, f * 8u);
             v[2 * k] = pr.x;
             v[2 * k + 1] = pr.y;
         } else {
-            const d2 pr = ldg<d2>(reinterpret_cast<const d2 *>(P.fgeo) + k * nf, f * 16u);
+            const d2 pr = ldg_stream(reinterpret_cast<const d2 *>(P.fgeo) + k * nf, f * 16u);
             v[2 * k] = pr.x;
             v[2 * k + 1] = pr.y;
         }
@@ -1365,7 +1394,12 @@ k_flux_t0(const ProbDesc *__restrict__ probs,
             ST::st(P.acc, k, ncu, l, ST::ld(P.acc, k, ncu, l) - out[k]);
             if (!wall) ST::st(P.acc, k, ncu, r, ST::ld(P.acc, k, ncu, r) + out[k]);
         } else if (!DF_ONLY || k >= 5) {
-            ST::st(P.FF, k, nf, f, out[k]);
+            // streaming stores (the update gathers them later).  In the FP64-storage
+            // forms the generic-address form of the store is used: with it the compiler
+            // keeps up to 21 record loads in flight rather than 9 (356 against 371 us a
+            // launch at 6 64^3, FP64)
+            if constexpr (!S32) __builtin_nontemporal_store(out[k], P.FF + (size_t)k * nf + f);
+            else ST::st_nt(P.FF, k, nf, f, out[k]);
         }
     }
     if constexpr (!COLOURED) {
@@ -1604,7 +1638,7 @@ __global__ __launch_bounds__(64) void k_flux_gp(const ProbDesc *__restrict__ pro
         const double o1 = __shfl_down(out[k], 1u), o2 = __shfl_down(out[k], 2u);
         const double sum = (out[k] + o1) + o2;
         if (k == 0) s0 = sum;
-        if (ok && g == 0u) ST::st(P.FF, k, nf, f, sum);
+        if (ok && g == 0u) ST::st_nt(P.FF, k, nf, f, sum);
     }
     if constexpr (MIXED) {
         // the fix-up pass has work: a face left to FP64 (flag cleared by the stage update)
@@ -2182,8 +2216,8 @@ __global__ __launch_bounds__(4 * HEX_FLUX_FACES) __attribute__((amdgpu_waves_per
         const uint32_t nf = (uint32_t)P.nf;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            P.FF[(size_t)k * nf + f] = Fo[k];
-            P.FF[(size_t)(5 + k) * nf + f] = dFo[k];
+            stg_nt<double>(P.FF + (size_t)k * nf, f * 8u, Fo[k]);
+            stg_nt<double>(P.FF + (size_t)(5 + k) * nf, f * 8u, dFo[k]);
         }
     }
     if constexpr (MIXED) {
