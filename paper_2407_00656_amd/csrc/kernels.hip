@@ -94,6 +94,11 @@ template <class T>
 __device__ __forceinline__ void stg_nt(void *base, uint32_t off, T v) {
     __builtin_nontemporal_store(v, (gptr<T>)((gptr<char>)base + off));
 }
+// A global load through a full per-lane address (for a select between two arrays)
+template <class T>
+__device__ __forceinline__ T ldg_at(const T *p) {
+    return *(gptr<const T>)p;
+}
 #else
 __device__ __forceinline__ d2 ldg_stream(const void *base, uint32_t off) {
     return *(const d2 *)((const char *)base + off);
@@ -111,6 +116,10 @@ __device__ __forceinline__ T ldg_nt(const void *base, uint32_t off) {
 template <class T>
 __device__ __forceinline__ void stg_nt(void *base, uint32_t off, T v) {
     *(T *)((char *)base + off) = v;
+}
+template <class T>
+__device__ __forceinline__ T ldg_at(const T *p) {
+    return *p;
 }
 template <class T>
 __device__ __forceinline__ T ldg(const void *base, uint32_t off) {
@@ -292,9 +301,10 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
                                (uint64_t)SUBFIRST[2][0] << 24 | (uint64_t)SUBFIRST[2][1] << 28 |
                                (uint64_t)SUBFIRST[2][2] << 32 | (uint64_t)SUBFIRST[3][0] << 36 |
                                (uint64_t)SUBFIRST[3][1] << 40 | (uint64_t)SUBFIRST[3][2] << 44;
-    const double ih = LDSGEO ? sgeo[0][cs] : P.cgeo[i];
-    const double ci[3] = {P.cen[i], P.cen[nc + i], P.cen[2 * nc + i]};
-    const uint32_t w0 = P.sshift[i], w1 = P.sshift[nc + i], w2 = P.sshift[2 * nc + i], w3 = P.sshift[3 * nc + i];
+    const double ih = LDSGEO ? sgeo[0][cs] : ldg<double>(P.cgeo, i * 8u);
+    const double ci[3] = {ldg<double>(P.cen, i * 8u), ldg<double>(P.cen + nc, i * 8u), ldg<double>(P.cen + 2 * nc, i * 8u)};
+    const uint32_t w0 = ldg<uint32_t>(P.sshift, i * 4u), w1 = ldg<uint32_t>(P.sshift + nc, i * 4u),
+                   w2 = ldg<uint32_t>(P.sshift + 2 * nc, i * 4u), w3 = ldg<uint32_t>(P.sshift + 3 * nc, i * 4u);
     T A[6][3];
     int32_t id[6];
     uint32_t code[6];
@@ -304,12 +314,12 @@ __device__ __forceinline__ void sub_stencil_pinv(const ProbDesc &P, uint32_t i, 
         const uint32_t wsel = sl >> 2;
         const uint32_t word = wsel == 0 ? w0 : (wsel == 1 ? w1 : (wsel == 2 ? w2 : w3));
         code[t] = (word >> (8 * (sl & 3u))) & 0xFFu;
-        id[t] = LDSID ? sid[sl][cs] : P.sten[sl * nc + i];
+        id[t] = LDSID ? sid[sl][cs] : ldg<int32_t>(P.sten + sl * nc, i * 4u);
         const int sh[3] = {(int)(code[t] % 5u) - 2, (int)((code[t] / 5u) % 5u) - 2, (int)(code[t] / 25u) - 2};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             // periodic image, or on a non-periodic axis the cell (s = 0) or its mirror in a wall
-            const double c = P.cen[a * nc + (size_t)id[t]];
+            const double c = ldg<double>(P.cen + a * nc, (uint32_t)id[t] * 8u);
             double x = c + (double)sh[a] * P.per[a];
             if constexpr (WALLS) {      // meshes without walls keep the plain periodic form
                 const double mlo = P.mir[a][0], mhi = P.mir[a][1];
@@ -413,29 +423,39 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
     const uint32_t last = (uint32_t)tl.end - 1;
     const d2 *p0 = reinterpret_cast<const d2 *>(P.pinv0);
     const f4 *p32 = reinterpret_cast<const f4 *>(P.pinv32);
-    // 1. stream the big-stencil pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the tile)
+    // 1. the cells' stencil ids (and in the FP32 form geometry), once per cell, then the
+    // stream of the big-stencil pseudo-inverses of cells c0 .. c0+WC-1 (clamped to the
+    // tile).  The ids are loaded first: their LDS copy then waits for them alone, not
+    // for the stream behind them (the wait counter is in order).
+    constexpr int IDS = (SLOTS * WC + NT - 1) / NT;
+    int32_t idv[IDS];
+#pragma unroll
+    for (int k = 0; k < IDS; ++k) {     // (clamped rather than guarded: no branch per load)
+        const uint32_t e = min(threadIdx.x + k * NT, (uint32_t)(SLOTS * WC - 1));
+        idv[k] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
+    }
+    double gv = 0.0;
+    if (F32 && threadIdx.x < 7u * WC) gv = Sto<F32>::ld(P.cgeo, threadIdx.x / WC, nc, min(c0 + threadIdx.x % WC, last));
     using SV = std::conditional_t<F32, f4, d2>;
     using DT = std::conditional_t<F32, float, double>;   // contraction precision
     constexpr int PER = (ROWS * WC + NT - 1) / NT;
     SV reg[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(ROWS * WC)) {
-            const uint32_t row = e / WC, c = min(c0 + e % WC, last);
-            if constexpr (F32)
-                reg[k] = ldg_stream_f4(p32 + (size_t)row * nc, c * 16u);
-            else
-                reg[k] = ldg_stream(p0 + (size_t)row * nc, c * 16u);
-        }
+        const uint32_t e = min(threadIdx.x + k * NT, (uint32_t)(ROWS * WC - 1));
+        const uint32_t row = e / WC, c = min(c0 + e % WC, last);
+        if constexpr (F32)
+            reg[k] = ldg_stream_f4(p32 + (size_t)row * nc, c * 16u);
+        else
+            reg[k] = ldg_stream(p0 + (size_t)row * nc, c * 16u);
     }
-    {   // the cells' stencil ids (and in the FP32 form geometry), once per cell
+    {
 #pragma unroll
-        for (uint32_t e = threadIdx.x; e < (uint32_t)(SLOTS * WC); e += NT)
-            sid[e / WC][e % WC] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
-        if (F32 && threadIdx.x < 7u * WC)
-            sgeo[threadIdx.x / WC][threadIdx.x % WC] =
-                Sto<F32>::ld(P.cgeo, threadIdx.x / WC, nc, min(c0 + threadIdx.x % WC, last));
+        for (int k = 0; k < IDS; ++k) {
+            const uint32_t e = threadIdx.x + k * NT;
+            if (e < (uint32_t)(SLOTS * WC)) sid[e / WC][e % WC] = idv[k];
+        }
+        if (F32 && threadIdx.x < 7u * WC) sgeo[threadIdx.x / WC][threadIdx.x % WC] = gv;
         __syncthreads();
     }
     // 2. the sub-stencil fits: thread (m, c) for m < 4.  The FP32 form stages them
@@ -1932,18 +1952,24 @@ __global__ __launch_bounds__(weno_threads<HEX_WC>()) __attribute__((amdgpu_waves
     const ProbDesc &P = probs[tl.prob];
     const uint32_t nc = (uint32_t)P.nc, ng = (uint32_t)P.ng;
     const uint32_t c0 = (uint32_t)tl.begin + part * WC, last = (uint32_t)tl.end - 1;
-    // 1. stencil ids, then the pseudo-inverse stream into registers
-    for (uint32_t e = threadIdx.x; e < (uint32_t)(NS * WC); e += NT)
-        sid[e / WC][e % WC] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
+    // 1. stencil ids, then the pseudo-inverse stream into registers (the ids' LDS copy
+    // then waits for the ids alone: the wait counter is in order)
+    constexpr int IDS = (NS * WC + NT - 1) / NT;
+    int32_t idv[IDS];
+#pragma unroll
+    for (int k = 0; k < IDS; ++k) {     // (clamped rather than guarded: no branch per load)
+        const uint32_t e = min(threadIdx.x + k * NT, (uint32_t)(NS * WC - 1));
+        idv[k] = ldg<int32_t>(P.sten + (size_t)(e / WC) * nc, min(c0 + e % WC, last) * 4u);
+    }
     constexpr int PER = (CROWS * WC + NT - 1) / NT;
     const d2 *p0 = reinterpret_cast<const d2 *>(P.hpinv);
     d2 reg[NCH][PER];                    // (one chunk live at a time)
     auto stream = [&](int h) {           // chunk h: pair columns h CH .. h CH + CH - 1 of the nine rows
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const uint32_t e = threadIdx.x + k * NT, lr = e / WC;
+            const uint32_t e = min(threadIdx.x + k * NT, (uint32_t)(CROWS * WC - 1)), lr = e / WC;
             const uint32_t grow = (lr / CH) * (NS / 2) + h * CH + lr % CH;
-            if (e < (uint32_t)(CROWS * WC)) reg[h][k] = ldg_stream(p0 + (size_t)grow * nc, min(c0 + e % WC, last) * 16u);
+            reg[h][k] = ldg_stream(p0 + (size_t)grow * nc, min(c0 + e % WC, last) * 16u);
         }
     };
     auto put = [&](int h) {
@@ -1954,6 +1980,11 @@ __global__ __launch_bounds__(weno_threads<HEX_WC>()) __attribute__((amdgpu_waves
         }
     };
     stream(0);                           // later chunks are fetched as the previous one is consumed
+#pragma unroll
+    for (int k = 0; k < IDS; ++k) {
+        const uint32_t e = threadIdx.x + k * NT;
+        if (e < (uint32_t)(NS * WC)) sid[e / WC][e % WC] = idv[k];
+    }
     const uint32_t v = threadIdx.x / WC, cl = threadIdx.x % WC;
     const bool active = v < 5u;
     const uint32_t i = min(c0 + cl, last);
@@ -1961,19 +1992,20 @@ __global__ __launch_bounds__(weno_threads<HEX_WC>()) __attribute__((amdgpu_waves
     const uint32_t vrow = active ? v : 0u;
     const double *Qv = (stage == 1 ? P.Q : P.Qs) + (size_t)vrow * nc;
     const double *Gv = P.G + (size_t)vrow * ng;
-    double qi = 0.0, geo[7];
+    const double qi = ldg<double>(Qv, i * 8u);
+    double geo[7];
     if (active) {
-        qi = Qv[i];
 #pragma unroll
         for (int q = 0; q < 7; ++q) geo[q] = ldg<double>(P.cgeo + (size_t)q * nc, i * 8u);
     }
     __syncthreads();                     // ids in LDS
-    // 2. the member differences, all gathers in flight together
+    // 2. the member differences, all gathers in flight together (no branch per member:
+    // the address selects the state or the ghost array; spare lanes all read cell i)
     double d[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const uint32_t id = (uint32_t)sid[s][cl];
-        d[s] = active ? (id < nc ? Qv[id] : Gv[id - nc]) - qi : 0.0;
+        const uint32_t id = active ? (uint32_t)sid[s][cl] : i;
+        d[s] = ldg_at(id < nc ? Qv + id : Gv + (id - nc)) - qi;
     }
     // 3. the big-stencil fit, chunk by chunk (slot order within each row's sum);
     // thread (m, c) fetches its sub-stencil inverse meanwhile
@@ -2087,7 +2119,7 @@ template <class T, bool REC32>
 __device__ __forceinline__ void hex_point(const ProbDesc &P, int stage, uint32_t f, uint32_t g, T n[3], double &w,
                                           T qL[5], T gL[5][3], T qR[5], T gR[5][3]) {
     const uint32_t nf = (uint32_t)P.nf;
-    auto fg = [&](uint32_t k) { return P.fgeo[(size_t)k * nf + f]; };
+    auto fg = [&](uint32_t k) { return ldg<double>(P.fgeo + (size_t)k * nf, f * 8u); };
     T yl[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -2095,8 +2127,8 @@ __device__ __forceinline__ void hex_point(const ProbDesc &P, int stage, uint32_t
         yl[a] = (T)fg(7 * g + 4 + a);
     }
     w = fg(7 * g + 3);
-    const uint32_t l = (uint32_t)P.fcell[f];
-    const int32_t r = P.fcell[nf + f];
+    const uint32_t l = (uint32_t)ldg<int32_t>(P.fcell, f * 4u);
+    const int32_t r = ldg<int32_t>(P.fcell + nf, f * 4u);
     recon_point<T, false, REC32>(P, stage, l, yl, qL, gL);
     T nm[3];
     if (r >= 0) {
