@@ -453,7 +453,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
 #pragma unroll
         for (int k = 0; k < IDS; ++k) {
             const uint32_t e = threadIdx.x + k * NT;
-            if (e < (uint32_t)(SLOTS * WC)) sid[e / WC][e % WC] = idv[k];
+            if ((k + 1) * NT <= SLOTS * WC || e < (uint32_t)(SLOTS * WC)) sid[e / WC][e % WC] = idv[k];
         }
         if (F32 && threadIdx.x < 7u * WC) sgeo[threadIdx.x / WC][threadIdx.x % WC] = gv;
         __syncthreads();
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(weno_threads<WC>()) void k_weno(const ProbDesc *__r
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(ROWS * WC)) {
+        if ((k + 1) * NT <= ROWS * WC || e < (uint32_t)(ROWS * WC)) {
             if constexpr (F32)
                 big32[e / WC][e % WC] = reg[k];
             else
@@ -1489,7 +1489,7 @@ __device__ __forceinline__ void point_flux_full(const ProbDesc &P, int stage, ui
             gR[v][0] = gR[v][1] = gR[v][2] = 0.0;
         }
     }
-    gks_flux_full<double>(qL, gL, qR, gR, nd, P.dt[0], P, Fo, dFo);
+    gks_flux_full<double>(qL, gL, qR, gR, nd, ldg<double>(P.dt, 0u), P, Fo, dFo);
 }
 
 // Whether a point state is well conditioned for the FP32 tau > 0 flux: its energy
@@ -1526,7 +1526,7 @@ __device__ __forceinline__ bool point_flux_full32(const ProbDesc &P, int stage, 
     if (!(physical_point(qL) && physical_point(qR))) return false;
     if (!(warm_point(qL) && warm_point(qR))) return false;
     float F[5], dF[5];
-    gks_flux_full<float>(qL, gL, qR, gR, n, (float)P.dt[0], P, F, dF);
+    gks_flux_full<float>(qL, gL, qR, gR, n, (float)ldg<double>(P.dt, 0u), P, F, dF);
     if (!finite_flux(F, dF)) return false;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -1759,7 +1759,7 @@ __global__ __launch_bounds__(UPD_TILE) void k_update(const ProbDesc *__restrict_
             }
         }
         const double iv = ST::ld(P.cgeo, 7, nc, i);
-        const double dt = P.dt[0];
+        const double dt = ldg<double>(P.dt, 0u);
         double qn[5];
         bool ok;
         if constexpr (STAGE == 1) {
@@ -1976,14 +1976,14 @@ __global__ __launch_bounds__(weno_threads<HEX_WC>()) __attribute__((amdgpu_waves
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const uint32_t e = threadIdx.x + k * NT;
-            if (e < (uint32_t)(CROWS * WC)) sp[e / WC][e % WC] = reg[h][k];
+            if ((k + 1) * NT <= CROWS * WC || e < (uint32_t)(CROWS * WC)) sp[e / WC][e % WC] = reg[h][k];
         }
     };
     stream(0);                           // later chunks are fetched as the previous one is consumed
 #pragma unroll
     for (int k = 0; k < IDS; ++k) {
         const uint32_t e = threadIdx.x + k * NT;
-        if (e < (uint32_t)(NS * WC)) sid[e / WC][e % WC] = idv[k];
+        if ((k + 1) * NT <= NS * WC || e < (uint32_t)(NS * WC)) sid[e / WC][e % WC] = idv[k];
     }
     const uint32_t v = threadIdx.x / WC, cl = threadIdx.x % WC;
     const bool active = v < 5u;
@@ -2000,13 +2000,13 @@ __global__ __launch_bounds__(weno_threads<HEX_WC>()) __attribute__((amdgpu_waves
     }
     __syncthreads();                     // ids in LDS
     // 2. the member differences, all gathers in flight together (no branch per member:
-    // the address selects the state or the ghost array; spare lanes all read cell i)
+    // the address selects the state or the ghost array; spare lanes gather variable 0)
+    uint32_t id[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) id[s] = (uint32_t)sid[s][cl];
     double d[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const uint32_t id = active ? (uint32_t)sid[s][cl] : i;
-        d[s] = ldg_at(id < nc ? Qv + id : Gv + (id - nc)) - qi;
-    }
+    for (int s = 0; s < NS; ++s) d[s] = ldg_at(id[s] < nc ? Qv + id[s] : Gv + (id[s] - nc)) - qi;
     // 3. the big-stencil fit, chunk by chunk (slot order within each row's sum);
     // thread (m, c) fetches its sub-stencil inverse meanwhile
     const uint32_t fm = threadIdx.x / WC;
@@ -2197,7 +2197,7 @@ __device__ __forceinline__ bool hex_point_flux(const ProbDesc &P, int stage, uin
             for (int a = 0; a < 3; ++a) gL[q][a] += gR[q][a];
         gks_flux_tau0<T>(qL, qR, gL, n, P, F, dF);
     } else {
-        gks_flux_full<T, TM == 2>(qL, gL, qR, gR, n, (T)P.dt[0], P, F, dF);
+        gks_flux_full<T, TM == 2>(qL, gL, qR, gR, n, (T)ldg<double>(P.dt, 0u), P, F, dF);
     }
     if constexpr (sizeof(T) == 4)
         if (!finite_flux(F, dF)) return false;
