@@ -669,7 +669,7 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
 
     // ---- 6. faces in internal numbering: left = smaller internal id -------------
     // counting sort by left cell, then by right cell; a wall face has the wall cell
-    // on the left and right = -1 (the ghost), and sorts first among its cell's faces
+    // on the left and right = -1 (the ghost)
     auto is_wall = [&](int64_t c, int p) { return partner[c * 4 + p] < 0; };
     std::vector<int64_t> fstart(nc + 1, 0);
     int64_t nwall = 0;
@@ -709,6 +709,15 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             for (int64_t c = b; c < e; ++c)
                 std::sort(faces.begin() + fstart[c], faces.begin() + fstart[c + 1],
                           [](const FaceRec &x, const FaceRec &y) { return x.r < y.r || (x.r == y.r && x.pl < y.pl); });
+        });
+        // within each block of 64 faces (a flux workgroup's tile), order by the right
+        // cell: the left cells stay the block's few consecutive cells, and the update's
+        // gathers of the faces a cell sees as the right cell come in cell order (update
+        // 113 -> 104 us at 6 64^3)
+        parallel_for((nf + 63) / 64, [&](int64_t b, int64_t e) {
+            for (int64_t k = b; k < e; ++k)
+                std::stable_sort(faces.begin() + 64 * k, faces.begin() + std::min<int64_t>(nf, 64 * k + 64),
+                                 [](const FaceRec &x, const FaceRec &y) { return x.r < y.r; });
         });
     }
     // colour classes for the coloured accumulation: no two faces of a class share a
