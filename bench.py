@@ -60,6 +60,9 @@ def algorithmic_bytes(kernel: str, nc: int, nf: int, mixed: bool, fp32: bool = F
         return nf * (8 + 16 * es + 7.5 * es) + nc * ((200 + 5 * es) if mixed else 400)
     if kernel == "update":
         return nc * (16 + 20 * es + 2 * es + 12.5 * es)
+    if kernel == "weno_hex":   # 24 stencil ids, own state, 9 x 24 pseudo-inverse, eight 3 x 3 inverses,
+        # seven geometry values, the record written (FP64 or FP32-mixed)
+        return nc * (96 + 40 + 1728 + 576 + 56 + (200 if mixed else 400))
     return 0.0
 
 
@@ -168,8 +171,15 @@ def sphere_bench(n: int, layers: int, run_steps: int, steps: int, warmup: int) -
         run_s = time.perf_counter() - t_run
         q, t = s.get_state()
         out["faces"] = s.info()["n_faces"]
+        wms, wcnt = prof["weno"]
+        wb = algorithmic_bytes("weno_hex", nc, 0, prec != hgks.FP64)
+        wgbs = wb / (wms / 1e3 / max(1, wcnt)) / 1e9
         out[name] = {"value": round(nc * steps / el, 1), "ms_per_step": round(1e3 * el / steps, 4),
                      "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items()},
+                     "weno_roofline": {"bound": "hbm", "achieved": round(wgbs, 1), "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(wgbs / HBM_PEAK_GBS, 4),
+                                       "alg_bytes_per_launch": wb,
+                                       "avg_launch_us": round(1e3 * wms / max(1, wcnt), 1)},
                      "run_steps": warmup + steps + rest, "run_s": round(run_s, 2), "t": t,
                      "setup_s": round(setup, 2), "footprint_GB": round(s.footprint() / 1e9, 3)}
         s.close()

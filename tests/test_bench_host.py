@@ -34,3 +34,12 @@ def test_flux_and_update_algorithmic_bytes():
     # the FP32 form: 4-byte geometry, fluxes and state, 4-byte ids as before
     assert bench.algorithmic_bytes("flux", nc, nf, True, True) == nf * 102 + nc * 220
     assert bench.algorithmic_bytes("update", nc, nf, True, True) == nc * 154
+
+
+def test_hex_weno_algorithmic_bytes():
+    """Per hexahedral cell: 24 stencil ids (96), own state (40), the 9 x 24 pseudo-inverse
+    (1728), eight 3 x 3 sub-stencil inverses (576), seven geometry values (56) and the
+    record written: 400 B in FP64, 200 B in FP32-mixed."""
+    assert bench.algorithmic_bytes("weno_hex", 1000, 0, False) == 1000 * 2896
+    assert bench.algorithmic_bytes("weno_hex", 1000, 0, True) == 1000 * 2696
+
