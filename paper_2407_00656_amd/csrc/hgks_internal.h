@@ -112,7 +112,7 @@ hgks_status build_mesh(const hgks_params &prm, int64_t n_nodes, const double *xy
 
 int host_threads();
 
-// (A^T A)^{-1} A^T of a full-column-rank m x n matrix (row-major, n <= 9) through a
+// (A^T A)^{-1} A^T of a full-column-rank m x n matrix (row-major, n = 9 or 3) through a
 // Cholesky factor of A^T A; false on a negligible pivot (rank deficiency).
 bool pinv_normal(int m, int n, const double *A, double *P);
 

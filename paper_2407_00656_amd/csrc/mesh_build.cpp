@@ -64,49 +64,62 @@ void pinv0_quads_f32(const HostMesh &hm, float *out) {
     });
 }
 
-// Pseudo-inverse of a full-column-rank m x n matrix (row-major, any m, n <= 9) by
+// Pseudo-inverse of a full-column-rank m x n matrix (row-major, any m; n = 9 or 3) by
 // the normal equations: P (n x m, row-major) = (A^T A)^{-1} A^T with a Cholesky
 // factor of A^T A (the least-squares fit the oracle solves the same way).  Returns
 // false when a pivot of the factor is negligible against the largest (rank
 // deficiency; the squared form of the test |R_jj| > 1e-9 max |R| on a QR factor).
 // With P == nullptr only the rank test runs.
-bool pinv_normal(int m, int n, const double *A, double *P) {
-    double L[9][9];
-    for (int i = 0; i < n; ++i)
+namespace {
+// the same with the column count fixed at compile time (the loops unroll)
+template <int N>
+bool pinv_normal_n(int m, const double *A, double *P) {
+    double L[N][N];
+    for (int i = 0; i < N; ++i)
         for (int j = 0; j <= i; ++j) {
             double s = 0.0;
-            for (int k = 0; k < m; ++k) s += A[k * n + i] * A[k * n + j];
+            for (int k = 0; k < m; ++k) s += A[k * N + i] * A[k * N + j];
             L[i][j] = s;
         }
     double dmax = 0.0;
-    for (int i = 0; i < n; ++i) dmax = std::max(dmax, L[i][i]);
-    for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < N; ++i) dmax = std::max(dmax, L[i][i]);
+    double id[N];                           // one division per pivot, not per column
+    for (int j = 0; j < N; ++j) {
         double d = L[j][j];
         for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
         if (!(d > 1e-18 * dmax)) return false;
         const double ljj = std::sqrt(d);
         L[j][j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
+        id[j] = 1.0 / ljj;
+        for (int i = j + 1; i < N; ++i) {
             double s = L[i][j];
             for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-            L[i][j] = s / ljj;
+            L[i][j] = s * id[j];
         }
     }
     if (!P) return true;
     for (int c = 0; c < m; ++c) {          // column c of P solves (L L^T) x = row c of A
-        double y[9];
-        for (int i = 0; i < n; ++i) {
-            double s = A[c * n + i];
+        double y[N];
+        for (int i = 0; i < N; ++i) {
+            double s = A[c * N + i];
             for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-            y[i] = s / L[i][i];
+            y[i] = s * id[i];
         }
-        for (int i = n - 1; i >= 0; --i) {
+        for (int i = N - 1; i >= 0; --i) {
             double s = y[i];
-            for (int k = i + 1; k < n; ++k) s -= L[k][i] * P[k * m + c];
-            P[i * m + c] = s / L[i][i];
+            for (int k = i + 1; k < N; ++k) s -= L[k][i] * y[k];
+            y[i] = s * id[i];
+            P[i * m + c] = y[i];
         }
     }
     return true;
+}
+}  // namespace
+
+bool pinv_normal(int m, int n, const double *A, double *P) {
+    if (n == 9) return pinv_normal_n<9>(m, A, P);
+    if (n == 3) return pinv_normal_n<3>(m, A, P);
+    return false;
 }
 
 namespace {
@@ -518,9 +531,26 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
     for (int64_t c = 0; c < nc; ++c) inv[perm[c]] = (int32_t)c;
 
     // ---- 5. stencils and pseudo-inverses, written in internal numbering --------
+    // the per-cell data in internal (Morton) order first, so that a stencil's members
+    // are read from nearby memory rather than from all over the caller's order
+    std::vector<V3> cenI(nc);
+    std::vector<std::array<double, 6>> smomI(nc);
+    std::vector<double> hI(nc);
+    std::vector<std::array<int32_t, 4>> nbI(nc);
+    std::vector<std::array<std::array<int8_t, 3>, 4>> nshI(nc);
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        for (int64_t c = b; c < e; ++c) {
+            const int64_t o = perm[c];
+            cenI[c] = cen[o];
+            smomI[c] = smom[o];
+            hI[c] = std::cbrt(vol[o]);
+            for (int p = 0; p < 4; ++p) nbI[c][p] = inv[nb[o][p]];
+            nshI[c] = nsh[o];
+        }
+    });
     // centroid of a member in the frame of the cell whose stencil holds it
     auto place = [&](const Member &x) {
-        V3 c = cen[x.cell];
+        V3 c = cenI[x.cell];
         double v[3] = {c.x, c.y, c.z};
         for (int a = 0; a < 3; ++a) {
             if (per[a] > 0)
@@ -542,16 +572,16 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
         double local_resid = 0.0;
         int lmax = 0, lmin = 1 << 30, ldup = 0;
         for (int64_t c = b; c < e; ++c) {
-            const int64_t i = perm[c];          // caller id
+            const int64_t i = c;                // internal ids throughout
             Member S[SLOTS];
-            for (int p = 0; p < 4; ++p) S[p] = {nb[i][p], {nsh[i][p][0], nsh[i][p][1], nsh[i][p][2]}};
+            for (int p = 0; p < 4; ++p) S[p] = {nbI[i][p], {nshI[i][p][0], nshI[i][p][1], nshI[i][p][2]}};
             for (int m = 0; m < 4; ++m) {
-                int32_t j = nb[i][m];
+                int32_t j = nbI[i][m];
                 int t = 0;
                 for (int q = 0; q < 4; ++q) {
-                    Member x{nb[j][q], {0, 0, 0}};
+                    Member x{nbI[j][q], {0, 0, 0}};
                     for (int a = 0; a < 3; ++a) {
-                        const int s1 = nsh[i][m][a], s2 = nsh[j][q][a];
+                        const int s1 = nshI[i][m][a], s2 = nshI[j][q][a];
                         if (per[a] > 0) {
                             x.s[a] = (int8_t)(s1 + s2);
                         } else {        // mirror images compose: the same wall twice is the identity
@@ -566,16 +596,16 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                 if (t != 3) bad = 3;
             }
             // least-squares rows in the scaled coordinates xi = (x - c_i)/h_i
-            const double h = std::cbrt(vol[i]);
+            const double ih = 1.0 / hI[i], ih2 = ih * ih;
             auto row = [&](const Member &x, double r[9]) {
-                V3 d = place(x) - cen[i];
-                r[0] = d.x / h;
-                r[1] = d.y / h;
-                r[2] = d.z / h;
+                V3 d = place(x) - cenI[i];
+                r[0] = d.x * ih;
+                r[1] = d.y * ih;
+                r[2] = d.z * ih;
                 for (int q = 0; q < 6; ++q) {
                     // a mirror flips the sign of the mixed moments that involve its axis
                     const double sg = mirror_sign(x, QA[q]) * mirror_sign(x, QB[q]);
-                    r[3 + q] = (sg * smom[x.cell][q] + comp(d, QA[q]) * comp(d, QB[q]) - smom[i][q]) / (h * h);
+                    r[3 + q] = (sg * smomI[x.cell][q] + comp(d, QA[q]) * comp(d, QB[q]) - smomI[i][q]) * ih2;
                 }
             };
             // distinct members of the big stencil (self excluded by construction)
@@ -613,7 +643,7 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
             for (int r = 0; r < 9; ++r)
                 for (int s = 0; s < SLOTS; ++s)
                     out.pinv0[(((size_t)(r * 8 + s / 2)) * nc + c) * 2 + (s & 1)] = first[s] >= 0 ? Pk[r * nm + first[s]] : 0.0;
-            for (int s = 0; s < SLOTS; ++s) out.sten[(size_t)s * nc + c] = inv[S[s].cell];
+            for (int s = 0; s < SLOTS; ++s) out.sten[(size_t)s * nc + c] = S[s].cell;
             for (int w = 0; w < 4; ++w) {
                 uint32_t word = 0;
                 for (int s = 4 * w; s < 4 * w + 4; ++s) {
@@ -635,11 +665,10 @@ hgks_status build_mesh(const hgks_params &prm, int64_t nn, const double *xyz, in
                         if (us[u] == S[sl[t]]) dup = true;
                     if (dup) continue;
                     us[ns] = S[sl[t]];
-                    double r[9];
-                    row(S[sl[t]], r);
-                    As[ns * 3 + 0] = r[0];
-                    As[ns * 3 + 1] = r[1];
-                    As[ns * 3 + 2] = r[2];
+                    const V3 d = place(S[sl[t]]) - cenI[i];      // the linear part of the row
+                    As[ns * 3 + 0] = d.x * ih;
+                    As[ns * 3 + 1] = d.y * ih;
+                    As[ns * 3 + 2] = d.z * ih;
                     ++ns;
                 }
                 if (ns < 3 || !pinv_normal(ns, 3, As, nullptr)) {
