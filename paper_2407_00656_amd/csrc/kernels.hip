@@ -10,13 +10,17 @@
 //              records once, evaluates them at the three Gauss points and writes
 //              S * sum_G w_G (F, dF) (dF only in the second stage, whose L(Q*)
 //              the S2O4 update does not use).
-//   k_flux     the same for tau > 0: one wave per Gauss point, the three
-//              contributions summed through LDS.
+//   k_flux_gp  the same for tau > 0: one lane per Gauss point, a face's three
+//              lanes summed by neighbour shuffles (k_flux: the coloured mode, one
+//              wave per Gauss point summed through LDS).
+//   k_flux_fix, k_flux_fix_full, k_flux_hex_fix
+//              rare passes over faces the main flux left non-finite (positivity
+//              fallback at tau = 0; FP32 points refused to FP64 at tau > 0).
 //   k_*_hex    the same steps on hexahedral meshes (eight sub-stencils, 2x2 Gauss
 //              points on bilinear faces, listed wall and far-field boundaries,
 //              viscous collision time).
-//   k_update   S2O4 stage update (Sec. 2.2).  Each cell gathers its four face
-//              fluxes in a fixed order: deterministic, no atomics.  The second
+//   k_update   S2O4 stage update (Sec. 2.2).  Each cell gathers its four (six)
+//              face fluxes in a fixed order: deterministic, no atomics.  The second
 //              stage also forms the next step's CFL bound per tile.
 //   k_dt_*     CFL time step kept on the device.
 //
