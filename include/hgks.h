@@ -55,17 +55,19 @@ typedef enum {
     HGKS_FP32_MIXED = 1       /* FP64 geometry, pseudo-inverse contraction, state and
                                  accumulation; FP32 smoothness indicators, weights,
                                  Gauss-point reconstruction and gas-kinetic flux
-                                 (with tau > 0, a Gauss point with a cold side, whose
-                                 energy is more than 90% kinetic, is evaluated in FP64:
-                                 there FP32 loses the pressure and the micro-slopes) */,
+                                 (with tau > 0, a face with a Gauss point that has a
+                                 cold side, whose energy is more than 90% kinetic, or a
+                                 non-finite FP32 flux is evaluated again in FP64 by a
+                                 separate pass: there FP32 loses the pressure and the
+                                 micro-slopes) */,
     HGKS_FP32 = 2             /* the single-precision build (Sec. 5.1, the memory and time
                                  comparison of FP32 against FP64): the state (Q^n, Q*, and
                                  the stage-2 base), the cell and face geometry, the face
                                  fluxes and the accumulators are stored in FP32, and so is
                                  the big-stencil pseudo-inverse (each value rounded once);
                                  both WENO contractions, the sub-stencil fits, the weights
-                                 and the gas-kinetic flux run in FP32 (tau > 0 Gauss points
-                                 with a cold side in FP64, as in the FP32-mixed form).  The
+                                 and the gas-kinetic flux run in FP32 (tau > 0 faces with
+                                 a cold side in FP64, as in the FP32-mixed form).  The
                                  few operations of the stage update run in FP64 registers
                                  on FP32 operands and are rounded once on store; dt and the
                                  time stay FP64, and so do the centroids the sub-stencil
