@@ -338,6 +338,29 @@ hgks_status build_hex_mesh(const hgks_params &prm, int64_t nn, const double *xyz
         }
     }
     const int64_t nf = (int64_t)fcell.size();
+    {   // within each block of 64 faces (a flux workgroup's tile), order by the right
+        // cell (listed faces first): the update's gathers of the faces a cell sees as
+        // the right cell then come in cell order
+        std::vector<int32_t> order(nf), newid(nf);
+        for (int64_t f = 0; f < nf; ++f) order[f] = (int32_t)f;
+        for (int64_t b = 0; b < nf; b += 64)
+            std::stable_sort(order.begin() + b, order.begin() + std::min<int64_t>(nf, b + 64),
+                             [&](int32_t x, int32_t y) { return fcell[x][1] < fcell[y][1]; });
+        std::vector<std::array<int32_t, 2>> fc2(nf);
+        std::vector<int32_t> fs2(nf);
+        for (int64_t k = 0; k < nf; ++k) {
+            newid[order[k]] = (int32_t)k;
+            fc2[k] = fcell[order[k]];
+            fs2[k] = fside[order[k]];
+        }
+        fcell.swap(fc2);
+        fside.swap(fs2);
+        for (int64_t ci = 0; ci < nc; ++ci)
+            for (int p = 0; p < 6; ++p) {
+                const int32_t code = cface[ci][p];
+                cface[ci][p] = (newid[code >> 1] << 1) | (code & 1);
+            }
+    }
 
     // neighbours (internal ids; ghosts nc + g) with image shifts
     std::vector<std::array<Mem, 6>> nb(nc);
